@@ -1,0 +1,186 @@
+"""Seeded synthetic latent-Gaussian-model inputs.
+
+This module is shared by the tests, the benchmark and the CPU oracle's callers.
+It draws inputs only: points, exposures, constraint rows, a smooth "true" field,
+counts and hyperparameter batches.  It holds none of the method's arithmetic (no
+covariance or precision is built here), so the oracle and the HIP library stay
+independent of each other.
+
+The shapes follow the paper's space x time Poisson interaction models (section
+"Application to disease mapping ...", Type IV interaction, sum-to-zero
+constraints per region and per time) and the exponential-covariance Gaussian
+model; the paper's own data sets (prostate-cancer mortality in Spain, the
+Penicillin crossed design) are not available and these draws stand in for them.
+
+Model dict keys (consumed by the oracle and by the C-ABI binding alike):
+    n, lik ('gaussian'|'poisson'), prior ('dense'|'expcov'|'kron'),
+    y (n,), E (n,) or None, A None (identity) or (m, n), C (k, n) or None,
+    e (k,) or None, coords (n_s, 2), n_s, n_t, Qprior (n, n) for 'dense'.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def points(rng, n_s):
+    """n_s points uniform in the unit square."""
+    return rng.uniform(0.0, 1.0, size=(n_s, 2))
+
+
+def smooth_field(rng, coords, n_t, n_waves=6, amp=0.35):
+    """A smooth space-time field x(s, t) = sum_m a_m sin(2 pi u_m . p_s + w_m t/n_t + phi_m),
+    laid out with index t*n_s + s.  It is not drawn from the prior."""
+    n_s = coords.shape[0]
+    t = np.arange(n_t)[:, None]
+    x = np.zeros((n_t, n_s))
+    for _ in range(n_waves):
+        u = rng.normal(0.0, 2.0, size=2)
+        w = rng.uniform(0.5, 6.0)
+        ph = rng.uniform(0.0, 2.0 * math.pi)
+        a = amp * rng.uniform(0.3, 1.0)
+        x += a * np.sin(2.0 * math.pi * (coords @ u)[None, :] + w * 2.0 * math.pi * t / n_t + ph)
+    return x
+
+
+def double_centre(x):
+    """Remove per-region and per-time means of an (n_t, n_s) array so that every
+    sum-to-zero row holds exactly: x - rowmean - colmean + grandmean."""
+    return x - x.mean(axis=1, keepdims=True) - x.mean(axis=0, keepdims=True) + x.mean()
+
+
+def sum_to_zero_rows(n_s, n_t):
+    """Per-region rows (sum over time for each region) and per-time rows (sum
+    over regions for each time), with the last per-time row dropped: the full set
+    has rank n_s + n_t - 1, so the kept k = n_s + n_t - 1 rows have full row rank
+    and span the same space."""
+    n = n_s * n_t
+    C = np.zeros((n_s + n_t - 1, n))
+    idx = np.arange(n).reshape(n_t, n_s)  # index t*n_s + s
+    for s in range(n_s):
+        C[s, idx[:, s]] = 1.0
+    for t in range(n_t - 1):
+        C[n_s + t, idx[t, :]] = 1.0
+    return C
+
+
+def kron_theta0(n_t):
+    """(log tau0, log 0.2, log 0.01, 0) with tau0 = (n_t^2 - 1)/(6 n_t 0.25), which
+    sets the average prior marginal variance of a first-order random walk of
+    length n_t to about 0.25 (trace of its pseudo-inverse is (n_t^2 - 1)/6)."""
+    tau0 = (n_t * n_t - 1.0) / (6.0 * n_t * 0.25)
+    return np.array([math.log(tau0), math.log(0.2), math.log(0.01), 0.0])
+
+
+def kron_poisson(n_s, n_t, seed, beta0=0.0, constrained=True):
+    """Poisson space x time interaction model, n = n_s * n_t latent (index t*n_s+s),
+    exposures E ~ U(5, 50), y ~ Poisson(E exp(beta0 + x_true))."""
+    rng = np.random.default_rng(seed)
+    coords = points(rng, n_s)
+    x = double_centre(smooth_field(rng, coords, n_t)).reshape(-1)
+    n = n_s * n_t
+    E = rng.uniform(5.0, 50.0, size=n)
+    y = rng.poisson(E * np.exp(beta0 + x)).astype(np.float64)
+    C = sum_to_zero_rows(n_s, n_t) if constrained else None
+    return {
+        "n": n, "lik": "poisson", "prior": "kron", "y": y, "E": E, "A": None,
+        "C": C, "e": None if C is None else np.zeros(C.shape[0]),
+        "coords": coords, "n_s": n_s, "n_t": n_t, "x_true": x,
+    }
+
+
+def expcov_gaussian(n, seed, sigma2=0.25, constrained=False):
+    """Gaussian model y = x + eps on n uniform points, eps ~ N(0, sigma2).  With
+    ``constrained`` a single sum-to-zero row is imposed (e = 0)."""
+    rng = np.random.default_rng(seed)
+    coords = points(rng, n)
+    x = smooth_field(rng, coords, 1)[0]
+    x = x - x.mean()
+    y = x + rng.normal(0.0, math.sqrt(sigma2), size=n)
+    C = np.ones((1, n)) if constrained else None
+    return {
+        "n": n, "lik": "gaussian", "prior": "expcov", "y": y, "E": None, "A": None,
+        "C": C, "e": None if C is None else np.zeros(1),
+        "coords": coords, "n_s": n, "n_t": 1, "x_true": x,
+    }
+
+
+def random_spd(n, seed, shift=0.5):
+    """A dense symmetric positive-definite test matrix G G^T / m + shift I."""
+    rng = np.random.default_rng(seed)
+    m = n + 8
+    G = rng.normal(size=(n, m))
+    return G @ G.T / m + shift * np.eye(n)
+
+
+def dense_poisson(n, k, seed):
+    """Poisson model with a caller-supplied dense prior precision and k random
+    full-rank constraint rows with a non-zero right-hand side."""
+    rng = np.random.default_rng(seed)
+    Q = random_spd(n, seed + 1000, shift=1.0)
+    x = rng.normal(0.0, 0.3, size=n)
+    E = rng.uniform(5.0, 50.0, size=n)
+    y = rng.poisson(E * np.exp(x)).astype(np.float64)
+    C = rng.integers(0, 2, size=(k, n)).astype(np.float64) if k else None
+    if k:
+        C[np.arange(k), np.arange(k)] = 1.0
+    e = rng.normal(0.0, 0.2, size=k) if k else None
+    return {
+        "n": n, "lik": "poisson", "prior": "dense", "y": y, "E": E, "A": None,
+        "C": C, "e": e, "coords": None, "n_s": n, "n_t": 1, "Qprior": Q,
+    }
+
+
+def fd_batch(theta0, h, dims):
+    """theta0 followed by theta0 +/- h e_j for each j in ``dims`` (the points of a
+    central finite-difference gradient)."""
+    th = [np.array(theta0, dtype=np.float64)]
+    for j in dims:
+        for s in (+1.0, -1.0):
+            t = np.array(theta0, dtype=np.float64)
+            t[j] += s * h
+            th.append(t)
+    return np.stack(th)
+
+
+def normal_batch(theta0, B, sd, seed):
+    """B draws of theta ~ N(theta0, sd^2 I)."""
+    rng = np.random.default_rng(seed)
+    return np.asarray(theta0)[None, :] + sd * rng.normal(size=(B, len(theta0)))
+
+
+# ----------------------------- named workloads -------------------------------- #
+def expcov400():
+    """n = 400 Gaussian model, theta0 = (0, log 0.2, log 0.25); batch of 5 =
+    theta0 and theta0 +/- 0.01 on log tau and log rho, then the two points
+    +/- 0.01 on log sigma^2."""
+    model = expcov_gaussian(400, seed=1)
+    theta0 = np.array([0.0, math.log(0.2), math.log(0.25)])
+    batch = fd_batch(theta0, 0.01, [0, 1, 2])
+    return model, batch
+
+
+def kron3000():
+    """n = 100 regions x 30 times Poisson model, k = 129, 9 theta points."""
+    model = kron_poisson(100, 30, seed=2)
+    return model, fd_batch(kron_theta0(30), 0.01, [0, 1, 2, 3])
+
+
+UNEVEN_SHAPES = [(32, 32), (64, 32), (100, 30), (128, 32), (192, 32)]
+
+
+def uneven_batch(B=64, seed=3):
+    """B theta points with n drawn from {1024, 2048, 3000, 4096, 6144}; one data
+    set per distinct n (seed 30 + i); theta_b ~ N(theta0(n_b), 0.5^2 I)."""
+    rng = np.random.default_rng(seed)
+    which = rng.integers(0, len(UNEVEN_SHAPES), size=B)
+    models = [kron_poisson(ns, nt, seed=30 + i) for i, (ns, nt) in enumerate(UNEVEN_SHAPES)]
+    thetas = np.stack([kron_theta0(UNEVEN_SHAPES[w][1]) + 0.5 * rng.normal(size=4) for w in which])
+    return [models[w] for w in which], thetas
+
+
+def headline(B=64, seed=81, n_s=128, n_t=64):
+    """n = 128 regions x 64 times = 8192 Poisson model, k = 191, B theta ~ N(theta0, 0.5^2 I)."""
+    model = kron_poisson(n_s, n_t, seed=seed)
+    return model, normal_batch(kron_theta0(n_t), B, 0.5, seed + 1)
