@@ -1,0 +1,207 @@
+/*
+ * inla_dense.h - C-ABI of the MI355X (gfx950) dense-INLA Laplace-evaluation library.
+ *
+ * The library evaluates, for a batch of hyperparameter points theta, the per-theta
+ * hot path of dense INLA (arXiv 2311.08050, "INLA+"): it assembles the dense
+ * posterior precision Q*(theta) = Q_prior(theta) + A^T W(x) A, factors it with a
+ * blocked Cholesky, takes log-determinants, runs the Newton iteration for the mode
+ * of a non-Gaussian likelihood, corrects every iterate onto the linear constraints
+ * C x = e by kriging, and forms the Laplace approximation of log pi(theta | y) and
+ * the marginal variances diag(Q*^{-1}) (constraint-corrected).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Latent Gaussian model of the paper's Introduction:
+ *        y_i | x, theta ~ f(eta_i, theta),  eta = offset + A x,  x | theta ~ N(0, Q_prior^{-1}),
+ *    with A = I (m = n observations, one per latent element).
+ *  - Matrices are column-major; a symmetric matrix is read from its lower triangle
+ *    only.  Constraint matrices C are k x n row-major.
+ *  - "device" pointers are HIP device memory owned by the caller; "host" pointers
+ *    are ordinary host memory owned by the caller.  The library never frees or
+ *    retains caller memory after a call returns.  The handle owns its own
+ *    workspace (grown on demand, released by inla_destroy).
+ *  - Work is enqueued on the handle's stream.  inla_logdet, inla_constrained_mode,
+ *    inla_laplace_eval and inla_marginal_var return only after their results are
+ *    complete (the Newton iteration makes host decisions on device flags), so host
+ *    outputs are valid on return and device outputs are valid for any later work
+ *    on the handle's stream.
+ *  - Return value: INLA_OK (0), -i when the i-th argument (1-based) is invalid,
+ *    INLA_ERR_HIP on a HIP runtime failure, INLA_ERR_NOMEM when the workspace
+ *    cannot be allocated.  Numerical outcomes are reported per theta in `info`
+ *    (see INLA_INFO_*); the library never aborts the process.
+ *
+ * Hyperparameter layout (row b of `theta`, stride `ldtheta` doubles): prior
+ * parameters first, then the likelihood parameter.
+ *    INLA_PRIOR_EXPCOV          (log tau, log rho, lik)
+ *    INLA_PRIOR_KRON_RW1_EXPCOV (log tau, log rho, log delta, lik)
+ *    INLA_PRIOR_DENSE           (lik)
+ *    lik = log sigma^2 for INLA_LIK_GAUSSIAN (eta = x),
+ *          beta0       for INLA_LIK_POISSON  (eta = beta0 + x).
+ */
+#ifndef INLA_DENSE_H
+#define INLA_DENSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ return codes */
+#define INLA_OK 0
+#define INLA_ERR_HIP (-1000)
+#define INLA_ERR_NOMEM (-1001)
+#define INLA_ERR_UNSUPPORTED (-1002)
+
+/* ----------------------------------------------------- per-theta info codes */
+/* info == j > 0: the leading minor of order j of the matrix being factored is
+ * not positive definite (LAPACK convention). */
+#define INLA_INFO_OK 0
+#define INLA_INFO_NEWTON_MAXIT (-1)     /* no convergence within max_iter; last iterate returned */
+#define INLA_INFO_CONSTRAINT_RANK (-2)  /* C Q^{-1} C^T not positive definite: C lacks full row rank */
+#define INLA_INFO_NONFINITE (-3)        /* NaN/Inf in theta, a start vector or an iterate */
+
+/* ----------------------------------------------------------------- enums */
+enum { INLA_LIK_GAUSSIAN = 0, INLA_LIK_POISSON = 1 };
+enum {
+  INLA_PRIOR_DENSE = 0,           /* Q_prior supplied by the caller (model.Qprior)       */
+  INLA_PRIOR_EXPCOV = 1,          /* Q_prior = tau Sigma(rho)^{-1}, Sigma_ij = exp(-d_ij/rho) */
+  INLA_PRIOR_KRON_RW1_EXPCOV = 2  /* Q_prior = tau (R_t kron Sigma_s(rho)^{-1} + delta I),
+                                     R_t the unscaled first-order random walk on n_t
+                                     steps, latent index t*n_s + s */
+};
+enum { INLA_PREC_FP64 = 0 };
+
+typedef struct inla_handle inla_handle;
+
+/* One latent Gaussian model.  The struct itself is host memory; the arrays it
+ * points to are device memory. */
+typedef struct inla_model {
+  int32_t n;      /* latent size = number of observations (A = I); n >= 1          */
+  int32_t k;      /* number of constraint rows (0: unconstrained); k < n            */
+  int32_t lik;    /* INLA_LIK_*                                                     */
+  int32_t prior;  /* INLA_PRIOR_*                                                   */
+  int32_t n_s;    /* EXPCOV: must equal n; KRON: number of regions                  */
+  int32_t n_t;    /* EXPCOV: 1; KRON: number of time points, n = n_s * n_t          */
+  int32_t ldq;    /* DENSE: leading dimension of Qprior (>= n); otherwise ignored    */
+  int32_t reserved;
+  const double *y;      /* device [n] observations                                  */
+  const double *E;      /* device [n] Poisson exposure phi, or NULL for all ones    */
+  const double *C;      /* device [k*n] constraint rows, row-major; NULL iff k == 0 */
+  const double *e;      /* device [k] constraint right-hand side, or NULL for zeros */
+  const double *coords; /* device [n_s*2] points (x, y) row-major (EXPCOV, KRON)    */
+  const double *Qprior; /* device, DENSE only: column-major n x n, lower triangle   */
+} inla_model;
+
+/* Newton options (appendix "Gaussian approximation strategy", algorithm
+ * "Gaussian Approximation"; the paper leaves norm and tolerance open, here
+ * ||x_new - x||_inf <= tol * max(1, ||x_new||_inf)). */
+typedef struct inla_opts {
+  int32_t prec;      /* INLA_PREC_FP64                                               */
+  int32_t max_iter;  /* <= 0: 50                                                     */
+  double tol;        /* <= 0: 1e-11                                                  */
+  int32_t start;     /* 0: start from x = 0; 1: start from the vectors in x_inout    */
+  int32_t reserved;
+} inla_opts;
+
+/* Per-theta results of inla_laplace_eval / inla_constrained_mode (host). */
+typedef struct inla_result {
+  double objective;     /* log pi~(y | theta) with pi(theta) excluded, Eq. (41)      */
+  double logdet_qprior; /* log|Q_prior|                                              */
+  double logdet_sprior; /* log|C Q_prior^{-1} C^T| (0 if k = 0)                      */
+  double ese;           /* e^T (C Q_prior^{-1} C^T)^{-1} e (0 if k = 0)               */
+  double xqx;           /* x*^T Q_prior x*                                           */
+  double loglik;        /* sum_i log pi(y_i | eta*_i), normalising constants included */
+  double logdet_qstar;  /* log|Q*| at the mode                                       */
+  double logdet_s;      /* log|C Q*^{-1} C^T| at the mode (0 if k = 0)               */
+  double step;          /* last Newton step ||x_new - x||_inf                        */
+  int32_t iters;        /* Newton iterations taken                                   */
+  int32_t info;         /* INLA_INFO_* or leading-minor index                        */
+} inla_result;
+
+/* ------------------------------------------------------------ lifecycle */
+/* Create a handle bound to `stream` (a hipStream_t; NULL = the null stream) on
+ * the current HIP device.  *h receives the handle.  Returns INLA_OK or an error. */
+int inla_create(inla_handle **h, void *stream);
+/* Release the handle and its workspace.  NULL is accepted. */
+int inla_destroy(inla_handle *h);
+/* Rebind the handle to another stream of the same device. */
+int inla_set_stream(inla_handle *h, void *stream);
+
+/* ------------------------------------------------------------ hot path */
+
+/* log-determinants of B symmetric positive-definite matrices (the Gaussian
+ * normalisers of Eq. (41)): Q_b = L_b L_b^T by blocked Cholesky, log|Q_b| =
+ * 2 sum_i log (L_b)_ii.
+ *   B        number of matrices (>= 0)
+ *   n        host [B] orders (>= 0; 0 gives log-det 0)
+ *   Q        host [B] of device pointers, column-major, lower triangle read; on
+ *            return the lower triangle holds L_b (strict upper triangle untouched)
+ *   ldq      host [B] leading dimensions (>= max(1, n_b))
+ *   logdet   host [B] output
+ *   info     host [B] output: 0, or j > 0 if the leading minor j is not positive
+ *            definite (then logdet is NaN and Q_b holds a partial factor). */
+int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq,
+                double *logdet, int32_t *info);
+
+/* Constrained Newton mode of the Gaussian approximation for B theta points
+ * (algorithm "Gaussian Approximation": Q* = Q_prior + Q_l(x), b = grad + Q_l x,
+ * solve Q* x = b; each iterate conditioned on C x = e by kriging, section
+ * "Identifiability constraints" and the appendix on an IGMRF under linear
+ * constraints).
+ *   models   host [B] model descriptions (may repeat; n may differ across b)
+ *   theta    host [B * ldtheta] hyperparameters (layout above)
+ *   x        host [B] of device pointers to [n_b] doubles: start vector when
+ *            opts->start == 1, the mode on return
+ *   opts     host options, NULL for defaults
+ *   res      host [B] results: iters, step and info are set (other fields 0). */
+int inla_constrained_mode(inla_handle *h, int32_t B, const inla_model *models, const double *theta,
+                          int32_t ldtheta, double *const *x, const inla_opts *opts, inla_result *res);
+
+/* Laplace approximation of log pi(theta | y) at B theta points (Eq. (41),
+ * mode-approx), with the constraint terms of conditioning on C x = e:
+ *   objective = 1/2 log|Q_p| + 1/2 log|S_p| + 1/2 e^T S_p^{-1} e - 1/2 x*^T Q_p x*
+ *               + sum_i log pi(y_i | eta*_i) - 1/2 log|Q*| - 1/2 log|S|,
+ *   S_p = C Q_p^{-1} C^T, S = C Q*^{-1} C^T, Q* refactored at the mode x*.
+ * Arguments as inla_constrained_mode; every field of res[b] is set. */
+int inla_laplace_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta,
+                      int32_t ldtheta, double *const *x, const inla_opts *opts, inla_result *res);
+
+/* Marginal variances at a given mode (Eq. (VBA): x | theta ~ N(x*, Q*^{-1}),
+ * with the kriging correction of the appendix on an IGMRF under constraints):
+ *   var_i = (Q*^{-1})_ii - (V S^{-1} V^T)_ii,  V = Q*^{-1} C^T,  S = C V.
+ *   x_mode   host [B] of device pointers to [n_b] modes (read)
+ *   var      host [B] of device pointers to [n_b] outputs
+ *   info     host [B] outputs (0, leading-minor index, or INLA_INFO_CONSTRAINT_RANK) */
+int inla_marginal_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta,
+                      int32_t ldtheta, const double *const *x_mode, double *const *var, int32_t *info);
+
+/* ------------------------------------------------------------ profiling */
+/* Kernel classes timed when profiling is on. */
+enum {
+  INLA_K_GEMM = 0,      /* MFMA tile update: trailing SYRK/GEMM and panel TRSM */
+  INLA_K_POTF2 = 1,     /* diagonal-block factorisation and inversion          */
+  INLA_K_ASSEMBLE = 2,  /* prior build, Q* / border assembly, likelihood       */
+  INLA_K_SOLVE = 3,     /* triangular solves, kriging system, reductions       */
+  INLA_K_COUNT = 4
+};
+typedef struct inla_kstats {
+  int64_t launches;  /* kernel launches recorded                              */
+  double time_ms;    /* sum of launch durations (HIP events on the handle's stream) */
+  double flops;      /* algorithmic flops of those launches (padding excluded) */
+  double bytes;      /* algorithmic HBM bytes of those launches                */
+} inla_kstats;
+/* Turn per-launch event timing on (1) or off (0); turning it on clears the
+ * counters.  Timing adds an event pair per launch. */
+int inla_profile(inla_handle *h, int32_t enable);
+/* Read the counters of kernel class `kclass` (collected up to the last
+ * completed call). */
+int inla_profile_get(inla_handle *h, int32_t kclass, inla_kstats *out);
+
+/* Library version string. */
+const char *inla_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* INLA_DENSE_H */

@@ -209,6 +209,23 @@ def rhs(model, g, W, x):
 # Kriging correction (sections "Identifiability constraints" and the appendix   #
 # on an IGMRF under linear constraints)                                         #
 # --------------------------------------------------------------------------- #
+# A constraint system S = C Q^{-1} C^T whose Cholesky factor has a squared pivot
+# below this fraction of the largest one is treated as rank deficient (the paper
+# does not discuss rank detection; exact dependence shows up as such a pivot).
+RANK_RTOL = 1e-13
+
+
+def constraint_cholesky(S):
+    """Cholesky factor of S, or None if S is not (numerically) positive definite."""
+    LS, info = cholesky(S)
+    if info:
+        return None
+    d = np.diag(LS) ** 2
+    if d.size and d.min() < RANK_RTOL * d.max():
+        return None
+    return LS
+
+
 def kriging(L, x_u, C, e):
     """Condition the Gaussian N(x_u, Q^{-1}) (Q = L L^T) on C x = e:
         V = Q^{-1} C^T,  S = C V,  lambda = S^{-1}(C x_u - e),  x = x_u - V lambda.
@@ -216,8 +233,8 @@ def kriging(L, x_u, C, e):
     positive definite, i.e. C lacks full row rank)."""
     V = chol_solve(L, C.T)
     S = C @ V
-    LS, info = cholesky(S)
-    if info:
+    LS = constraint_cholesky(S)
+    if LS is None:
         return x_u, V, S, None
     lam = chol_solve(LS, C @ x_u - e)
     return x_u - V @ lam, V, S, LS
@@ -298,10 +315,11 @@ def laplace_eval(model, theta, x0=None, tol=NEWTON_TOL, max_iter=NEWTON_MAX_ITER
     if C is not None:
         Vp = chol_solve(Lp, C.T)
         Sp = C @ Vp
-        ld_sp, LSp, info = logdet(Sp)
-        if info:
+        LSp = constraint_cholesky(Sp)
+        if LSp is None:
             out["info"] = INFO_CONSTRAINT_RANK
             return out
+        ld_sp = logdet_from_chol(LSp)
         ese = float(e @ chol_solve(LSp, e))
     out["logdet_sprior"] = ld_sp
     out["ese"] = ese
@@ -325,10 +343,11 @@ def laplace_eval(model, theta, x0=None, tol=NEWTON_TOL, max_iter=NEWTON_MAX_ITER
     ld_S = 0.0
     if C is not None:
         V = chol_solve(Ls, C.T)
-        ld_S, _, info = logdet(C @ V)
-        if info:
+        LS = constraint_cholesky(C @ V)
+        if LS is None:
             out["info"] = INFO_CONSTRAINT_RANK
             return out
+        ld_S = logdet_from_chol(LS)
     xqx = float(x @ (Qp @ x))
     out.update(
         logdet_qstar=ld_s,

@@ -1,0 +1,213 @@
+"""ctypes binding of ``libinla_dense.so`` (C-ABI in ``include/inla_dense.h``).
+
+Argument marshalling only: device buffers are torch tensors on the current HIP
+device, host outputs are numpy arrays, and every step of the computation runs in
+the library's HIP kernels.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libinla_dense.so")
+
+LIK = {"gaussian": 0, "poisson": 1}
+PRIOR = {"dense": 0, "expcov": 1, "kron": 2}
+N_PRIOR_PARAMS = {"dense": 0, "expcov": 2, "kron": 3}
+
+INFO_OK = 0
+INFO_NEWTON_MAXIT = -1
+INFO_CONSTRAINT_RANK = -2
+INFO_NONFINITE = -3
+
+K_GEMM, K_POTF2, K_ASSEMBLE, K_SOLVE = 0, 1, 2, 3
+K_NAMES = {K_GEMM: "gemm", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve"}
+
+# Symbols declared by include/inla_dense.h
+EXPORTS = [
+    "inla_create", "inla_destroy", "inla_set_stream", "inla_logdet", "inla_constrained_mode",
+    "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
+]
+
+
+class Model(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("k", C.c_int32), ("lik", C.c_int32), ("prior", C.c_int32),
+        ("n_s", C.c_int32), ("n_t", C.c_int32), ("ldq", C.c_int32), ("reserved", C.c_int32),
+        ("y", C.c_void_p), ("E", C.c_void_p), ("C", C.c_void_p), ("e", C.c_void_p),
+        ("coords", C.c_void_p), ("Qprior", C.c_void_p),
+    ]
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("start", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [
+        ("objective", C.c_double), ("logdet_qprior", C.c_double), ("logdet_sprior", C.c_double),
+        ("ese", C.c_double), ("xqx", C.c_double), ("loglik", C.c_double), ("logdet_qstar", C.c_double),
+        ("logdet_s", C.c_double), ("step", C.c_double), ("iters", C.c_int32), ("info", C.c_int32),
+    ]
+
+    def asdict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class KStats(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("time_ms", C.c_double), ("flops", C.c_double), ("bytes", C.c_double)]
+
+
+def load_library(path: str = LIBPATH):
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    i32, pi32 = C.c_int32, C.POINTER(C.c_int32)
+    pd = C.POINTER(C.c_double)
+    lib.inla_create.argtypes = [C.POINTER(P), P]
+    lib.inla_destroy.argtypes = [P]
+    lib.inla_set_stream.argtypes = [P, P]
+    lib.inla_logdet.argtypes = [P, i32, pi32, C.POINTER(P), pi32, pd, pi32]
+    for f in (lib.inla_constrained_mode, lib.inla_laplace_eval):
+        f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
+    lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
+    lib.inla_profile.argtypes = [P, i32]
+    lib.inla_profile_get.argtypes = [P, i32, C.POINTER(KStats)]
+    lib.inla_version.restype = C.c_char_p
+    for name in EXPORTS:
+        if name != "inla_version":
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class DeviceModel:
+    """A model dict (see ``synth``) with its arrays copied to the GPU."""
+
+    def __init__(self, model: dict, device="cuda"):
+        import torch
+
+        def dev(a):
+            if a is None:
+                return None
+            return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).to(device)
+
+        self.model = model
+        self.n = int(model["n"])
+        Cm = model.get("C")
+        self.k = 0 if Cm is None else int(np.asarray(Cm).shape[0])
+        self.y = dev(model["y"])
+        self.E = dev(model.get("E"))
+        self.C = dev(Cm) if self.k else None
+        self.e = dev(model.get("e")) if self.k else None
+        self.coords = dev(model.get("coords"))
+        Q = model.get("Qprior")
+        # column-major n x n: the transpose of a C-order array is its column-major view
+        self.Q = dev(np.asarray(Q).T) if Q is not None else None
+        self.struct = Model(
+            n=self.n, k=self.k, lik=LIK[model["lik"]], prior=PRIOR[model["prior"]],
+            n_s=int(model.get("n_s") or self.n), n_t=int(model.get("n_t") or 1),
+            ldq=self.n if Q is not None else 0, reserved=0,
+            y=_ptr(self.y), E=_ptr(self.E), C=_ptr(self.C), e=_ptr(self.e),
+            coords=_ptr(self.coords), Qprior=_ptr(self.Q),
+        )
+
+
+class LibraryError(RuntimeError):
+    pass
+
+
+class Library:
+    """One handle bound to torch's current stream on the current device."""
+
+    def __init__(self, path: str = LIBPATH):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise LibraryError("no HIP device available")
+        self.torch = torch
+        self.lib = load_library(path)
+        self.h = C.c_void_p()
+        rc = self.lib.inla_create(C.byref(self.h), C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        self._check(rc, "inla_create")
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) and self.h.value:
+                self.lib.inla_destroy(self.h)
+                self.h = C.c_void_p()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _check(rc, what):
+        if rc != 0:
+            raise LibraryError(f"{what} returned {rc}")
+
+    # ------------------------------------------------------------- entry points
+    def logdet(self, mats):
+        """log|Q_b| for a list of square float64 device tensors (C-order symmetric
+        matrices; C order is the column-major transpose, identical for symmetric
+        input).  Overwrites their lower (column-major) triangle with L."""
+        B = len(mats)
+        n = (C.c_int32 * B)(*[int(m.shape[0]) for m in mats])
+        ld = (C.c_int32 * B)(*[max(1, int(m.shape[0])) for m in mats])
+        ptrs = (C.c_void_p * B)(*[m.data_ptr() for m in mats])
+        out = (C.c_double * B)()
+        info = (C.c_int32 * B)()
+        rc = self.lib.inla_logdet(self.h, B, n, ptrs, ld, out, info)
+        self._check(rc, "inla_logdet")
+        return np.array(out[:]), np.array(info[:], dtype=np.int32)
+
+    def _common(self, dmodels, theta, x):
+        B = len(dmodels)
+        theta = np.ascontiguousarray(np.atleast_2d(np.asarray(theta, dtype=np.float64)))
+        assert theta.shape[0] == B
+        models = (Model * B)(*[m.struct for m in dmodels])
+        if x is None:
+            x = [self.torch.zeros(m.n, dtype=self.torch.float64, device="cuda") for m in dmodels]
+        ptrs = (C.c_void_p * B)(*[t.data_ptr() for t in x])
+        return B, theta, models, x, ptrs
+
+    def _run(self, fn, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
+        B, theta, models, x, ptrs = self._common(dmodels, theta, x)
+        opts = Opts(prec=0, max_iter=max_iter, tol=tol, start=start, reserved=0)
+        res = (Result * B)()
+        rc = fn(self.h, B, models, theta.ctypes.data_as(C.POINTER(C.c_double)), theta.shape[1], ptrs,
+                C.byref(opts), res)
+        self._check(rc, fn.__name__)
+        return [r.asdict() for r in res], x
+
+    def laplace_eval(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
+        """(results, modes): per-theta dicts of inla_result fields and device modes."""
+        return self._run(self.lib.inla_laplace_eval, dmodels, theta, x, start, max_iter, tol)
+
+    def constrained_mode(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
+        return self._run(self.lib.inla_constrained_mode, dmodels, theta, x, start, max_iter, tol)
+
+    def marginal_var(self, dmodels, theta, x_modes):
+        B, theta, models, x_modes, xptrs = self._common(dmodels, theta, x_modes)
+        var = [self.torch.empty(m.n, dtype=self.torch.float64, device="cuda") for m in dmodels]
+        vptrs = (C.c_void_p * B)(*[t.data_ptr() for t in var])
+        info = (C.c_int32 * B)()
+        rc = self.lib.inla_marginal_var(self.h, B, models, theta.ctypes.data_as(C.POINTER(C.c_double)),
+                                        theta.shape[1], xptrs, vptrs, info)
+        self._check(rc, "inla_marginal_var")
+        return var, np.array(info[:], dtype=np.int32)
+
+    # ------------------------------------------------------------- profiling
+    def profile(self, on: bool):
+        self._check(self.lib.inla_profile(self.h, 1 if on else 0), "inla_profile")
+
+    def profile_get(self, kclass):
+        s = KStats()
+        self._check(self.lib.inla_profile_get(self.h, kclass, C.byref(s)), "inla_profile_get")
+        return {"launches": s.launches, "time_ms": s.time_ms, "flops": s.flops, "bytes": s.bytes}

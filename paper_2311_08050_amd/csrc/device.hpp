@@ -1,0 +1,102 @@
+// Shared device-side definitions of the dense-INLA HIP library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace inla {
+
+// Tile geometry of the blocked Cholesky.
+constexpr int NBI = 64;      // diagonal block / inner panel width
+constexpr int PADN = 128;    // matrix orders and border heights are padded to this
+constexpr int KC = 16;       // K chunk staged through LDS by the MFMA kernels
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// One matrix being factored by the bordered blocked Cholesky.  Columns [0, nf)
+// are factored; rows [nf, nrows) are border rows carried along (they end up as
+// G L^{-T}); the trailing update also maintains the Schur block of the border
+// for columns [nf, ncols).  Column-major, leading dimension ld >= nrows.
+struct FactorDesc {
+  double *A;
+  double *linv;    // NBI x NBI scratch: inverse of the current diagonal block (col-major)
+  int *info;       // first failing pivot (1-based), 0 if none
+  int ld;
+  int nf;          // columns to factor (multiple of PADN)
+  int nrows;       // multiple of PADN
+  int ncols;       // nf <= ncols <= nrows, multiple of PADN
+  int id_row0;     // first row of an identity border block (INT_MAX if none)
+  int pad_;
+};
+
+// Likelihood / prior kinds (values match the C header).
+enum { LIK_GAUSSIAN = 0, LIK_POISSON = 1 };
+enum { PRIOR_DENSE = 0, PRIOR_EXPCOV = 1, PRIOR_KRON = 2 };
+
+// Per-theta model and workspace description used by the assembly, solve and
+// reduction kernels.
+struct ThetaDesc {
+  // model (device pointers owned by the caller)
+  const double *y, *E, *C, *e, *coords, *Quser;
+  int n, k, lik, prior, n_s, n_t, ldquser;
+  int n_pad;       // round_up(n, PADN)
+  double tau, rho, delta, lpar;   // prior parameters; lpar = sigma^2 or beta0
+  // workspace (owned by the library)
+  double *Qp; int ldqp;           // prior precision, n_pad x n_pad, lower, identity padded
+  double *W; int ldw; int Nw; int Ncw;  // big working matrix: Nw rows, Ncw columns written
+  double *S; int lds; int Ns; int k_pad;   // small (kriging) system working matrix
+  double *P; int ldp; int Np; int ns_pad;  // prior-build working matrix
+  double *x;       // current iterate [n_pad]
+  double *r;       // right-hand side / new iterate [n_pad]
+  double *lam;     // [k_pad] kriging multipliers
+  double *part;    // [2 * ldw] per-column partial sums (loglik, x'Qx)
+  double *dres;    // [16] per-theta device results (see DRES_*)
+  double *out;     // caller's output vector (mode or variances), device
+};
+
+// Per-theta device result slots.
+enum {
+  DRES_LOGDET_L = 0,   // 2 sum log L_ii of the big factor (first n pivots)
+  DRES_LOGDET_S = 1,   // 2 sum log of the kriging factor (first k pivots)
+  DRES_WNORM2 = 2,     // ||L_S^{-1} (C x_u - e)||^2
+  DRES_STEP = 3,       // ||x_new - x||_inf
+  DRES_SCALE = 4,      // max(1, ||x_new||_inf)
+  DRES_XQX = 5,
+  DRES_LOGLIK = 6,
+  DRES_NONFINITE = 7,  // 1 if a non-finite value was met
+  DRES_RANK = 8,       // 1 if the kriging system is numerically singular
+  DRES_COUNT = 16
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Deterministic sum over a 256-thread block (fixed pairing order).
+__device__ __forceinline__ double block_sum256(double v, double *sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
+}
+__device__ __forceinline__ double block_max256(double v, double *sh) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+  __syncthreads();
+  return t;
+}
+
+}  // namespace inla

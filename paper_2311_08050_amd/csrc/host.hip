@@ -1,0 +1,744 @@
+// C-ABI entry points and the host-side orchestration of the per-theta hot path:
+// prior build, prior pass, Newton iteration with kriging, final pass at the mode
+// and the Laplace objective of Eq. (41) (mode-approx).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <limits>
+
+#include "device.hpp"
+#include "host.hpp"
+#include "model.hpp"
+
+namespace inla {
+
+// ------------------------------------------------------------------ Ctx
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+void *Ctx::upload(const void *src, size_t bytes) {
+  bytes = align256(bytes);
+  if (bytes > ring_size) return nullptr;
+  if (ring_off + bytes > ring_size) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
+    ring_off = 0;
+  }
+  std::memcpy(ring_host + ring_off, src, bytes);
+  void *dst = ring + ring_off;
+  if (hipMemcpyAsync(dst, ring_host + ring_off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return nullptr;
+  ring_off += bytes;
+  return dst;
+}
+
+bool Ctx::reserve(size_t bytes) {
+  if (bytes <= ws_size) return true;
+  if (ws) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    (void)hipFree(ws);
+    ws = nullptr;
+    ws_size = 0;
+  }
+  if (hipMalloc(&ws, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ws = nullptr;
+    return false;
+  }
+  ws_size = bytes;
+  return true;
+}
+
+void Ctx::launch(int cls, double flops, double bytes, const std::function<void()> &f) {
+  if (!prof) {
+    f();
+    return;
+  }
+  hipEvent_t a, b;
+  if (event_pool.size() >= 2) {
+    a = event_pool.back(); event_pool.pop_back();
+    b = event_pool.back(); event_pool.pop_back();
+  } else {
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+  }
+  (void)hipEventRecord(a, stream);
+  f();
+  (void)hipEventRecord(b, stream);
+  pending.push_back({a, b, cls, flops, bytes});
+  if (pending.size() >= 8192) harvest();
+}
+
+void Ctx::harvest() {
+  if (pending.empty()) return;
+  (void)hipStreamSynchronize(stream);
+  for (auto &p : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      stats[p.cls].launches += 1;
+      stats[p.cls].time_ms += ms;
+      stats[p.cls].flops += p.flops;
+      stats[p.cls].bytes += p.bytes;
+    }
+    event_pool.push_back(p.a);
+    event_pool.push_back(p.b);
+  }
+  pending.clear();
+}
+
+int Ctx::check() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    last = e;
+    return INLA_ERR_HIP;
+  }
+  return INLA_OK;
+}
+
+Ctx::~Ctx() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  else (void)hipDeviceSynchronize();
+  for (auto &p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : event_pool) (void)hipEventDestroy(e);
+  if (ws) (void)hipFree(ws);
+  if (ring) (void)hipFree(ring);
+  if (ring_host) (void)hipHostFree(ring_host);
+}
+
+// ------------------------------------------------------------------ planning
+static int g_nb() {
+  static int nb = [] {
+    const char *s = std::getenv("INLA_NB");
+    int v = s ? std::atoi(s) : 256;
+    if (v != 128 && v != 256 && v != 512) v = 256;
+    return v;
+  }();
+  return nb;
+}
+
+// Per-theta workspace plan.
+struct Plan {
+  ThetaDesc t{};
+  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, bytes = 0;
+  int ns_real = 0;
+  bool needs_prior_build = false;
+};
+
+enum Mode { MODE_LAPLACE = 0, MODE_VAR = 1, MODE_LOGDET = 2 };
+
+static int n_prior_params(int prior) { return prior == PRIOR_DENSE ? 0 : (prior == PRIOR_EXPCOV ? 2 : 3); }
+
+// Validate one model; returns 0 or a negative argument index code.
+static int check_model(const inla_model &m) {
+  if (m.n < 1 || m.k < 0 || m.k >= m.n) return -1;
+  if (m.lik != LIK_GAUSSIAN && m.lik != LIK_POISSON) return -1;
+  if (!m.y) return -1;
+  if (m.k > 0 && !m.C) return -1;
+  if (m.prior == PRIOR_DENSE) {
+    if (!m.Qprior || m.ldq < m.n) return -1;
+  } else if (m.prior == PRIOR_EXPCOV) {
+    if (!m.coords || m.n_s != m.n) return -1;
+  } else if (m.prior == PRIOR_KRON) {
+    if (!m.coords || m.n_s < 1 || m.n_t < 1 || (int64_t)m.n_s * m.n_t != m.n) return -1;
+  } else {
+    return -1;
+  }
+  return 0;
+}
+
+static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
+  Plan p;
+  ThetaDesc &t = p.t;
+  t.y = m.y; t.E = m.E; t.C = m.C; t.e = m.e; t.coords = m.coords; t.Quser = m.Qprior;
+  t.n = m.n; t.k = m.k; t.lik = m.lik; t.prior = m.prior; t.n_s = m.n_s; t.n_t = m.n_t; t.ldquser = m.ldq;
+  t.n_pad = round_up(m.n, PADN);
+  const int npp = n_prior_params(m.prior);
+  t.tau = npp ? std::exp(th[0]) : 1.0;
+  t.rho = npp ? std::exp(th[1]) : 1.0;
+  t.delta = npp == 3 ? std::exp(th[2]) : 0.0;
+  const double lp = th[npp];
+  t.lpar = m.lik == LIK_GAUSSIAN ? std::exp(lp) : lp;
+  t.k_pad = round_up(m.k, PADN);
+  t.ldqp = t.n_pad;
+  if (mode == MODE_VAR) {
+    t.Nw = t.n_pad + t.k_pad + t.n_pad;
+    t.Ncw = t.n_pad + t.k_pad;
+    t.Ns = t.k_pad + t.n_pad;
+  } else {
+    t.Nw = t.n_pad + round_up(m.k + 1, PADN);
+    t.Ncw = t.Nw;
+    t.Ns = t.k_pad + PADN;
+  }
+  t.ldw = t.Nw;
+  t.lds = t.Ns;
+  p.needs_prior_build = m.prior != PRIOR_DENSE;
+  if (m.prior == PRIOR_EXPCOV) { t.ns_pad = t.n_pad; p.ns_real = m.n; }
+  else if (m.prior == PRIOR_KRON) { t.ns_pad = round_up(m.n_s, PADN); p.ns_real = m.n_s; }
+  t.Np = 2 * t.ns_pad;
+  t.ldp = t.Np;
+  // layout: [Qp][W/P alias][S][vectors][linv]
+  size_t off = 0;
+  p.off_Qp = off; off += align256(sizeof(double) * (size_t)t.n_pad * t.n_pad);
+  p.off_W = off;
+  const size_t wbytes = sizeof(double) * (size_t)t.ldw * t.Ncw;
+  const size_t pbytes = sizeof(double) * (size_t)t.ldp * t.Np;
+  off += align256(std::max(wbytes, pbytes));
+  p.off_S = off; off += align256(sizeof(double) * (size_t)t.lds * std::max(t.k_pad, 1));
+  p.off_vec = off;
+  off += align256(sizeof(double) * (size_t)(2 * t.n_pad + std::max(t.k_pad, 64) + 2 * t.ldw + DRES_COUNT));
+  p.off_linv = off; off += align256(sizeof(double) * NBI * NBI);
+  p.bytes = off;
+  return p;
+}
+
+static void bind(Plan &p, char *base) {
+  ThetaDesc &t = p.t;
+  t.Qp = (double *)(base + p.off_Qp);
+  t.W = (double *)(base + p.off_W);
+  t.P = t.W;   // the prior build finishes before the working matrix is assembled
+  t.S = (double *)(base + p.off_S);
+  double *v = (double *)(base + p.off_vec);
+  t.x = v; v += t.n_pad;
+  t.r = v; v += t.n_pad;
+  t.lam = v; v += std::max(t.k_pad, 64);
+  t.part = v; v += 2 * t.ldw;
+  t.dres = v;
+}
+
+// State shared by the passes of one call.
+struct Batch {
+  Ctx &ctx;
+  std::vector<Plan> plans;
+  std::vector<char *> bases;
+  int *dinfo = nullptr;        // device [B * 4]: prior-build, big, small, spare
+  double *ddres_all = nullptr; // device copy target list not needed: dres live in workspace
+  std::vector<int> hinfo;
+  std::vector<double> hdres;
+  double *pin = nullptr;       // pinned staging for results
+  explicit Batch(Ctx &c) : ctx(c) {}
+};
+
+// HostFactor for one of the three matrices of a theta.
+enum { F_PRIOR = 0, F_BIG = 1, F_SMALL = 2 };
+static HostFactor factor_of(const Plan &p, int which, int *info, double *linv, Mode mode) {
+  const ThetaDesc &t = p.t;
+  HostFactor h{};
+  h.d.info = info;
+  h.d.linv = linv;
+  h.d.id_row0 = std::numeric_limits<int>::max();
+  if (which == F_PRIOR) {
+    h.d.A = t.P; h.d.ld = t.ldp; h.d.nf = t.ns_pad; h.d.nrows = t.Np; h.d.ncols = t.Np; h.d.id_row0 = t.ns_pad;
+    h.n_real = p.ns_real; h.kb_real = p.ns_real; h.ks_real = p.ns_real;
+  } else if (which == F_BIG) {
+    h.d.A = t.W; h.d.ld = t.ldw; h.d.nf = t.n_pad; h.d.nrows = t.Nw; h.d.ncols = t.Ncw;
+    h.n_real = t.n;
+    if (mode == MODE_VAR) {
+      h.d.id_row0 = t.n_pad + t.k_pad;
+      h.kb_real = t.k_pad + t.n;   // counts the identity rows as border rows
+      h.ks_real = t.k;
+    } else if (mode == MODE_LOGDET) {
+      h.kb_real = 0; h.ks_real = 0;
+    } else {
+      h.kb_real = t.k + 1; h.ks_real = t.k + 1;
+    }
+  } else {
+    h.d.A = t.S; h.d.ld = t.lds; h.d.nf = t.k_pad; h.d.nrows = t.Ns; h.d.ncols = t.k_pad;
+    h.n_real = t.k;
+    h.kb_real = mode == MODE_VAR ? t.n : 1;
+    h.ks_real = 0;
+  }
+  return h;
+}
+
+// Upload the descriptors of a subset of thetas.
+static ThetaDesc *upload_td(Batch &b, const std::vector<int> &ids) {
+  std::vector<ThetaDesc> v;
+  v.reserve(ids.size());
+  for (int i : ids) v.push_back(b.plans[i].t);
+  return (ThetaDesc *)b.ctx.upload(v.data(), sizeof(ThetaDesc) * v.size());
+}
+
+static int run_factor(Batch &b, const std::vector<int> &ids, int which, Mode mode) {
+  std::vector<HostFactor> fs;
+  for (int i : ids) {
+    const Plan &p = b.plans[i];
+    HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (double *)(b.bases[i] + p.off_linv), mode);
+    if (h.d.nf > 0) fs.push_back(h);
+  }
+  return factor_batch(b.ctx, fs, g_nb());
+}
+
+// Read back dres and info of every theta (one synchronisation).
+static int readback(Batch &b) {
+  const int B = (int)b.plans.size();
+  for (int i = 0; i < B; ++i) {
+    if (hipMemcpyAsync(b.pin + DRES_COUNT * i, b.plans[i].t.dres, sizeof(double) * DRES_COUNT, hipMemcpyDeviceToHost,
+                       b.ctx.stream) != hipSuccess)
+      return INLA_ERR_HIP;
+  }
+  int *ipin = (int *)(b.pin + DRES_COUNT * B);
+  if (hipMemcpyAsync(ipin, b.dinfo, sizeof(int) * 4 * B, hipMemcpyDeviceToHost, b.ctx.stream) != hipSuccess)
+    return INLA_ERR_HIP;
+  if (hipStreamSynchronize(b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  b.hdres.assign(b.pin, b.pin + DRES_COUNT * B);
+  b.hinfo.assign(ipin, ipin + 4 * B);
+  return b.ctx.check();
+}
+
+static int max_over(const Batch &b, const std::vector<int> &ids, int ThetaDesc::*f) {
+  int m = 0;
+  for (int i : ids) m = std::max(m, b.plans[i].t.*f);
+  return m;
+}
+
+// Prior build for every theta: Sigma^{-1} by the identity-bordered factorisation,
+// then Q_prior.
+static int prior_build(Batch &b, const std::vector<int> &ids) {
+  std::vector<int> pb;
+  for (int i : ids) if (b.plans[i].needs_prior_build) pb.push_back(i);
+  int rc;
+  if (!pb.empty()) {
+    ThetaDesc *d = upload_td(b, pb);
+    if (!d) return INLA_ERR_NOMEM;
+    launch_expcov_bordered(b.ctx, d, (int)pb.size(), max_over(b, pb, &ThetaDesc::Np));
+    if ((rc = run_factor(b, pb, F_PRIOR, MODE_LAPLACE))) return rc;
+  }
+  ThetaDesc *d = upload_td(b, ids);
+  if (!d) return INLA_ERR_NOMEM;
+  double bytes = 0;
+  for (int i : ids) bytes += 8.0 * 0.5 * b.plans[i].t.n * (b.plans[i].t.n + 1.0);
+  launch_prior_assemble(b.ctx, d, (int)ids.size(), max_over(b, ids, &ThetaDesc::n_pad), bytes);
+  return b.ctx.check();
+}
+
+// One pass: assemble the bordered matrix at the current x, factor it, build and
+// factor the kriging system, solve it; then (Newton) form the corrected
+// right-hand side and back-substitute, or (prior / final) reduce the log-dets.
+enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2 };
+static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass) {
+  if (ids.empty()) return 0;
+  ThetaDesc *d = upload_td(b, ids);
+  if (!d) return INLA_ERR_NOMEM;
+  const int B = (int)ids.size();
+  double abytes = 0, tbytes = 0;
+  for (int i : ids) {
+    const ThetaDesc &t = b.plans[i].t;
+    abytes += 8.0 * (0.5 * t.n * (t.n + 1.0)) * 2.0 + 8.0 * (double)t.n * (t.k + 1);
+    tbytes += 8.0 * 0.5 * t.n * (t.n + 1.0);
+  }
+  launch_assemble(b.ctx, d, B, max_over(b, ids, &ThetaDesc::Ncw), pass != PASS_PRIOR, pass == PASS_FINAL, BORDER_CB,
+                  abytes);
+  int rc;
+  if ((rc = run_factor(b, ids, F_BIG, MODE_LAPLACE))) return rc;
+  launch_kriging_build(b.ctx, d, B, max_over(b, ids, &ThetaDesc::k_pad));
+  if ((rc = run_factor(b, ids, F_SMALL, MODE_LAPLACE))) return rc;
+  launch_kriging_solve(b.ctx, d, B);
+  if (pass == PASS_NEWTON) {
+    launch_rhs(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad));
+    launch_trsv(b.ctx, d, B, tbytes);
+  } else {
+    launch_finish(b.ctx, d, B);
+  }
+  return b.ctx.check();
+}
+
+// Allocate and bind the workspace of a batch; zero the per-theta scratch.
+static int setup(Batch &b, int B, const inla_model *models, const double *theta, int ldtheta, Mode mode) {
+  b.plans.resize(B);
+  size_t total = 0;
+  std::vector<size_t> offs(B);
+  for (int i = 0; i < B; ++i) {
+    b.plans[i] = make_plan(models[i], theta ? theta + (size_t)i * ldtheta : nullptr, mode);
+    offs[i] = total;
+    total += b.plans[i].bytes;
+  }
+  const size_t info_off = total;
+  total += align256(sizeof(int) * 4 * B);
+  const size_t pin_off = total;  // not used on device; keeps layout simple
+  (void)pin_off;
+  if (!b.ctx.reserve(total)) return INLA_ERR_NOMEM;
+  b.bases.resize(B);
+  for (int i = 0; i < B; ++i) {
+    b.bases[i] = b.ctx.ws + offs[i];
+    bind(b.plans[i], b.bases[i]);
+  }
+  b.dinfo = (int *)(b.ctx.ws + info_off);
+  if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  for (int i = 0; i < B; ++i) {
+    const ThetaDesc &t = b.plans[i].t;
+    if (hipMemsetAsync(t.dres, 0, sizeof(double) * DRES_COUNT, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  }
+  if (hipHostMalloc(&b.pin, sizeof(double) * DRES_COUNT * B + sizeof(int) * 4 * B + 64) != hipSuccess)
+    return INLA_ERR_NOMEM;
+  return 0;
+}
+
+static void teardown(Batch &b) {
+  if (b.pin) (void)hipHostFree(b.pin);
+  b.pin = nullptr;
+}
+
+// Memory budget for one chunk of thetas: 85% of the device's free memory.
+static size_t budget(Ctx &ctx) {
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) return (size_t)64 << 30;
+  return (size_t)((fr + ctx.ws_size) * 0.85);
+}
+
+static int validate_common(inla_handle *h, int B, const inla_model *models, const double *theta, int ldtheta,
+                           inla_result *res_or_null, bool need_res) {
+  if (!h) return -1;
+  if (B < 0) return -2;
+  if (B > 0 && !models) return -3;
+  if (B > 0 && !theta) return -4;
+  int maxp = 0;
+  for (int i = 0; i < B; ++i) {
+    if (check_model(models[i])) return -3;
+    maxp = std::max(maxp, n_prior_params(models[i].prior) + 1);
+  }
+  if (B > 0 && ldtheta < maxp) return -5;
+  if (need_res && B > 0 && !res_or_null) return -8;
+  return 0;
+}
+
+// Split [0, B) into chunks whose workspace fits the budget.
+static std::vector<std::pair<int, int>> chunks(Ctx &ctx, int B, const inla_model *models, const double *theta,
+                                               int ldtheta, Mode mode) {
+  std::vector<std::pair<int, int>> out;
+  const size_t cap = budget(ctx);
+  int s = 0;
+  while (s < B) {
+    size_t tot = 0;
+    int e = s;
+    while (e < B) {
+      const size_t need = make_plan(models[e], theta + (size_t)e * ldtheta, mode).bytes + 4096;
+      if (e > s && tot + need > cap) break;
+      tot += need;
+      ++e;
+    }
+    out.push_back({s, e});
+    s = e;
+  }
+  return out;
+}
+
+// The whole per-theta evaluation for one chunk.
+static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta, double *const *x,
+                      const inla_opts *opts, inla_result *res, bool laplace) {
+  Batch b(ctx);
+  int rc = setup(b, B, models, theta, ldtheta, MODE_LAPLACE);
+  if (rc) { teardown(b); return rc; }
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 50;
+  const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-11;
+  const bool warm = opts && opts->start == 1;
+  std::vector<int> all, ok;
+  for (int i = 0; i < B; ++i) {
+    res[i] = inla_result{};
+    const ThetaDesc &t = b.plans[i].t;
+    bool finite = true;
+    for (int j = 0; j < ldtheta && j <= n_prior_params(t.prior); ++j) finite = finite && std::isfinite(theta[(size_t)i * ldtheta + j]);
+    if (!finite) { res[i].info = INLA_INFO_NONFINITE; continue; }
+    all.push_back(i);
+    if (warm) {
+      if (hipMemcpyAsync(t.x, x[i], sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) { teardown(b); return INLA_ERR_HIP; }
+      if (t.n_pad > t.n && hipMemsetAsync(t.x + t.n, 0, sizeof(double) * (t.n_pad - t.n), ctx.stream) != hipSuccess) { teardown(b); return INLA_ERR_HIP; }
+    } else if (hipMemsetAsync(t.x, 0, sizeof(double) * t.n_pad, ctx.stream) != hipSuccess) {
+      teardown(b); return INLA_ERR_HIP;
+    }
+  }
+  auto fail = [&](int r) { teardown(b); return r; };
+  if ((rc = prior_build(b, all))) return fail(rc);
+  if ((rc = run_pass(b, all, PASS_PRIOR))) return fail(rc);
+  if ((rc = readback(b))) return fail(rc);
+  for (int i : all) {
+    const int *inf = &b.hinfo[4 * i];
+    const double *dr = &b.hdres[DRES_COUNT * i];
+    if (inf[F_PRIOR]) { res[i].info = inf[F_PRIOR]; continue; }
+    if (inf[F_BIG]) { res[i].info = inf[F_BIG]; continue; }
+    if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; continue; }
+    res[i].logdet_qprior = dr[DRES_LOGDET_L];
+    res[i].logdet_sprior = dr[DRES_LOGDET_S];
+    res[i].ese = dr[DRES_WNORM2];
+    ok.push_back(i);
+  }
+  // Newton iteration (warm-start vectors were checked for finiteness by the
+  // first assembly: a non-finite W or b sets the flag).
+  std::vector<int> active = ok, done;
+  std::vector<char> failed(B, 0);
+  for (int it = 1; it <= max_iter && !active.empty(); ++it) {
+    if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    if ((rc = run_pass(b, active, PASS_NEWTON))) return fail(rc);
+    if ((rc = readback(b))) return fail(rc);
+    std::vector<int> next;
+    for (int i : active) {
+      const int *inf = &b.hinfo[4 * i];
+      const double *dr = &b.hdres[DRES_COUNT * i];
+      res[i].iters = it;
+      if (dr[DRES_NONFINITE] != 0.0) { res[i].info = INLA_INFO_NONFINITE; failed[i] = 1; continue; }
+      if (inf[F_BIG]) { res[i].info = inf[F_BIG]; failed[i] = 1; continue; }
+      if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; failed[i] = 1; continue; }
+      res[i].step = dr[DRES_STEP];
+      const bool conv = b.plans[i].t.lik == LIK_GAUSSIAN || dr[DRES_STEP] <= tol * dr[DRES_SCALE];
+      if (conv) done.push_back(i);
+      else if (it == max_iter) { res[i].info = INLA_INFO_NEWTON_MAXIT; done.push_back(i); }
+      else next.push_back(i);
+    }
+    active.swap(next);
+  }
+  // copy the modes out
+  for (int i : ok) {
+    if (failed[i]) continue;
+    const ThetaDesc &t = b.plans[i].t;
+    if (hipMemcpyAsync(x[i], t.x, sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+  }
+  if (laplace) {
+    std::vector<int> fin;
+    for (int i : done) if (!failed[i]) fin.push_back(i);
+    if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    if ((rc = run_pass(b, fin, PASS_FINAL))) return fail(rc);
+    if ((rc = readback(b))) return fail(rc);
+    for (int i : fin) {
+      const int *inf = &b.hinfo[4 * i];
+      const double *dr = &b.hdres[DRES_COUNT * i];
+      if (inf[F_BIG]) { res[i].info = inf[F_BIG]; continue; }
+      if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; continue; }
+      inla_result &r = res[i];
+      r.logdet_qstar = dr[DRES_LOGDET_L];
+      r.logdet_s = dr[DRES_LOGDET_S];
+      r.xqx = dr[DRES_XQX];
+      r.loglik = dr[DRES_LOGLIK];
+      r.objective = 0.5 * r.logdet_qprior + 0.5 * r.logdet_sprior + 0.5 * r.ese - 0.5 * r.xqx + r.loglik -
+                    0.5 * r.logdet_qstar - 0.5 * r.logdet_s;
+    }
+  } else {
+    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+  }
+  ctx.harvest();
+  teardown(b);
+  return ctx.check();
+}
+
+static int var_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
+                     const double *const *xm, double *const *var, int32_t *info) {
+  Batch b(ctx);
+  int rc = setup(b, B, models, theta, ldtheta, MODE_VAR);
+  if (rc) { teardown(b); return rc; }
+  auto fail = [&](int r) { teardown(b); return r; };
+  std::vector<int> all;
+  for (int i = 0; i < B; ++i) {
+    info[i] = 0;
+    ThetaDesc &t = b.plans[i].t;
+    t.out = var[i];
+    if (hipMemcpyAsync(t.x, xm[i], sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    if (t.n_pad > t.n && hipMemsetAsync(t.x + t.n, 0, sizeof(double) * (t.n_pad - t.n), ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    all.push_back(i);
+  }
+  if ((rc = prior_build(b, all))) return fail(rc);
+  ThetaDesc *d = upload_td(b, all);
+  if (!d) return fail(INLA_ERR_NOMEM);
+  launch_assemble(ctx, d, B, max_over(b, all, &ThetaDesc::Ncw), 1, 0, BORDER_CI, 0.0);
+  if ((rc = run_factor(b, all, F_BIG, MODE_VAR))) return fail(rc);
+  launch_var_small_build(ctx, d, B, max_over(b, all, &ThetaDesc::k_pad));
+  if ((rc = run_factor(b, all, F_SMALL, MODE_VAR))) return fail(rc);
+  launch_var_norms(ctx, d, B, max_over(b, all, &ThetaDesc::n_pad));
+  if ((rc = readback(b))) return fail(rc);
+  for (int i = 0; i < B; ++i) {
+    const int *inf = &b.hinfo[4 * i];
+    if (inf[F_PRIOR]) info[i] = inf[F_PRIOR];
+    else if (inf[F_BIG]) info[i] = inf[F_BIG];
+    else if (inf[F_SMALL]) info[i] = INLA_INFO_CONSTRAINT_RANK;
+    else if (b.hdres[DRES_COUNT * i + DRES_NONFINITE] != 0.0) info[i] = INLA_INFO_NONFINITE;
+  }
+  ctx.harvest();
+  teardown(b);
+  return ctx.check();
+}
+
+}  // namespace inla
+
+// ====================================================================== C-ABI
+using namespace inla;
+
+struct inla_handle {
+  Ctx ctx;
+};
+
+extern "C" {
+
+const char *inla_version(void) { return "inla_dense 0.1 (gfx950, fp64 mfma)"; }
+
+int inla_create(inla_handle **h, void *stream) {
+  if (!h) return -1;
+  *h = nullptr;
+  inla_handle *p = new (std::nothrow) inla_handle();
+  if (!p) return INLA_ERR_NOMEM;
+  p->ctx.stream = (hipStream_t)stream;
+  if (hipGetDevice(&p->ctx.device) != hipSuccess) { delete p; return INLA_ERR_HIP; }
+  p->ctx.ring_size = (size_t)4 << 20;
+  if (hipMalloc(&p->ctx.ring, p->ctx.ring_size) != hipSuccess ||
+      hipHostMalloc(&p->ctx.ring_host, p->ctx.ring_size) != hipSuccess) {
+    delete p;
+    return INLA_ERR_NOMEM;
+  }
+  *h = p;
+  return INLA_OK;
+}
+
+int inla_destroy(inla_handle *h) {
+  delete h;
+  return INLA_OK;
+}
+
+int inla_set_stream(inla_handle *h, void *stream) {
+  if (!h) return -1;
+  if (hipStreamSynchronize(h->ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  h->ctx.stream = (hipStream_t)stream;
+  return INLA_OK;
+}
+
+int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq, double *logdet,
+                int32_t *info) {
+  if (!h) return -1;
+  if (B < 0) return -2;
+  if (B == 0) return INLA_OK;
+  if (!n) return -3;
+  if (!Q) return -4;
+  if (!ldq) return -5;
+  if (!logdet) return -6;
+  if (!info) return -7;
+  for (int i = 0; i < B; ++i) {
+    if (n[i] < 0) return -3;
+    if (n[i] > 0 && !Q[i]) return -4;
+    if (ldq[i] < std::max(1, n[i])) return -5;
+  }
+  Ctx &ctx = h->ctx;
+  // one chunk per memory budget
+  const size_t cap = budget(ctx);
+  int s = 0;
+  while (s < B) {
+    std::vector<int> ids;
+    size_t tot = 0;
+    int e = s;
+    for (; e < B; ++e) {
+      const int np = round_up(std::max(n[e], 1), PADN);
+      const size_t need = align256(8ull * np * np) + align256(8ull * (2 * np + 64 + 2 * np + DRES_COUNT)) + align256(8 * NBI * NBI);
+      if (e > s && tot + need > cap) break;
+      tot += need;
+    }
+    Batch b(ctx);
+    const int Bc = e - s;
+    b.plans.resize(Bc);
+    size_t total = 0;
+    std::vector<size_t> offs(Bc);
+    for (int i = 0; i < Bc; ++i) {
+      Plan &p = b.plans[i];
+      ThetaDesc &t = p.t;
+      t.n = n[s + i]; t.n_pad = round_up(std::max(t.n, 1), PADN);
+      t.Quser = Q[s + i]; t.ldquser = ldq[s + i];
+      t.ldw = t.Nw = t.Ncw = t.n_pad;
+      size_t off = 0;
+      p.off_W = off; off += align256(8ull * t.n_pad * t.n_pad);
+      p.off_vec = off; off += align256(8ull * (2 * t.n_pad + 64 + 2 * t.ldw + DRES_COUNT));
+      p.off_linv = off; off += align256(8 * NBI * NBI);
+      p.bytes = off;
+      offs[i] = total; total += off;
+    }
+    const size_t info_off = total;
+    total += align256(sizeof(int) * 4 * Bc);
+    if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+    b.bases.resize(Bc);
+    for (int i = 0; i < Bc; ++i) {
+      Plan &p = b.plans[i];
+      b.bases[i] = ctx.ws + offs[i];
+      ThetaDesc &t = p.t;
+      t.W = (double *)(b.bases[i] + p.off_W);
+      double *v = (double *)(b.bases[i] + p.off_vec);
+      t.x = v; v += t.n_pad; t.r = v; v += t.n_pad; t.lam = v; v += 64; t.part = v; v += 2 * t.ldw; t.dres = v;
+      t.Qp = nullptr; t.S = nullptr; t.P = nullptr;
+    }
+    b.dinfo = (int *)(ctx.ws + info_off);
+    if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * Bc, ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    if (hipHostMalloc(&b.pin, sizeof(double) * DRES_COUNT * Bc + sizeof(int) * 4 * Bc + 64) != hipSuccess)
+      return INLA_ERR_NOMEM;
+    std::vector<int> ids2;
+    for (int i = 0; i < Bc; ++i) if (b.plans[i].t.n > 0) ids2.push_back(i);
+    int rc = 0;
+    if (!ids2.empty()) {
+      ThetaDesc *d = upload_td(b, ids2);
+      if (!d) { teardown(b); return INLA_ERR_NOMEM; }
+      launch_copy_in(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n_pad));
+      if ((rc = run_factor(b, ids2, F_BIG, MODE_LOGDET))) { teardown(b); return rc; }
+      launch_finish(ctx, d, (int)ids2.size());
+      launch_copy_out(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n));
+    }
+    if ((rc = readback(b))) { teardown(b); return rc; }
+    for (int i = 0; i < Bc; ++i) {
+      const int f = b.hinfo[4 * i + F_BIG];
+      info[s + i] = f;
+      logdet[s + i] = b.plans[i].t.n == 0 ? 0.0 : (f ? std::numeric_limits<double>::quiet_NaN() : b.hdres[DRES_COUNT * i + DRES_LOGDET_L]);
+    }
+    ctx.harvest();
+    teardown(b);
+    s = e;
+  }
+  return ctx.check();
+}
+
+static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                        double *const *x, const inla_opts *opts, inla_result *res, bool laplace) {
+  int rc = validate_common(h, B, models, theta, ldtheta, res, true);
+  if (rc) return rc;
+  if (B == 0) return INLA_OK;
+  if (!x) return -6;
+  for (int i = 0; i < B; ++i) if (!x[i]) return -6;
+  if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
+  for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
+    rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
+                    x + c.first, opts, res + c.first, laplace);
+    if (rc) return rc;
+  }
+  return INLA_OK;
+}
+
+int inla_constrained_mode(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                          double *const *x, const inla_opts *opts, inla_result *res) {
+  return mode_or_eval(h, B, models, theta, ldtheta, x, opts, res, false);
+}
+
+int inla_laplace_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                      double *const *x, const inla_opts *opts, inla_result *res) {
+  return mode_or_eval(h, B, models, theta, ldtheta, x, opts, res, true);
+}
+
+int inla_marginal_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                      const double *const *x_mode, double *const *var, int32_t *info) {
+  int rc = validate_common(h, B, models, theta, ldtheta, nullptr, false);
+  if (rc) return rc;
+  if (B == 0) return INLA_OK;
+  if (!x_mode) return -6;
+  if (!var) return -7;
+  if (!info) return -8;
+  for (int i = 0; i < B; ++i) if (!x_mode[i] || !var[i]) return -6;
+  for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_VAR)) {
+    rc = var_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
+                   x_mode + c.first, var + c.first, info + c.first);
+    if (rc) return rc;
+  }
+  return INLA_OK;
+}
+
+int inla_profile(inla_handle *h, int32_t enable) {
+  if (!h) return -1;
+  h->ctx.harvest();
+  h->ctx.prof = enable != 0;
+  if (enable) for (auto &s : h->ctx.stats) s = inla_kstats{};
+  return INLA_OK;
+}
+
+int inla_profile_get(inla_handle *h, int32_t kclass, inla_kstats *out) {
+  if (!h) return -1;
+  if (kclass < 0 || kclass >= INLA_K_COUNT) return -2;
+  if (!out) return -3;
+  h->ctx.harvest();
+  *out = h->ctx.stats[kclass];
+  return INLA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+// Triangular solves, the kriging solve, Newton control and fixed-order
+// reductions.  One workgroup per theta unless stated otherwise.
+#include "device.hpp"
+#include "host.hpp"
+#include "model.hpp"
+
+namespace inla {
+
+// Solve L^T x = x in place for a lower-triangular L (column-major, order np, a
+// multiple of 64) in 64-row blocks from the bottom.  For each block: the 64
+// dot products with the already solved tail (coalesced column reads, 16 columns
+// per wave), then a 64-step substitution in wave 0 with the block's columns held
+// in registers.  Global writes to x are made visible to the other waves of the
+// workgroup by the barriers.
+__device__ void trsv_lt_block(const double *__restrict__ L, int ld, int np, double *x, double *sred) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i0 = np - 64; i0 >= 0; i0 -= 64) {
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    const double *Lc = L + (size_t)(i0 + 16 * w) * ld;
+    for (int j = i0 + 64 + lane; j < np; j += 64) {
+      const double xj = x[j];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] += Lc[(size_t)q * ld + j] * xj;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const double s = wave_sum(acc[q]);
+      if (lane == 0) sred[16 * w + q] = s;
+    }
+    __syncthreads();
+    if (w == 0) {
+      double dcol[64];
+      const double *Dc = L + (size_t)(i0 + lane) * ld + i0;
+#pragma unroll
+      for (int i = 0; i < 64; ++i) dcol[i] = Dc[i];
+      double rhs = x[i0 + lane] - sred[lane];
+      double xm = 0.0;
+#pragma unroll
+      for (int i = 63; i >= 0; --i) {
+        const double xi = __shfl(rhs / dcol[i], i, 64);
+        if (lane == i) xm = xi;
+        if (lane < i) rhs -= dcol[i] * xi;
+      }
+      x[i0 + lane] = xm;
+    }
+    __syncthreads();
+  }
+}
+
+// Newton solve x_new = L^{-T} r, then the stopping quantities
+// ||x_new - x||_inf and max(1, ||x_new||_inf) over the n real entries, and x <- x_new.
+__global__ __launch_bounds__(256) void trsv_newton_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sred[64];
+  __shared__ double sh[4];
+  trsv_lt_block(t.W, t.ldw, t.n_pad, t.r, sred);
+  double st = 0.0, sc = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < t.n; i += 256) {
+    const double xn = t.r[i], xo = t.x[i];
+    if (!isfinite(xn)) bad = 1.0;
+    st = fmax(st, fabs(xn - xo));
+    sc = fmax(sc, fabs(xn));
+  }
+  st = block_max256(st, sh);
+  sc = block_max256(sc, sh);
+  bad = block_sum256(bad, sh);
+  for (int i = threadIdx.x; i < t.n_pad; i += 256) t.x[i] = i < t.n ? t.r[i] : 0.0;
+  if (threadIdx.x == 0) {
+    t.dres[DRES_STEP] = st;
+    t.dres[DRES_SCALE] = fmax(1.0, sc);
+    if (bad > 0.0) t.dres[DRES_NONFINITE] = 1.0;
+  }
+}
+
+// Kriging solve after the small factorisation: w from the border row, then
+// lambda = L_S^{-T} w; also log|S| = 2 sum log (L_S)_ii and ||w||^2.
+__global__ __launch_bounds__(256) void kriging_solve_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sred[64];
+  __shared__ double sh[4];
+  const int kp = t.k_pad, k = t.k;
+  double lds_ = 0.0, w2 = 0.0, dmin = INFINITY, dmax = 0.0;
+  for (int i = threadIdx.x; i < kp; i += 256) {
+    const double wv = i < k ? t.S[(size_t)i * t.lds + kp] : 0.0;
+    t.lam[i] = wv;
+    w2 += wv * wv;
+    if (i < k) {
+      const double d = t.S[(size_t)i * t.lds + i];
+      lds_ += log(d);
+      dmin = fmin(dmin, d * d);
+      dmax = fmax(dmax, d * d);
+    }
+  }
+  lds_ = block_sum256(lds_, sh);
+  w2 = block_sum256(w2, sh);
+  dmin = -block_max256(-dmin, sh);
+  dmax = block_max256(dmax, sh);
+  trsv_lt_block(t.S, t.lds, kp, t.lam, sred);
+  if (threadIdx.x == 0) {
+    t.dres[DRES_LOGDET_S] = 2.0 * lds_;
+    t.dres[DRES_WNORM2] = w2;
+    // squared pivot below 1e-13 of the largest: numerically dependent constraints
+    t.dres[DRES_RANK] = (k > 0 && !(dmin >= 1e-13 * dmax)) ? 1.0 : 0.0;
+  }
+}
+
+// r_c = z_c - sum_a lambda_a (G L^{-T})_{a,c}: the kriging-corrected right-hand
+// side for x = L^{-T} (L^{-1} b - L^{-1} C^T lambda).  z is the factored b row.
+__global__ __launch_bounds__(256) void rhs_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c0 = blockIdx.x * 64 + w * 16;
+  if (c0 >= t.n_pad) return;
+  const int k = t.k, np = t.n_pad;
+  for (int q = 0; q < 16; ++q) {
+    const int c = c0 + q;
+    const double *col = t.W + (size_t)c * t.ldw + np;
+    double s = 0.0;
+    for (int a = lane; a < k; a += 64) s += t.lam[a] * col[a];
+    s = wave_sum(s);
+    if (lane == 0) t.r[c] = col[k] - s;
+  }
+}
+
+// log|Q| = 2 sum_{i<n} log L_ii of the big factor, and the fixed-order sums of
+// the per-column partials (log-likelihood, x^T Q_prior x).
+__global__ __launch_bounds__(256) void finish_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sh[4];
+  double ld = 0.0, ll = 0.0, xq = 0.0;
+  for (int i = threadIdx.x; i < t.n; i += 256) {
+    ld += log(t.W[(size_t)i * t.ldw + i]);
+    ll += t.part[i];
+    xq += t.part[t.ldw + i];
+  }
+  ld = block_sum256(ld, sh);
+  ll = block_sum256(ll, sh);
+  xq = block_sum256(xq, sh);
+  if (threadIdx.x == 0) {
+    t.dres[DRES_LOGDET_L] = 2.0 * ld;
+    t.dres[DRES_LOGLIK] = ll;
+    t.dres[DRES_XQX] = xq;
+  }
+}
+
+// Caller matrix (t.Quser, ld t.ldquser, order n) -> working matrix, identity padded.
+__global__ __launch_bounds__(256) void copy_in_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= t.Nw) return;
+  double *col = t.W + (size_t)c * t.ldw;
+  const double *src = t.Quser + (size_t)c * t.ldquser;
+  for (int r = c + threadIdx.x; r < t.Nw; r += 256) col[r] = (r < t.n && c < t.n) ? src[r] : (r == c ? 1.0 : 0.0);
+}
+// Factor -> caller matrix (lower triangle only).
+__global__ __launch_bounds__(256) void copy_out_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= t.n) return;
+  const double *col = t.W + (size_t)c * t.ldw;
+  double *dst = (double *)t.Quser + (size_t)c * t.ldquser;
+  for (int r = c + threadIdx.x; r < t.n; r += 256) dst[r] = col[r];
+}
+
+// Marginal variances, small system: S = -Schur(C, C) with the border rows
+// V_i = -Schur(I_i, C) (V = Q^{-1} C^T) below it, k_pad columns to factor.
+__global__ __launch_bounds__(256) void var_small_build_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int c = blockIdx.x;
+  const int kp = t.k_pad, k = t.k, np = t.n_pad;
+  if (c >= kp) return;
+  double *col = t.S + (size_t)c * t.lds;
+  const double *sch = t.W + (size_t)(np + c) * t.ldw + np;   // column np + c of the big matrix, from row np
+  for (int r = c + threadIdx.x; r < t.Ns; r += 256) {
+    double v = 0.0;
+    if (r < kp) {
+      if (r < k && c < k) v = -sch[r];
+      else if (r == c) v = 1.0;
+    } else if (c < k) {
+      v = -sch[kp + (r - kp)];     // row np + kp + i of the big matrix: identity-border row i
+    }
+    col[r] = v;
+  }
+}
+
+// var_i = ||row i of L^{-T}||^2 - ||row i of V L_S^{-T}||^2 (i < n), written to t.out.
+__global__ __launch_bounds__(256) void var_norms_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.n) return;
+  const int np = t.n_pad, kp = t.k_pad;
+  const double *row = t.W + np + kp + i;
+  double s = 0.0;
+  for (int c = 0; c < np; ++c) { const double v = row[(size_t)c * t.ldw]; s += v * v; }
+  double s2 = 0.0;
+  if (t.k > 0) {
+    const double *row2 = t.S + kp + i;
+    for (int c = 0; c < t.k; ++c) { const double v = row2[(size_t)c * t.lds]; s2 += v * v; }
+  }
+  t.out[i] = s - s2;
+}
+
+// ------------------------------------------------------------------ launchers
+void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(kriging_solve_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(rhs_kernel, dim3((np_max + 63) / 64, B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] { hipLaunchKernelGGL(trsv_newton_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(finish_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] { hipLaunchKernelGGL(copy_in_kernel, dim3(np_max, B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max) {
+  if (B <= 0 || n_max <= 0) return;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] { hipLaunchKernelGGL(copy_out_kernel, dim3(n_max, B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_var_small_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max) {
+  if (B <= 0 || kp_max <= 0) return;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(var_small_build_kernel, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+void launch_var_norms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(var_norms_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+
+}  // namespace inla

@@ -1,0 +1,28 @@
+// Host launchers of the model / solve kernels and shared enums.
+#pragma once
+#include "device.hpp"
+#include "host.hpp"
+
+namespace inla {
+
+enum { BORDER_CB = 0,   // border rows [C; b^T]  (Newton / prior / final passes)
+       BORDER_CI = 1 }; // border rows [C; I]    (marginal variances)
+
+__device__ __forceinline__ int round_up_dev(int v, int m) { return (v + m - 1) / m * m; }
+
+void launch_expcov_bordered(Ctx &ctx, const ThetaDesc *dtd, int B, int Np_max);
+void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes);
+void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
+                     double bytes);
+void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int Ns_max);
+
+void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B);
+void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
+void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes);
+void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B);
+void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
+void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max);
+void launch_var_small_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max);
+void launch_var_norms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
+
+}  // namespace inla
