@@ -122,11 +122,16 @@ def prior_exact(model, theta):
     return Q
 
 
+def _lik_param(model, theta):
+    """Theta holds the prior parameters first, then the likelihood parameter."""
+    return float(theta[{"dense": 0, "expcov": 2, "kron": 3}[model["prior"]]])
+
+
 def lik_exact(model, theta, eta):
     """(g, W, loglik) at float eta; g and W returned as Fractions."""
     y = [float(v) for v in model["y"]]
     if model["lik"] == "gaussian":
-        s2 = math.exp(theta[-1])
+        s2 = math.exp(_lik_param(model, theta))
         g = [F((yi - ei) / s2) for yi, ei in zip(y, eta)]
         W = [F(1.0 / s2)] * len(y)
         ll = sum(-0.5 * math.log(2 * math.pi * s2) - (yi - ei) ** 2 / (2 * s2) for yi, ei in zip(y, eta))
@@ -141,7 +146,7 @@ def lik_exact(model, theta, eta):
 
 
 def _offset(model, theta):
-    return float(theta[-1]) if model["lik"] == "poisson" else 0.0
+    return _lik_param(model, theta) if model["lik"] == "poisson" else 0.0
 
 
 def _A(model, n):

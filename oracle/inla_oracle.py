@@ -152,8 +152,13 @@ def chol_solve(L, B):
 # Likelihood (sections "Bypassing constraints ..." and "Model": Poisson with    #
 # exposure phi; the configurations add a Gaussian likelihood).                  #
 # --------------------------------------------------------------------------- #
+def lik_param(model, theta):
+    """The likelihood parameter: the entry right after the prior parameters."""
+    return float(theta[n_prior_params(model["prior"])])
+
+
 def offset_of(model, theta):
-    return float(theta[-1]) if model["lik"] == "poisson" else 0.0
+    return lik_param(model, theta) if model["lik"] == "poisson" else 0.0
 
 
 def lik_terms(model, theta, eta):
@@ -161,7 +166,7 @@ def lik_terms(model, theta, eta):
     (the Q_l of the Gaussian approximation), loglik = sum_i log pi(y_i|eta_i)."""
     y = np.asarray(model["y"], dtype=np.float64)
     if model["lik"] == "gaussian":
-        s2 = math.exp(theta[-1])
+        s2 = math.exp(lik_param(model, theta))
         r = y - eta
         g = r / s2
         W = np.full_like(eta, 1.0 / s2)

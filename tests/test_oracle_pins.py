@@ -229,3 +229,15 @@ def test_rank_deficient_constraints_flagged():
     model["e"] = np.zeros(model["C"].shape[0])
     out = O.laplace_eval(model, synth.kron_theta0(3))
     assert out["info"] == O.INFO_CONSTRAINT_RANK
+
+
+def test_theta_layout_padded_rows():
+    """Theta rows may be padded: the likelihood parameter is the entry right
+    after the prior parameters, whatever the row length."""
+    m = synth.dense_poisson(12, 2, seed=3)
+    a = O.laplace_eval(m, np.array([0.1]))
+    b = O.laplace_eval(m, np.array([0.1, 0.0, 0.0, 0.0]))
+    assert a["objective"] == b["objective"]
+    g = synth.expcov_gaussian(10, seed=3)
+    th = np.array([0.2, math.log(0.3), math.log(0.4)])
+    assert O.laplace_eval(g, th)["objective"] == O.laplace_eval(g, np.append(th, 7.0))["objective"]
