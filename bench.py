@@ -95,7 +95,7 @@ def main():
         log(f"step {s} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    gemm = lib.profile_get(binding.K_GEMM)
+    gemm = lib.profile_get(binding.K_TRAIL)
     stats = {binding.K_NAMES[c]: lib.profile_get(c) for c in binding.K_NAMES}
     lib.profile(False)
 
@@ -107,8 +107,9 @@ def main():
     avg_ms = gemm["time_ms"] / max(1, gemm["launches"])
     achieved = gemm["flops"] / (gemm["time_ms"] * 1e-3) / 1e12 if gemm["time_ms"] > 0 else 0.0
     # whole-factorisation rate: every kernel of the blocked Cholesky
-    fact_ms = stats["gemm"]["time_ms"] + stats["potf2"]["time_ms"]
-    fact_flops = stats["gemm"]["flops"] + stats["potf2"]["flops"]
+    fact = ("trail", "panel", "potf2")
+    fact_ms = sum(stats[c]["time_ms"] for c in fact)
+    fact_flops = sum(stats[c]["flops"] for c in fact)
     out = {
         "metric": METRIC,
         "value": value,
@@ -130,7 +131,7 @@ def main():
         },
         "roofline": {
             "bound": "mfma",
-            "kernel": "gemm_update_kernel (FP64 MFMA trailing SYRK/GEMM + panel TRSM)",
+            "kernel": "gemm_update_kernel<128,128> (FP64 MFMA trailing update of the blocked Cholesky)",
             "achieved": achieved,
             "peak": PEAK_FP64_MFMA_TFLOPS,
             "unit": "TFLOP/s",

@@ -179,11 +179,12 @@ int inla_marginal_var(inla_handle *h, int32_t B, const inla_model *models, const
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */
 enum {
-  INLA_K_GEMM = 0,      /* MFMA tile update: trailing SYRK/GEMM and panel TRSM */
-  INLA_K_POTF2 = 1,     /* diagonal-block factorisation and inversion          */
-  INLA_K_ASSEMBLE = 2,  /* prior build, Q* / border assembly, likelihood       */
-  INLA_K_SOLVE = 3,     /* triangular solves, kriging system, reductions       */
-  INLA_K_COUNT = 4
+  INLA_K_TRAIL = 0,     /* MFMA trailing update of the blocked Cholesky (128 x 128 tiles) */
+  INLA_K_PANEL = 1,     /* MFMA panel TRSM and in-panel updates (64 x 64 tiles)           */
+  INLA_K_POTF2 = 2,     /* diagonal-block factorisation and inversion                     */
+  INLA_K_ASSEMBLE = 3,  /* prior build, Q* / border assembly, likelihood                  */
+  INLA_K_SOLVE = 4,     /* triangular solves, kriging system, reductions                  */
+  INLA_K_COUNT = 5
 };
 typedef struct inla_kstats {
   int64_t launches;  /* kernel launches recorded                              */

@@ -23,8 +23,8 @@ INFO_NEWTON_MAXIT = -1
 INFO_CONSTRAINT_RANK = -2
 INFO_NONFINITE = -3
 
-K_GEMM, K_POTF2, K_ASSEMBLE, K_SOLVE = 0, 1, 2, 3
-K_NAMES = {K_GEMM: "gemm", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve"}
+K_TRAIL, K_PANEL, K_POTF2, K_ASSEMBLE, K_SOLVE = 0, 1, 2, 3, 4
+K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve"}
 
 # Symbols declared by include/inla_dense.h
 EXPORTS = [

@@ -13,6 +13,17 @@ constexpr int KC = 16;       // K chunk staged through LDS by the MFMA kernels
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
+// Global-address-space views.  Pointers read out of descriptor structs are
+// generic; without the cast the compiler emits flat loads, which also count
+// against the LDS wait counter and so serialise prefetch with LDS reads.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) d2 gd2;
+typedef __attribute__((address_space(1))) const d2 gcd2;
+template <typename T> __device__ __forceinline__ __attribute__((address_space(1))) T *gptr(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 // One matrix being factored by the bordered blocked Cholesky.  Columns [0, nf)
 // are factored; rows [nf, nrows) are border rows carried along (they end up as
 // G L^{-T}); the trailing update also maintains the Schur block of the border

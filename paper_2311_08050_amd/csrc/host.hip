@@ -106,8 +106,8 @@ Ctx::~Ctx() {
 static int g_nb() {
   static int nb = [] {
     const char *s = std::getenv("INLA_NB");
-    int v = s ? std::atoi(s) : 256;
-    if (v != 128 && v != 256 && v != 512) v = 256;
+    int v = s ? std::atoi(s) : 512;
+    if (v != 128 && v != 256 && v != 512) v = 512;
     return v;
   }();
   return nb;

@@ -28,57 +28,106 @@ namespace inla {
 enum { KIND_TRSM = 0, KIND_PANEL = 1, KIND_TRAIL = 2 };
 
 // --------------------------------------------------------------------------
-// Diagonal block: unblocked right-looking Cholesky of the 64 x 64 block in LDS,
-// then its triangular inverse by column-wise forward substitution.
+// Diagonal block: Cholesky of the 64 x 64 block A_jj and its inverse in one
+// LDS-resident pass.  The block is bordered below by the 64 x 64 identity, so
+// the same sub-panel steps that produce L_jj turn the border into
+// I L_jj^{-T} = L_jj^{-T}, whose transpose is the inverse used by the MFMA TRSM.
+// Sub-panels of width 16: an unblocked 16 x 16 Cholesky held in registers of
+// wave 0 (lane r owns row r), a forward-substitution TRSM of the rows below
+// (one thread per row), and the rank-16 update of the rest (row in registers,
+// column values broadcast from LDS).  12 barriers in all.
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__restrict__ descs, int j) {
   const FactorDesc d = descs[blockIdx.x];
   if (j >= d.nf) return;
-  __shared__ double L[NBI][NBI + 1];
-  __shared__ double X[NBI][NBI + 1];
+  constexpr int W = 16, M2 = 2 * NBI;
+  __shared__ double M[M2][NBI + 1];
   __shared__ int fail;
   const int tid = threadIdx.x;
-  double *Ad = d.A + (size_t)j * d.ld + j;
+  gdouble *Ad = gptr(d.A) + (size_t)j * d.ld + j;
   for (int e = tid; e < NBI * NBI; e += 256) {
     const int r = e & (NBI - 1), c = e >> 6;
-    L[r][c] = (r >= c) ? Ad[(size_t)c * d.ld + r] : 0.0;
+    M[r][c] = (r >= c) ? Ad[(size_t)c * d.ld + r] : 0.0;
+    M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
   }
   if (tid == 0) fail = 0;
   __syncthreads();
-  for (int c = 0; c < NBI; ++c) {
-    if (tid == 0) {
-      double v = L[c][c];
-      if (!(v > 0.0)) {
-        if (fail == 0) fail = c + 1;
-        v = __builtin_nan("");
+  for (int jb = 0; jb < NBI; jb += W) {
+    // 1. 16 x 16 diagonal Cholesky in wave 0
+    if (tid < 64) {
+      const int r = tid & (W - 1);
+      double a[W];
+#pragma unroll
+      for (int cc = 0; cc < W; ++cc) a[cc] = M[jb + r][jb + cc];
+      int bad = 0;
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double dcc = __shfl(a[c], c, 64);
+        if (!(dcc > 0.0)) {
+          if (bad == 0) bad = jb + c + 1;
+          dcc = __builtin_nan("");
+        }
+        const double sd = sqrt(dcc);
+        const double l = (r == c) ? sd : a[c] / sd;
+        a[c] = l;
+#pragma unroll
+        for (int cc = c + 1; cc < W; ++cc) a[cc] -= l * __shfl(l, cc, 64);
       }
-      L[c][c] = sqrt(v);
+      if (tid < W) {
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc)
+          if (cc <= r) M[jb + r][jb + cc] = a[cc];
+      }
+      if (tid == 0 && bad != 0 && fail == 0) fail = bad;
     }
     __syncthreads();
-    if (tid > c && tid < NBI) L[tid][c] /= L[c][c];
+    // 2. TRSM of every row below the sub-panel (block rows and border rows)
+    const int R = M2 - (jb + W);
+    if (tid < R) {
+      const int r = jb + W + tid;
+      double x[W];
+#pragma unroll
+      for (int c = 0; c < W; ++c) x[c] = M[r][jb + c];
+#pragma unroll
+      for (int c = 0; c < W; ++c) {
+        double s = x[c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s -= x[m] * M[jb + c][jb + m];
+        x[c] = s / M[jb + c][jb + c];
+      }
+#pragma unroll
+      for (int c = 0; c < W; ++c) M[r][jb + c] = x[c];
+    }
     __syncthreads();
-    for (int e = tid; e < NBI * NBI; e += 256) {
-      const int r = e & (NBI - 1), cc = e >> 6;
-      if (cc > c && r >= cc) L[r][cc] -= L[r][c] * L[cc][c];
+    // 3. rank-16 update of columns [jb + 16, 64) for the rows below
+    const int Cn = NBI - (jb + W);
+    if (Cn > 0) {
+      const int nsplit = 256 / R;
+      const int rr = tid % R, part = tid / R;
+      if (part < nsplit) {
+        const int r = jb + W + rr;
+        double p[W];
+#pragma unroll
+        for (int m = 0; m < W; ++m) p[m] = M[r][jb + m];
+        const int per = (Cn + nsplit - 1) / nsplit;
+        const int cb = jb + W + part * per;
+        const int ce = min(cb + per, NBI);
+        for (int c = cb; c < ce; ++c) {
+          if (r < NBI && c > r) break;
+          double s = M[r][c];
+#pragma unroll
+          for (int m = 0; m < W; ++m) s -= p[m] * M[c][jb + m];
+          M[r][c] = s;
+        }
+      }
     }
     __syncthreads();
   }
-  // X = L^{-1}: thread c owns column c.
-  if (tid < NBI) {
-    const int c = tid;
-    for (int r = 0; r < c; ++r) X[r][c] = 0.0;
-    X[c][c] = 1.0 / L[c][c];
-    for (int r = c + 1; r < NBI; ++r) {
-      double s = 0.0;
-      for (int m = c; m < r; ++m) s += L[r][m] * X[m][c];
-      X[r][c] = -s / L[r][r];
-    }
-  }
-  __syncthreads();
+  gdouble *Li = gptr(d.linv);
   for (int e = tid; e < NBI * NBI; e += 256) {
     const int r = e & (NBI - 1), c = e >> 6;
-    if (r >= c) Ad[(size_t)c * d.ld + r] = L[r][c];
-    d.linv[c * NBI + r] = X[r][c];
+    if (r >= c) Ad[(size_t)c * d.ld + r] = M[r][c];
+    Li[c * NBI + r] = M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
   }
   if (tid == 0 && fail != 0 && *d.info == 0) *d.info = j + fail;
 }
@@ -142,12 +191,12 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   if (kind != KIND_TRSM && col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return;
 
   const int ld = d.ld;
-  const double *Ag = d.A + (size_t)ks * ld + row0;
-  const double *Bg;
+  gcdouble *Ag = gptr((const double *)d.A) + (size_t)ks * ld + row0;
+  gcdouble *Bg;
   int ldb;
-  if (kind == KIND_TRSM) { Bg = d.linv; ldb = NBI; }
-  else { Bg = d.A + (size_t)ks * ld + col0; ldb = ld; }
-  double *Cg = d.A + (size_t)col0 * ld + row0;
+  if (kind == KIND_TRSM) { Bg = gptr((const double *)d.linv); ldb = NBI; }
+  else { Bg = gptr((const double *)d.A) + (size_t)ks * ld + col0; ldb = ld; }
+  gdouble *Cg = gptr(d.A) + (size_t)col0 * ld + row0;
   const int K = ke - ks;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -165,12 +214,12 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 #pragma unroll
     for (int it = 0; it < LA; ++it) {
       const int lin = it * 256 + tid, kk = lin / (TM / 2), rp = lin % (TM / 2);
-      ra[it] = *reinterpret_cast<const d2 *>(Ag + (size_t)(kc + kk) * ld + 2 * rp);
+      ra[it] = *reinterpret_cast<gcd2 *>(Ag + (size_t)(kc + kk) * ld + 2 * rp);
     }
 #pragma unroll
     for (int it = 0; it < LB; ++it) {
       const int lin = it * 256 + tid, kk = lin / (TN / 2), rp = lin % (TN / 2);
-      rb[it] = *reinterpret_cast<const d2 *>(Bg + (size_t)(kc + kk) * ldb + 2 * rp);
+      rb[it] = *reinterpret_cast<gcd2 *>(Bg + (size_t)(kc + kk) * ldb + 2 * rp);
     }
   };
   auto lstore = [&](int buf) {
@@ -213,21 +262,43 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 
   // Epilogue.  Lane holds C(row = rb + li, col = cb + g + 4 v).
   const bool diag_tile = (kind != KIND_TRSM) && (row0 < col0 + TN);
-  const bool sub = kind != KIND_TRSM;
+  if (kind == KIND_TRSM) {
 #pragma unroll
-  for (int a = 0; a < BM; ++a) {
+    for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      const int rl = wm * WTM + a * 16 + li;
-      const int cl = wn * WTN + b * 16 + g;
+      for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int cc = cl + 4 * v;
-        if (diag_tile && row0 + rl < col0 + cc) continue;
-        double *p = Cg + (size_t)cc * ld + rl;
-        *p = sub ? (*p - acc[a][b][v]) : acc[a][b][v];
-      }
+        for (int v = 0; v < 4; ++v)
+          Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li] = acc[a][b][v];
+  } else if (!diag_tile) {
+#pragma unroll
+    for (int a = 0; a < BM; ++a) {
+      double cv[BN][4];
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          cv[b][v] = Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li] = cv[b][v] - acc[a][b][v];
     }
+  } else {
+    // diagonal tile: only the lower triangle (row >= col) is touched
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int rl = wm * WTM + a * 16 + li, cc = wn * WTN + b * 16 + g + 4 * v;
+          if (row0 + rl >= col0 + cc) {
+            gdouble *p = Cg + (size_t)cc * ld + rl;
+            *p = *p - acc[a][b][v];
+          }
+        }
   }
 }
 
@@ -316,7 +387,7 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
           }
         }
         if (gx == 0) continue;
-        ctx.launch(INLA_K_GEMM, fl, by, [&] {
+        ctx.launch(INLA_K_PANEL, fl, by, [&] {
           hipLaunchKernelGGL((gemm_update_kernel<64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0, nb, j);
         });
       }
@@ -336,7 +407,7 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
       }
     }
     if (gx > 0)
-      ctx.launch(INLA_K_GEMM, fl, by, [&] {
+      ctx.launch(INLA_K_TRAIL, fl, by, [&] {
         hipLaunchKernelGGL((gemm_update_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, KIND_TRAIL, p0,
                            nb, p0);
       });
