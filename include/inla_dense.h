@@ -70,7 +70,14 @@ enum {
                                      R_t the unscaled first-order random walk on n_t
                                      steps, latent index t*n_s + s */
 };
-enum { INLA_PREC_FP64 = 0 };
+/* Precision of the Newton and final-pass factorisations.  FP64: everything in
+ * FP64.  FP32: FP32 storage and FP32 MFMA (FP32 accumulate) for the blocked
+ * Cholesky of Q*; the prior pass, the log-det sums, the k x k kriging system and
+ * the residuals stay FP64, and every Newton solve is refined on the constrained
+ * (KKT) system with FP64 residuals until the correction is below 1e-13
+ * relative; a theta whose refinement does not converge within its budget is
+ * re-evaluated in FP64 and flagged in inla_result.fallback. */
+enum { INLA_PREC_FP64 = 0, INLA_PREC_FP32 = 1 };
 
 typedef struct inla_handle inla_handle;
 
@@ -97,7 +104,7 @@ typedef struct inla_model {
  * "Gaussian Approximation"; the paper leaves norm and tolerance open, here
  * ||x_new - x||_inf <= tol * max(1, ||x_new||_inf)). */
 typedef struct inla_opts {
-  int32_t prec;      /* INLA_PREC_FP64                                               */
+  int32_t prec;      /* INLA_PREC_FP64 or INLA_PREC_FP32                             */
   int32_t max_iter;  /* <= 0: 50                                                     */
   double tol;        /* <= 0: 1e-11                                                  */
   int32_t start;     /* 0: start from x = 0; 1: start from the vectors in x_inout    */
@@ -117,6 +124,8 @@ typedef struct inla_result {
   double step;          /* last Newton step ||x_new - x||_inf                        */
   int32_t iters;        /* Newton iterations taken                                   */
   int32_t info;         /* INLA_INFO_* or leading-minor index                        */
+  int32_t ir_steps;     /* mixed precision: refinement steps summed over iterations  */
+  int32_t fallback;     /* 1 if the theta was re-evaluated in FP64                    */
 } inla_result;
 
 /* ------------------------------------------------------------ lifecycle */

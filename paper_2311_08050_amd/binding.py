@@ -16,6 +16,7 @@ LIBPATH = os.path.join(HERE, "libinla_dense.so")
 
 LIK = {"gaussian": 0, "poisson": 1}
 PRIOR = {"dense": 0, "expcov": 1, "kron": 2}
+PREC = {"fp64": 0, "fp32": 1}
 N_PRIOR_PARAMS = {"dense": 0, "expcov": 2, "kron": 3}
 
 INFO_OK = 0
@@ -52,6 +53,7 @@ class Result(C.Structure):
         ("objective", C.c_double), ("logdet_qprior", C.c_double), ("logdet_sprior", C.c_double),
         ("ese", C.c_double), ("xqx", C.c_double), ("loglik", C.c_double), ("logdet_qstar", C.c_double),
         ("logdet_s", C.c_double), ("step", C.c_double), ("iters", C.c_int32), ("info", C.c_int32),
+        ("ir_steps", C.c_int32), ("fallback", C.c_int32),
     ]
 
     def asdict(self):
@@ -177,21 +179,21 @@ class Library:
         ptrs = (C.c_void_p * B)(*[t.data_ptr() for t in x])
         return B, theta, models, x, ptrs
 
-    def _run(self, fn, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
+    def _run(self, fn, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0, prec="fp64"):
         B, theta, models, x, ptrs = self._common(dmodels, theta, x)
-        opts = Opts(prec=0, max_iter=max_iter, tol=tol, start=start, reserved=0)
+        opts = Opts(prec=PREC[prec], max_iter=max_iter, tol=tol, start=start, reserved=0)
         res = (Result * B)()
         rc = fn(self.h, B, models, theta.ctypes.data_as(C.POINTER(C.c_double)), theta.shape[1], ptrs,
                 C.byref(opts), res)
         self._check(rc, fn.__name__)
         return [r.asdict() for r in res], x
 
-    def laplace_eval(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
+    def laplace_eval(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0, prec="fp64"):
         """(results, modes): per-theta dicts of inla_result fields and device modes."""
-        return self._run(self.lib.inla_laplace_eval, dmodels, theta, x, start, max_iter, tol)
+        return self._run(self.lib.inla_laplace_eval, dmodels, theta, x, start, max_iter, tol, prec)
 
-    def constrained_mode(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0):
-        return self._run(self.lib.inla_constrained_mode, dmodels, theta, x, start, max_iter, tol)
+    def constrained_mode(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0, prec="fp64"):
+        return self._run(self.lib.inla_constrained_mode, dmodels, theta, x, start, max_iter, tol, prec)
 
     def marginal_var(self, dmodels, theta, x_modes):
         B, theta, models, x_modes, xptrs = self._common(dmodels, theta, x_modes)

@@ -29,8 +29,8 @@ template <typename T> __device__ __forceinline__ __attribute__((address_space(1)
 // G L^{-T}); the trailing update also maintains the Schur block of the border
 // for columns [nf, ncols).  Column-major, leading dimension ld >= nrows.
 struct FactorDesc {
-  double *A;
-  double *linv;    // NBI x NBI scratch: inverse of the current diagonal block (col-major)
+  void *A;         // double or float elements (the factorisation's storage type)
+  void *linv;      // NBI x NBI scratch: inverse of the current diagonal block (col-major)
   int *info;       // first failing pivot (1-based), 0 if none
   int ld;
   int nf;          // columns to factor (multiple of PADN)
@@ -54,12 +54,16 @@ struct ThetaDesc {
   double tau, rho, delta, lpar;   // prior parameters; lpar = sigma^2 or beta0
   // workspace (owned by the library)
   double *Qp; int ldqp;           // prior precision, n_pad x n_pad, lower, identity padded
-  double *W; int ldw; int Nw; int Ncw;  // big working matrix: Nw rows, Ncw columns written
+  void *W; int ldw; int Nw; int Ncw;    // big working matrix (double or float): Nw rows, Ncw columns
   double *S; int lds; int Ns; int k_pad;   // small (kriging) system working matrix
   double *P; int ldp; int Np; int ns_pad;  // prior-build working matrix
-  double *x;       // current iterate [n_pad]
+  double *x;       // current iterate / linearisation point [n_pad]
   double *r;       // right-hand side / new iterate [n_pad]
+  double *xn;      // refined new iterate [n_pad] (mixed precision)
+  double *z;       // residual / forward-solve vector [n_pad] (mixed precision)
   double *lam;     // [k_pad] kriging multipliers
+  double *dlam;    // [k_pad] multiplier correction (mixed precision)
+  double *rtwo;    // [k_pad] constraint residual e - C x (mixed precision)
   double *part;    // [2 * ldw] per-column partial sums (loglik, x'Qx)
   double *dres;    // [16] per-theta device results (see DRES_*)
   double *out;     // caller's output vector (mode or variances), device
@@ -76,6 +80,8 @@ enum {
   DRES_LOGLIK = 6,
   DRES_NONFINITE = 7,  // 1 if a non-finite value was met
   DRES_RANK = 8,       // 1 if the kriging system is numerically singular
+  DRES_IR_DX = 9,      // last refinement correction ||dx||_inf
+  DRES_IR_X = 10,      // max(1, ||x||_inf) of the refined iterate
   DRES_COUNT = 16
 };
 

@@ -182,7 +182,7 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
   off += align256(std::max(wbytes, pbytes));
   p.off_S = off; off += align256(sizeof(double) * (size_t)t.lds * std::max(t.k_pad, 1));
   p.off_vec = off;
-  off += align256(sizeof(double) * (size_t)(2 * t.n_pad + std::max(t.k_pad, 64) + 2 * t.ldw + DRES_COUNT));
+  off += align256(sizeof(double) * (size_t)(4 * t.n_pad + 3 * std::max(t.k_pad, 64) + 2 * t.ldw + DRES_COUNT));
   p.off_linv = off; off += align256(sizeof(double) * NBI * NBI);
   p.bytes = off;
   return p;
@@ -191,13 +191,17 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
 static void bind(Plan &p, char *base) {
   ThetaDesc &t = p.t;
   t.Qp = (double *)(base + p.off_Qp);
-  t.W = (double *)(base + p.off_W);
-  t.P = t.W;   // the prior build finishes before the working matrix is assembled
+  t.W = (void *)(base + p.off_W);
+  t.P = (double *)t.W;   // the prior build finishes before the working matrix is assembled
   t.S = (double *)(base + p.off_S);
   double *v = (double *)(base + p.off_vec);
   t.x = v; v += t.n_pad;
   t.r = v; v += t.n_pad;
+  t.xn = v; v += t.n_pad;
+  t.z = v; v += t.n_pad;
   t.lam = v; v += std::max(t.k_pad, 64);
+  t.dlam = v; v += std::max(t.k_pad, 64);
+  t.rtwo = v; v += std::max(t.k_pad, 64);
   t.part = v; v += 2 * t.ldw;
   t.dres = v;
 }
@@ -217,14 +221,14 @@ struct Batch {
 
 // HostFactor for one of the three matrices of a theta.
 enum { F_PRIOR = 0, F_BIG = 1, F_SMALL = 2 };
-static HostFactor factor_of(const Plan &p, int which, int *info, double *linv, Mode mode) {
+static HostFactor factor_of(const Plan &p, int which, int *info, void *linv, Mode mode) {
   const ThetaDesc &t = p.t;
   HostFactor h{};
   h.d.info = info;
   h.d.linv = linv;
   h.d.id_row0 = std::numeric_limits<int>::max();
   if (which == F_PRIOR) {
-    h.d.A = t.P; h.d.ld = t.ldp; h.d.nf = t.ns_pad; h.d.nrows = t.Np; h.d.ncols = t.Np; h.d.id_row0 = t.ns_pad;
+    h.d.A = (void *)t.P; h.d.ld = t.ldp; h.d.nf = t.ns_pad; h.d.nrows = t.Np; h.d.ncols = t.Np; h.d.id_row0 = t.ns_pad;
     h.n_real = p.ns_real; h.kb_real = p.ns_real; h.ks_real = p.ns_real;
   } else if (which == F_BIG) {
     h.d.A = t.W; h.d.ld = t.ldw; h.d.nf = t.n_pad; h.d.nrows = t.Nw; h.d.ncols = t.Ncw;
@@ -255,14 +259,14 @@ static ThetaDesc *upload_td(Batch &b, const std::vector<int> &ids) {
   return (ThetaDesc *)b.ctx.upload(v.data(), sizeof(ThetaDesc) * v.size());
 }
 
-static int run_factor(Batch &b, const std::vector<int> &ids, int which, Mode mode) {
+static int run_factor(Batch &b, const std::vector<int> &ids, int which, Mode mode, int prec = INLA_PREC_FP64) {
   std::vector<HostFactor> fs;
   for (int i : ids) {
     const Plan &p = b.plans[i];
-    HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (double *)(b.bases[i] + p.off_linv), mode);
+    HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (void *)(b.bases[i] + p.off_linv), mode);
     if (h.d.nf > 0) fs.push_back(h);
   }
-  return factor_batch(b.ctx, fs, g_nb());
+  return factor_batch(b.ctx, fs, g_nb(), prec);
 }
 
 // Read back dres and info of every theta (one synchronisation).
@@ -312,30 +316,68 @@ static int prior_build(Batch &b, const std::vector<int> &ids) {
 // factor the kriging system, solve it; then (Newton) form the corrected
 // right-hand side and back-substitute, or (prior / final) reduce the log-dets.
 enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2 };
-static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass) {
+static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) {
   if (ids.empty()) return 0;
   ThetaDesc *d = upload_td(b, ids);
   if (!d) return INLA_ERR_NOMEM;
   const int B = (int)ids.size();
+  const double esz = prec == INLA_PREC_FP32 ? 4.0 : 8.0;
   double abytes = 0, tbytes = 0;
   for (int i : ids) {
     const ThetaDesc &t = b.plans[i].t;
-    abytes += 8.0 * (0.5 * t.n * (t.n + 1.0)) * 2.0 + 8.0 * (double)t.n * (t.k + 1);
-    tbytes += 8.0 * 0.5 * t.n * (t.n + 1.0);
+    abytes += (8.0 + esz) * (0.5 * t.n * (t.n + 1.0)) + esz * (double)t.n * (t.k + 1);
+    tbytes += esz * 0.5 * t.n * (t.n + 1.0);
   }
   launch_assemble(b.ctx, d, B, max_over(b, ids, &ThetaDesc::Ncw), pass != PASS_PRIOR, pass == PASS_FINAL, BORDER_CB,
-                  abytes);
+                  abytes, prec);
   int rc;
-  if ((rc = run_factor(b, ids, F_BIG, MODE_LAPLACE))) return rc;
-  launch_kriging_build(b.ctx, d, B, max_over(b, ids, &ThetaDesc::k_pad));
+  if ((rc = run_factor(b, ids, F_BIG, MODE_LAPLACE, prec))) return rc;
+  launch_kriging_build(b.ctx, d, B, max_over(b, ids, &ThetaDesc::k_pad), prec);
   if ((rc = run_factor(b, ids, F_SMALL, MODE_LAPLACE))) return rc;
   launch_kriging_solve(b.ctx, d, B);
   if (pass == PASS_NEWTON) {
-    launch_rhs(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad));
-    launch_trsv(b.ctx, d, B, tbytes);
+    launch_rhs(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad), 0, prec);
+    launch_trsv(b.ctx, d, B, tbytes, prec != INLA_PREC_FP64, prec);
   } else {
-    launch_finish(b.ctx, d, B);
+    launch_finish(b.ctx, d, B, prec);
   }
+  return b.ctx.check();
+}
+
+// Mixed precision: refine the constrained Newton solve of every theta in `ids`
+// on the KKT system with FP64 residuals, using the low-precision factor.
+// Returns the thetas whose refinement did not reach ||dx|| <= tol_ir * max(1, ||x||).
+static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, double tol_ir, std::vector<int> &failed,
+                  std::vector<int> &steps) {
+  std::vector<int> act = ids;
+  const double esz = prec == INLA_PREC_FP32 ? 4.0 : 8.0;
+  for (int s = 1; s <= max_ir && !act.empty(); ++s) {
+    ThetaDesc *d = upload_td(b, act);
+    if (!d) return INLA_ERR_NOMEM;
+    const int B = (int)act.size();
+    double rb = 0, tb = 0;
+    for (int i : act) {
+      const ThetaDesc &t = b.plans[i].t;
+      rb += 8.0 * (double)t.n * t.n;
+      tb += esz * (double)t.n * t.n;
+    }
+    launch_kkt_residual(b.ctx, d, B, max_over(b, act, &ThetaDesc::n_pad), max_over(b, act, &ThetaDesc::k_pad), rb);
+    launch_kkt_small(b.ctx, d, B, 0.5 * tb, prec);
+    launch_rhs(b.ctx, d, B, max_over(b, act, &ThetaDesc::n_pad), 1, prec);
+    launch_ir_update(b.ctx, d, B, 0.5 * tb, prec);
+    for (int i : act) steps[i] += 1;
+    if (s % 2 == 0 || s == max_ir) {
+      int rc;
+      if ((rc = readback(b))) return rc;
+      std::vector<int> next;
+      for (int i : act) {
+        const double *dr = &b.hdres[DRES_COUNT * i];
+        if (!(dr[DRES_IR_DX] <= tol_ir * dr[DRES_IR_X])) next.push_back(i);
+      }
+      act.swap(next);
+    }
+  }
+  failed = act;
   return b.ctx.check();
 }
 
@@ -419,7 +461,10 @@ static std::vector<std::pair<int, int>> chunks(Ctx &ctx, int B, const inla_model
   return out;
 }
 
-// The whole per-theta evaluation for one chunk.
+// The whole per-theta evaluation for one chunk.  `prec` selects the precision
+// of the Newton and final-pass factorisations (the prior pass is always FP64).
+// A theta whose mixed-precision refinement does not converge is re-evaluated
+// in FP64 and flagged.
 static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta, double *const *x,
                       const inla_opts *opts, inla_result *res, bool laplace) {
   Batch b(ctx);
@@ -428,6 +473,10 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 50;
   const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-11;
   const bool warm = opts && opts->start == 1;
+  const int prec = opts ? opts->prec : INLA_PREC_FP64;
+  const bool mixed = prec != INLA_PREC_FP64;
+  const int max_ir = 10;
+  const double tol_ir = 1e-13;
   std::vector<int> all, ok;
   for (int i = 0; i < B; ++i) {
     res[i] = inla_result{};
@@ -442,10 +491,14 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     } else if (hipMemsetAsync(t.x, 0, sizeof(double) * t.n_pad, ctx.stream) != hipSuccess) {
       teardown(b); return INLA_ERR_HIP;
     }
+    if (mixed && (hipMemsetAsync(t.lam, 0, sizeof(double) * std::max(t.k_pad, 64), ctx.stream) != hipSuccess ||
+                  hipMemsetAsync(t.xn, 0, sizeof(double) * t.n_pad, ctx.stream) != hipSuccess)) {
+      teardown(b); return INLA_ERR_HIP;
+    }
   }
   auto fail = [&](int r) { teardown(b); return r; };
   if ((rc = prior_build(b, all))) return fail(rc);
-  if ((rc = run_pass(b, all, PASS_PRIOR))) return fail(rc);
+  if ((rc = run_pass(b, all, PASS_PRIOR, INLA_PREC_FP64))) return fail(rc);
   if ((rc = readback(b))) return fail(rc);
   for (int i : all) {
     const int *inf = &b.hinfo[4 * i];
@@ -460,11 +513,23 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   }
   // Newton iteration (warm-start vectors were checked for finiteness by the
   // first assembly: a non-finite W or b sets the flag).
-  std::vector<int> active = ok, done;
+  std::vector<int> active = ok, done, redo;
   std::vector<char> failed(B, 0);
+  std::vector<int> irsteps(B, 0);
   for (int it = 1; it <= max_iter && !active.empty(); ++it) {
     if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
-    if ((rc = run_pass(b, active, PASS_NEWTON))) return fail(rc);
+    if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
+    if (mixed) {
+      std::vector<int> nconv;
+      if ((rc = refine(b, active, prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
+      for (int i : nconv) { failed[i] = 1; redo.push_back(i); }
+      std::vector<int> keep;
+      for (int i : active) if (!failed[i]) keep.push_back(i);
+      active.swap(keep);
+      ThetaDesc *d = upload_td(b, active);
+      if (!active.empty() && !d) return fail(INLA_ERR_NOMEM);
+      launch_newton_accept(ctx, d, (int)active.size());
+    }
     if ((rc = readback(b))) return fail(rc);
     std::vector<int> next;
     for (int i : active) {
@@ -492,7 +557,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     std::vector<int> fin;
     for (int i : done) if (!failed[i]) fin.push_back(i);
     if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
-    if ((rc = run_pass(b, fin, PASS_FINAL))) return fail(rc);
+    if ((rc = run_pass(b, fin, PASS_FINAL, prec))) return fail(rc);
     if ((rc = readback(b))) return fail(rc);
     for (int i : fin) {
       const int *inf = &b.hinfo[4 * i];
@@ -510,9 +575,33 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   } else {
     if (hipStreamSynchronize(ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
   }
+  for (int i = 0; i < B; ++i) res[i].ir_steps = irsteps[i];
   ctx.harvest();
   teardown(b);
-  return ctx.check();
+  if ((rc = ctx.check())) return rc;
+  // FP64 re-evaluation of thetas whose refinement did not converge
+  if (!redo.empty()) {
+    std::vector<inla_model> m2;
+    std::vector<double> th2;
+    std::vector<double *> x2;
+    for (int i : redo) {
+      m2.push_back(models[i]);
+      th2.insert(th2.end(), theta + (size_t)i * ldtheta, theta + (size_t)(i + 1) * ldtheta);
+      x2.push_back(x[i]);
+    }
+    inla_opts o2 = opts ? *opts : inla_opts{};
+    o2.prec = INLA_PREC_FP64;
+    std::vector<inla_result> r2(redo.size());
+    rc = eval_chunk(ctx, (int)redo.size(), m2.data(), th2.data(), ldtheta, x2.data(), &o2, r2.data(), laplace);
+    if (rc) return rc;
+    for (size_t q = 0; q < redo.size(); ++q) {
+      const int st = res[redo[q]].ir_steps;
+      res[redo[q]] = r2[q];
+      res[redo[q]].fallback = 1;
+      res[redo[q]].ir_steps = st;
+    }
+  }
+  return INLA_OK;
 }
 
 static int var_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
@@ -533,7 +622,7 @@ static int var_chunk(Ctx &ctx, int B, const inla_model *models, const double *th
   if ((rc = prior_build(b, all))) return fail(rc);
   ThetaDesc *d = upload_td(b, all);
   if (!d) return fail(INLA_ERR_NOMEM);
-  launch_assemble(ctx, d, B, max_over(b, all, &ThetaDesc::Ncw), 1, 0, BORDER_CI, 0.0);
+  launch_assemble(ctx, d, B, max_over(b, all, &ThetaDesc::Ncw), 1, 0, BORDER_CI, 0.0, INLA_PREC_FP64);
   if ((rc = run_factor(b, all, F_BIG, MODE_VAR))) return fail(rc);
   launch_var_small_build(ctx, d, B, max_over(b, all, &ThetaDesc::k_pad));
   if ((rc = run_factor(b, all, F_SMALL, MODE_VAR))) return fail(rc);
@@ -648,7 +737,7 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
       Plan &p = b.plans[i];
       b.bases[i] = ctx.ws + offs[i];
       ThetaDesc &t = p.t;
-      t.W = (double *)(b.bases[i] + p.off_W);
+      t.W = (void *)(b.bases[i] + p.off_W);
       double *v = (double *)(b.bases[i] + p.off_vec);
       t.x = v; v += t.n_pad; t.r = v; v += t.n_pad; t.lam = v; v += 64; t.part = v; v += 2 * t.ldw; t.dres = v;
       t.Qp = nullptr; t.S = nullptr; t.P = nullptr;
@@ -665,7 +754,7 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
       if (!d) { teardown(b); return INLA_ERR_NOMEM; }
       launch_copy_in(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n_pad));
       if ((rc = run_factor(b, ids2, F_BIG, MODE_LOGDET))) { teardown(b); return rc; }
-      launch_finish(ctx, d, (int)ids2.size());
+      launch_finish(ctx, d, (int)ids2.size(), INLA_PREC_FP64);
       launch_copy_out(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n));
     }
     if ((rc = readback(b))) { teardown(b); return rc; }
@@ -688,7 +777,7 @@ static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, con
   if (B == 0) return INLA_OK;
   if (!x) return -6;
   for (int i = 0; i < B; ++i) if (!x[i]) return -6;
-  if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
+  if (opts && opts->prec != INLA_PREC_FP64 && opts->prec != INLA_PREC_FP32) return INLA_ERR_UNSUPPORTED;
   for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
     rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
                     x + c.first, opts, res + c.first, laplace);

@@ -53,7 +53,7 @@ struct Ctx {
 };
 
 // Library entry points implemented in other translation units.
-int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb);
+int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec);
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 

@@ -13,13 +13,17 @@
 // factorisation's own MFMA updates.
 //
 // Steps per inner block j (width NBI = 64) of an outer panel [p0, p0 + nb):
-//   potf2_inv  : L_jj = chol(A_jj) in LDS and X = L_jj^{-1} (one workgroup per theta)
+//   potf2_inv  : L_jj = chol(A_jj) and X = L_jj^{-1} in FP64 in LDS (one workgroup per theta)
 //   TRSM       : A[j+64:, j:j+64] <- A[j+64:, j:j+64] X^T     (MFMA, in place)
 //   PANEL      : A[j+64:, j+64:pend] -= A[j+64:, j:j+64] A[j+64:pend, j:j+64]^T
 // and per outer panel
 //   TRAIL      : A[pend:, pend:ncols] -= A[pend:, p0:pend] A[pend:ncols, p0:pend]^T
-// All updates are FP64 MFMA (v_mfma_f64_16x16x4f64) tile kernels with LDS-staged,
-// double-buffered K chunks.
+//
+// Storage and MFMA precision are template parameters: FP64 storage with
+// v_mfma_f64_16x16x4f64, or FP32 storage with v_mfma_f32_16x16x4f32 (FP32
+// accumulate).  Operands are LDS-staged in double-buffered K chunks.
+#include <type_traits>
+
 #include "device.hpp"
 #include "host.hpp"
 
@@ -27,16 +31,19 @@ namespace inla {
 
 enum { KIND_TRSM = 0, KIND_PANEL = 1, KIND_TRAIL = 2 };
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
 // --------------------------------------------------------------------------
 // Diagonal block: Cholesky of the 64 x 64 block A_jj and its inverse in one
-// LDS-resident pass.  The block is bordered below by the 64 x 64 identity, so
-// the same sub-panel steps that produce L_jj turn the border into
+// LDS-resident FP64 pass.  The block is bordered below by the 64 x 64 identity,
+// so the same sub-panel steps that produce L_jj turn the border into
 // I L_jj^{-T} = L_jj^{-T}, whose transpose is the inverse used by the MFMA TRSM.
 // Sub-panels of width 16: an unblocked 16 x 16 Cholesky held in registers of
 // wave 0 (lane r owns row r), a forward-substitution TRSM of the rows below
 // (one thread per row), and the rank-16 update of the rest (row in registers,
 // column values broadcast from LDS).  12 barriers in all.
 // --------------------------------------------------------------------------
+template <typename T>
 __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__restrict__ descs, int j) {
   const FactorDesc d = descs[blockIdx.x];
   if (j >= d.nf) return;
@@ -44,10 +51,10 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
   __shared__ double M[M2][NBI + 1];
   __shared__ int fail;
   const int tid = threadIdx.x;
-  gdouble *Ad = gptr(d.A) + (size_t)j * d.ld + j;
+  __attribute__((address_space(1))) T *Ad = gptr((T *)d.A) + (size_t)j * d.ld + j;
   for (int e = tid; e < NBI * NBI; e += 256) {
     const int r = e & (NBI - 1), c = e >> 6;
-    M[r][c] = (r >= c) ? Ad[(size_t)c * d.ld + r] : 0.0;
+    M[r][c] = (r >= c) ? (double)Ad[(size_t)c * d.ld + r] : 0.0;
     M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
   }
   if (tid == 0) fail = 0;
@@ -123,11 +130,11 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
     }
     __syncthreads();
   }
-  gdouble *Li = gptr(d.linv);
+  __attribute__((address_space(1))) T *Li = gptr((T *)d.linv);
   for (int e = tid; e < NBI * NBI; e += 256) {
     const int r = e & (NBI - 1), c = e >> 6;
-    if (r >= c) Ad[(size_t)c * d.ld + r] = M[r][c];
-    Li[c * NBI + r] = M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
+    if (r >= c) Ad[(size_t)c * d.ld + r] = (T)M[r][c];
+    Li[c * NBI + r] = (T)M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
   }
   if (tid == 0 && fail != 0 && *d.info == 0) *d.info = j + fail;
 }
@@ -136,22 +143,35 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
 // MFMA tile update.  C(TM x TN) = or -= A(TM x K) B(TN x K)^T, A and B read from
 // column-major storage (element (r, k) at base[k*ld + r]).
 //
-// MFMA operands are swapped (x from B, y from A) so that lane l's four results
-// are C rows (l % 16) of columns (l / 16 + 4 v): with the f64 16x16x4 output
-// layout (D row = l/16 + 4v, D column = l%16) every store covers four whole
-// 128-byte column segments.  Lane group g = l/16 supplies k = 4g + s at
-// MFMA step s of a 16-deep chunk.
+// FP64: v_mfma_f64_16x16x4f64 puts D row (l/16 + 4v), column (l%16) in lane l;
+// the operands are swapped (x from B, y from A) so that a lane's four results
+// are C row (l%16) of columns (l/16 + 4v) and every store covers four whole
+// 128-byte column segments.
+// FP32: v_mfma_f32_16x16x4f32 puts D rows (4(l/16) + v), column (l%16) in lane
+// l; operands are not swapped, so a lane's four results are four consecutive
+// rows of one column.
+// Lane group g = l/16 supplies k = 4g + s at MFMA step s of each 16-deep
+// sub-chunk.  LDS rows are padded by 4 elements so that each read is free of
+// bank conflicts.
 // --------------------------------------------------------------------------
-template <int TM, int TN>
+template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
                                                              int p0, int nb, int j) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int KCH = F64 ? 16 : 32;            // K chunk staged per LDS buffer
+  constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte global load
   constexpr int WM = 2, WN = 2;                 // 2 x 2 waves
   constexpr int WTM = TM / WM, WTN = TN / WN;   // wave tile
   constexpr int BM = WTM / 16, BN = WTN / 16;   // MFMA blocks per wave
   constexpr int PAD = 4;
-  constexpr int LA = TM / 32, LB = TN / 32;     // double2 loads per thread per chunk
-  __shared__ __attribute__((aligned(16))) double As[2][KC][TM + PAD];
-  __shared__ __attribute__((aligned(16))) double Bs[2][KC][TN + PAD];
+  constexpr int LA = KCH * TM / VEC / 256, LB = KCH * TN / VEC / 256;
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  typedef __attribute__((address_space(1))) T gT;
+  typedef __attribute__((address_space(1))) const T gcT;
+  typedef __attribute__((address_space(1))) const vec_t gcvec;
+  typedef typename std::conditional<F64, d4, f4>::type acc_t;
+  __shared__ __attribute__((aligned(16))) T As[2][KCH][TM + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[2][KCH][TN + PAD];
 
   const FactorDesc d = descs[blockIdx.y];
   if (j >= d.nf) return;
@@ -191,47 +211,47 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   if (kind != KIND_TRSM && col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return;
 
   const int ld = d.ld;
-  gcdouble *Ag = gptr((const double *)d.A) + (size_t)ks * ld + row0;
-  gcdouble *Bg;
+  gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
+  gcT *Bg;
   int ldb;
-  if (kind == KIND_TRSM) { Bg = gptr((const double *)d.linv); ldb = NBI; }
-  else { Bg = gptr((const double *)d.A) + (size_t)ks * ld + col0; ldb = ld; }
-  gdouble *Cg = gptr(d.A) + (size_t)col0 * ld + row0;
+  if (kind == KIND_TRSM) { Bg = gptr((const T *)d.linv); ldb = NBI; }
+  else { Bg = gptr((const T *)d.A) + (size_t)ks * ld + col0; ldb = ld; }
+  gT *Cg = gptr((T *)d.A) + (size_t)col0 * ld + row0;
   const int K = ke - ks;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WN, wn = w % WN;
   const int g = lane >> 4, li = lane & 15;
 
-  d4 acc[BM][BN];
+  acc_t acc[BM][BN];
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < BN; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < BN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-  d2 ra[LA], rb[LB];
+  vec_t ra[LA], rb[LB];
   auto gload = [&](int kc) {
 #pragma unroll
     for (int it = 0; it < LA; ++it) {
-      const int lin = it * 256 + tid, kk = lin / (TM / 2), rp = lin % (TM / 2);
-      ra[it] = *reinterpret_cast<gcd2 *>(Ag + (size_t)(kc + kk) * ld + 2 * rp);
+      const int lin = it * 256 + tid, kk = lin / (TM / VEC), rp = lin % (TM / VEC);
+      ra[it] = *reinterpret_cast<gcvec *>(Ag + (size_t)(kc + kk) * ld + VEC * rp);
     }
 #pragma unroll
     for (int it = 0; it < LB; ++it) {
-      const int lin = it * 256 + tid, kk = lin / (TN / 2), rp = lin % (TN / 2);
-      rb[it] = *reinterpret_cast<gcd2 *>(Bg + (size_t)(kc + kk) * ldb + 2 * rp);
+      const int lin = it * 256 + tid, kk = lin / (TN / VEC), rp = lin % (TN / VEC);
+      rb[it] = *reinterpret_cast<gcvec *>(Bg + (size_t)(kc + kk) * ldb + VEC * rp);
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
     for (int it = 0; it < LA; ++it) {
-      const int lin = it * 256 + tid, kk = lin / (TM / 2), rp = lin % (TM / 2);
-      *reinterpret_cast<d2 *>(&As[buf][kk][2 * rp]) = ra[it];
+      const int lin = it * 256 + tid, kk = lin / (TM / VEC), rp = lin % (TM / VEC);
+      *reinterpret_cast<vec_t *>(&As[buf][kk][VEC * rp]) = ra[it];
     }
 #pragma unroll
     for (int it = 0; it < LB; ++it) {
-      const int lin = it * 256 + tid, kk = lin / (TN / 2), rp = lin % (TN / 2);
-      *reinterpret_cast<d2 *>(&Bs[buf][kk][2 * rp]) = rb[it];
+      const int lin = it * 256 + tid, kk = lin / (TN / VEC), rp = lin % (TN / VEC);
+      *reinterpret_cast<vec_t *>(&Bs[buf][kk][VEC * rp]) = rb[it];
     }
   };
 
@@ -239,13 +259,13 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   lstore(0);
   __syncthreads();
   int buf = 0;
-  for (int kc = 0; kc < K; kc += KC) {
-    const bool more = kc + KC < K;
-    if (more) gload(kc + KC);
+  for (int kc = 0; kc < K; kc += KCH) {
+    const bool more = kc + KCH < K;
+    if (more) gload(kc + KCH);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = 4 * g + s;
-      double ya[BM], xb[BN];
+    for (int s = 0; s < KCH / 4; ++s) {
+      const int kk = 16 * (s >> 2) + 4 * g + (s & 3);
+      T ya[BM], xb[BN];
 #pragma unroll
       for (int a = 0; a < BM; ++a) ya[a] = As[buf][kk][wm * WTM + a * 16 + li];
 #pragma unroll
@@ -253,14 +273,19 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 #pragma unroll
       for (int a = 0; a < BM; ++a)
 #pragma unroll
-        for (int b = 0; b < BN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < BN; ++b) {
+          if constexpr (F64) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
+          else acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[a], xb[b], acc[a][b], 0, 0, 0);
+        }
     }
     if (more) lstore(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
 
-  // Epilogue.  Lane holds C(row = rb + li, col = cb + g + 4 v).
+  // Epilogue: tile element (rl(a, v), cl(b, v)) for accumulator component v.
+  auto rl = [&](int a, int v) { return wm * WTM + a * 16 + (F64 ? li : 4 * g + v); };
+  auto cl = [&](int b, int v) { return wn * WTN + b * 16 + (F64 ? g + 4 * v : li); };
   const bool diag_tile = (kind != KIND_TRSM) && (row0 < col0 + TN);
   if (kind == KIND_TRSM) {
 #pragma unroll
@@ -268,22 +293,19 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 #pragma unroll
       for (int b = 0; b < BN; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li] = acc[a][b][v];
+        for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = acc[a][b][v];
   } else if (!diag_tile) {
 #pragma unroll
     for (int a = 0; a < BM; ++a) {
-      double cv[BN][4];
+      T cv[BN][4];
 #pragma unroll
       for (int b = 0; b < BN; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          cv[b][v] = Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li];
+        for (int v = 0; v < 4; ++v) cv[b][v] = Cg[(size_t)cl(b, v) * ld + rl(a, v)];
 #pragma unroll
       for (int b = 0; b < BN; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          Cg[(size_t)(wn * WTN + b * 16 + g + 4 * v) * ld + wm * WTM + a * 16 + li] = cv[b][v] - acc[a][b][v];
+        for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = cv[b][v] - acc[a][b][v];
     }
   } else {
     // diagonal tile: only the lower triangle (row >= col) is touched
@@ -293,9 +315,8 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
       for (int b = 0; b < BN; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int rl = wm * WTM + a * 16 + li, cc = wn * WTN + b * 16 + g + 4 * v;
-          if (row0 + rl >= col0 + cc) {
-            gdouble *p = Cg + (size_t)cc * ld + rl;
+          if (row0 + rl(a, v) >= col0 + cl(b, v)) {
+            gT *p = Cg + (size_t)cl(b, v) * ld + rl(a, v);
             *p = *p - acc[a][b][v];
           }
         }
@@ -338,9 +359,11 @@ static int tiles_for(const FactorDesc &d, int kind, int p0, int nb, int j, int T
   return nc * (nc + 1) / 2 + (nr - nc) * nc;
 }
 
-int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
+template <typename T>
+static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
   const int B = (int)fs.size();
   if (B == 0) return 0;
+  const double esz = sizeof(T);
   // device descriptor array, sorted by nf descending so active sets are prefixes
   std::vector<int> order(B);
   for (int i = 0; i < B; ++i) order[i] = i;
@@ -358,7 +381,6 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
   for (int p0 = 0; p0 < nf_max; p0 += nb) {
     for (int j = p0; j < p0 + nb && j < nf_max; j += NBI) {
       const int act = active(j);
-      // potf2 + inverse
       {
         double fl = 0;
         for (int i = 0; i < act; ++i) {
@@ -366,7 +388,9 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
           const double kr = std::max(0, std::min(NBI, h.n_real - j));
           fl += 2.0 * kr * kr * kr / 3.0;
         }
-        ctx.launch(INLA_K_POTF2, fl, 0.0, [&] { hipLaunchKernelGGL(potf2_inv_kernel, dim3(act), dim3(256), 0, ctx.stream, dd, j); });
+        ctx.launch(INLA_K_POTF2, fl, 0.0, [&] {
+          hipLaunchKernelGGL(potf2_inv_kernel<T>, dim3(act), dim3(256), 0, ctx.stream, dd, j);
+        });
       }
       for (int kind : {KIND_TRSM, KIND_PANEL}) {
         int gx = 0;
@@ -379,16 +403,17 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
           if (kind == KIND_TRSM) {
             const double m = count_rows_real(h, j + NBI);
             fl += m * kr * kr;
-            by += 16.0 * m * kr;
+            by += 2.0 * esz * m * kr;
           } else if (j + NBI < pend) {
             const double nc = count_cols_real(h, j + NBI, pend), nr = count_rows_real(h, j + NBI);
             fl += 2.0 * trap_elems(nr, nc) * kr;
-            by += 16.0 * trap_elems(nr, nc) + 8.0 * (nr + nc) * kr;
+            by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
           }
         }
         if (gx == 0) continue;
         ctx.launch(INLA_K_PANEL, fl, by, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0, nb, j);
+          hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
+                             nb, j);
         });
       }
     }
@@ -403,16 +428,21 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
       const double nc = count_cols_real(h, pend, h.d.ncols), nr = count_rows_real(h, pend);
       if (nc > 0) {
         fl += 2.0 * trap_elems(nr, nc) * kr;
-        by += 16.0 * trap_elems(nr, nc) + 8.0 * (nr + nc) * kr;
+        by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
       }
     }
     if (gx > 0)
       ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-        hipLaunchKernelGGL((gemm_update_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, KIND_TRAIL, p0,
-                           nb, p0);
+        hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                           KIND_TRAIL, p0, nb, p0);
       });
   }
   return ctx.check();
+}
+
+int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec) {
+  if (prec == INLA_PREC_FP32) return factor_batch_t<float>(ctx, fs, nb);
+  return factor_batch_t<double>(ctx, fs, nb);
 }
 
 }  // namespace inla

@@ -1,5 +1,7 @@
 // Model assembly kernels: prior precision builders, the bordered Q* / b
-// assembly with the likelihood terms, and the kriging-system build.
+// assembly with the likelihood terms, the kriging-system build, and the FP64
+// residuals of the constrained Newton system used by mixed-precision
+// refinement.
 #include "device.hpp"
 #include "host.hpp"
 #include "model.hpp"
@@ -9,8 +11,7 @@ namespace inla {
 // Sigma_ij = exp(-||p_i - p_j|| / rho) for the first n_s points, identity padded
 // to ns_pad, bordered below by the identity (rows ns_pad + i = e_i).  Factoring
 // the first ns_pad columns leaves -Sigma^{-1} in the Schur block.  The prior of
-// the exponential-covariance models is tau Sigma^{-1} (configurations of the
-// Gaussian and space x time models).
+// the exponential-covariance models is tau Sigma^{-1}.  Always FP64.
 __global__ __launch_bounds__(256) void expcov_bordered_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
@@ -43,8 +44,9 @@ __global__ __launch_bounds__(256) void expcov_bordered_kernel(const ThetaDesc *_
 //   EXPCOV: Q = tau Sigma^{-1};
 //   KRON:   Q[t1 n_s + s1, t2 n_s + s2] = tau (R_t[t1,t2] Sigma_s^{-1}[s1,s2] + delta [i == j]),
 //           R_t the unscaled first-order random walk (tridiagonal 1,2,..,2,1 / -1);
-//   DENSE:  copy of the caller's matrix.
-// Lower triangle, identity on padded diagonal entries, one workgroup per column.
+//   DENSE:  copy of the caller's matrix (its lower triangle).
+// Both triangles are written (the FP64 residual reads whole columns); identity
+// on padded diagonal entries; one workgroup per column.
 __global__ __launch_bounds__(256) void prior_assemble_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
@@ -52,26 +54,31 @@ __global__ __launch_bounds__(256) void prior_assemble_kernel(const ThetaDesc *__
   double *col = t.Qp + (size_t)c * t.ldqp;
   const int n = t.n;
   if (c >= n) {
-    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = (r == c) ? 1.0 : 0.0;
+    for (int r = threadIdx.x; r < t.n_pad; r += 256) col[r] = (r == c) ? 1.0 : 0.0;
     return;
   }
   if (t.prior == PRIOR_DENSE) {
-    const double *src = t.Quser + (size_t)c * t.ldquser;
-    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = r < n ? src[r] : 0.0;
+    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
+      const int a = r > c ? r : c, b = r > c ? c : r;
+      col[r] = r < n ? t.Quser[(size_t)b * t.ldquser + a] : 0.0;
+    }
   } else if (t.prior == PRIOR_EXPCOV) {
-    const double *src = t.P + (size_t)(t.ns_pad + c) * t.ldp + t.ns_pad;
-    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = r < n ? -t.tau * src[r] : 0.0;
+    const double *Sn = t.P + (size_t)t.ns_pad * t.ldp + t.ns_pad;  // -Sigma^{-1}, lower
+    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
+      const int a = r > c ? r : c, b = r > c ? c : r;
+      col[r] = r < n ? -t.tau * Sn[(size_t)b * t.ldp + a] : 0.0;
+    }
   } else {
     const int ns = t.n_s, nt = t.n_t;
     const int t2 = c / ns, s2 = c % ns;
     const double *Sn = t.P + (size_t)t.ns_pad * t.ldp + t.ns_pad;  // -Sigma_s^{-1}, lower
-    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) {
+    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
       double v = 0.0;
       if (r < n) {
         const int t1 = r / ns, s1 = r % ns;
         double R = 0.0;
         if (t1 == t2) R = (nt == 1) ? 0.0 : ((t1 == 0 || t1 == nt - 1) ? 1.0 : 2.0);
-        else if (t1 - t2 == 1) R = -1.0;
+        else if (t1 - t2 == 1 || t2 - t1 == 1) R = -1.0;
         if (R != 0.0) {
           const int a = s1 > s2 ? s1 : s2, b = s1 > s2 ? s2 : s1;
           v = -R * Sn[(size_t)b * t.ldp + a];
@@ -104,7 +111,7 @@ __device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, d
 
 // The bordered posterior precision of one Newton step (algorithm "Gaussian
 // Approximation": Q* = Q_prior + Q_l(x0), b = grad + Q_l x0; A = I so Q_l is the
-// diagonal W):
+// diagonal W), written in the factorisation's storage type T:
 //   rows [0, n_pad)          Q_prior + diag(W)            (lower)
 //   rows n_pad + a, a < k    constraint row C_a
 //   row  n_pad + k           b^T                 (border == BORDER_CB)
@@ -112,17 +119,18 @@ __device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, d
 // Schur-block columns start at zero.  `with_lik` = 0 gives the prior pass
 // (W = 0, b = 0).  Per-column partial sums of log pi(y|eta) and x^T Q_prior x go
 // to t.part for a fixed-order reduction.
+template <typename T>
 __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restrict__ td, int with_lik, int want_xqx,
                                                        int border) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   const int N = t.Nw;
   if (c >= t.Ncw) return;
-  double *col = t.W + (size_t)c * t.ldw;
+  T *col = (T *)t.W + (size_t)c * t.ldw;
   const int np = t.n_pad, n = t.n, k = t.k;
   __shared__ double sh[4];
   if (c >= np) {
-    for (int r = c + threadIdx.x; r < N; r += 256) col[r] = 0.0;
+    for (int r = c + threadIdx.x; r < N; r += 256) col[r] = (T)0;
     return;
   }
   double g = 0.0, W = 0.0, ll = 0.0, xc = 0.0;
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restri
       else if (border == BORDER_CB) v = (a == k) ? bc : 0.0;
       else v = (a - kc_pad == c) ? 1.0 : 0.0;
     }
-    col[r] = v;
+    col[r] = (T)v;
   }
   if (want_xqx) {
     xq = block_sum256(xq, sh);
@@ -160,26 +168,77 @@ __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restri
 
 // Kriging system from the Schur block -[[S, C x_u], [., b^T x_u]] of the big
 // factorisation: S into rows/cols [0, k) (identity padded to k_pad) and the
-// border row (C x_u - e)^T at row k_pad.  Factoring it leaves L_S and
-// w^T = (C x_u - e)^T L_S^{-T} in the border row.
+// border row (C x_u - e)^T at row k_pad, always in FP64.  Factoring it leaves
+// L_S and w^T = (C x_u - e)^T L_S^{-T} in the border row.
+template <typename T>
 __global__ __launch_bounds__(256) void kriging_build_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   const int kp = t.k_pad, N = t.Ns, k = t.k;
   if (c >= kp) return;   // only the k_pad factor columns exist; the border is a row
   double *col = t.S + (size_t)c * t.lds;
-  const double *sch = t.W + (size_t)(t.n_pad + c) * t.ldw + t.n_pad;
+  const T *sch = (const T *)t.W + (size_t)(t.n_pad + c) * t.ldw + t.n_pad;
   for (int r = c + threadIdx.x; r < N; r += 256) {
     double v = 0.0;
     if (r < kp) {
-      if (r < k && c < k) v = -sch[r];
+      if (r < k && c < k) v = -(double)sch[r];
       else if (r == c) v = 1.0;
     } else if (r == kp && c < k) {
       const double e = t.e ? t.e[c] : 0.0;
-      v = -sch[k] - e;   // C x_u - e (Schur holds -C Q^{-1} b = -C x_u)
+      v = -(double)sch[k] - e;   // C x_u - e (Schur holds -C Q^{-1} b = -C x_u)
     }
     col[r] = v;
   }
+}
+
+// FP64 residual of the constrained Newton system at the refined iterate xn:
+//   r1 = b - (Q_prior + diag W) xn - C^T lambda,   b = g(x) + W(x) x
+// with g, W at the linearisation point x.  Q_prior is stored symmetric, so the
+// product reads whole columns.  One wave per 16 rows; the result goes to t.z.
+__global__ __launch_bounds__(256) void kkt_residual_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 64 + w * 16;
+  if (i0 >= t.n_pad) return;
+  const int n = t.n, k = t.k;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const double *Q0 = t.Qp + (size_t)i0 * t.ldqp;
+  for (int j = lane; j < n; j += 64) {
+    const double xj = t.xn[j];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += Q0[(size_t)q * t.ldqp + j] * xj;
+  }
+  for (int q = 0; q < 16; ++q) {
+    const int i = i0 + q;
+    double ct = 0.0;
+    if (i < n)
+      for (int a = lane; a < k; a += 64) ct += t.C[(size_t)a * n + i] * t.lam[a];
+    const double s = wave_sum(acc[q] + ct);
+    if (lane == 0) {
+      double r = 0.0;
+      if (i < n) {
+        double g, W, ll;
+        lik_point(t, i, t.x[i], g, W, ll);
+        r = (g + W * t.x[i]) - W * t.xn[i] - s;
+      }
+      t.z[i] = r;
+    }
+  }
+}
+
+// r2 = e - C xn, one wave per constraint row (zero on padded rows).
+__global__ __launch_bounds__(256) void constraint_residual_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int a = blockIdx.x * 4 + w;
+  if (a >= t.k_pad) return;
+  double s = 0.0;
+  if (a < t.k)
+    for (int i = lane; i < t.n; i += 64) s += t.C[(size_t)a * t.n + i] * t.xn[i];
+  s = wave_sum(s);
+  if (lane == 0) t.rtwo[a] = a < t.k ? (t.e ? t.e[a] : 0.0) - s : 0.0;
 }
 
 // ------------------------------------------------------------------ launchers
@@ -196,17 +255,35 @@ void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, do
   });
 }
 void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
-                     double bytes) {
+                     double bytes, int prec) {
   if (B <= 0 || N_max <= 0) return;
   ctx.launch(INLA_K_ASSEMBLE, 0.0, bytes, [&] {
-    hipLaunchKernelGGL(assemble_kernel, dim3(N_max, B), dim3(256), 0, ctx.stream, dtd, with_lik, want_xqx, border);
+    if (prec == INLA_PREC_FP32)
+      hipLaunchKernelGGL(assemble_kernel<float>, dim3(N_max, B), dim3(256), 0, ctx.stream, dtd, with_lik, want_xqx,
+                         border);
+    else
+      hipLaunchKernelGGL(assemble_kernel<double>, dim3(N_max, B), dim3(256), 0, ctx.stream, dtd, with_lik, want_xqx,
+                         border);
   });
 }
-void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int Ns_max) {
-  if (B <= 0 || Ns_max <= 0) return;
+void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec) {
+  if (B <= 0 || kp_max <= 0) return;
   ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(kriging_build_kernel, dim3(Ns_max, B), dim3(256), 0, ctx.stream, dtd);
+    if (prec == INLA_PREC_FP32)
+      hipLaunchKernelGGL(kriging_build_kernel<float>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
+    else
+      hipLaunchKernelGGL(kriging_build_kernel<double>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
   });
+}
+void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
+    hipLaunchKernelGGL(kkt_residual_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd);
+  });
+  if (kp_max > 0)
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(constraint_residual_kernel, dim3(kp_max / 4, B), dim3(256), 0, ctx.stream, dtd);
+    });
 }
 
 }  // namespace inla

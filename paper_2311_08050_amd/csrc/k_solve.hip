@@ -1,5 +1,7 @@
-// Triangular solves, the kriging solve, Newton control and fixed-order
-// reductions.  One workgroup per theta unless stated otherwise.
+// Triangular solves, the kriging solve, Newton control, mixed-precision
+// refinement steps and fixed-order reductions.  One workgroup per theta unless
+// stated otherwise.  Factors may be stored in FP64 or FP32 (template T); every
+// solve accumulates in FP64.
 #include "device.hpp"
 #include "host.hpp"
 #include "model.hpp"
@@ -9,39 +11,39 @@ namespace inla {
 // Solve L^T x = x in place for a lower-triangular L (column-major, order np, a
 // multiple of 64) in 64-row blocks from the bottom.  For each block: the 64
 // dot products with the already solved tail (coalesced column reads, 16 columns
-// per wave), then a 64-step substitution in wave 0 with the block's columns held
-// in registers.  Global writes to x are made visible to the other waves of the
-// workgroup by the barriers.
-__device__ void trsv_lt_block(const double *__restrict__ L, int ld, int np, double *x, double *sred) {
+// per wave), then a 64-step substitution in wave 0 against the block staged in
+// LDS (D, 64 x 65 doubles).  Global writes to x are made visible to the other
+// waves of the workgroup by the barriers.
+template <typename T>
+__device__ void trsv_lt_block(const T *__restrict__ L, int ld, int np, double *x, double *sred, double (*D)[65]) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int i0 = np - 64; i0 >= 0; i0 -= 64) {
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    const double *Lc = L + (size_t)(i0 + 16 * w) * ld;
+    const T *Lc = L + (size_t)(i0 + 16 * w) * ld;
     for (int j = i0 + 64 + lane; j < np; j += 64) {
       const double xj = x[j];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] += Lc[(size_t)q * ld + j] * xj;
+      for (int q = 0; q < 16; ++q) acc[q] += (double)Lc[(size_t)q * ld + j] * xj;
     }
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const double s = wave_sum(acc[q]);
       if (lane == 0) sred[16 * w + q] = s;
     }
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      D[r][c] = (double)L[(size_t)(i0 + c) * ld + i0 + r];
+    }
     __syncthreads();
     if (w == 0) {
-      double dcol[64];
-      const double *Dc = L + (size_t)(i0 + lane) * ld + i0;
-#pragma unroll
-      for (int i = 0; i < 64; ++i) dcol[i] = Dc[i];
       double rhs = x[i0 + lane] - sred[lane];
       double xm = 0.0;
-#pragma unroll
       for (int i = 63; i >= 0; --i) {
-        const double xi = __shfl(rhs / dcol[i], i, 64);
+        const double xi = __shfl(rhs, i, 64) / D[i][i];
         if (lane == i) xm = xi;
-        if (lane < i) rhs -= dcol[i] * xi;
+        if (lane < i) rhs -= D[i][lane] * xi;
       }
       x[i0 + lane] = xm;
     }
@@ -49,13 +51,51 @@ __device__ void trsv_lt_block(const double *__restrict__ L, int ld, int np, doub
   }
 }
 
-// Newton solve x_new = L^{-T} r, then the stopping quantities
-// ||x_new - x||_inf and max(1, ||x_new||_inf) over the n real entries, and x <- x_new.
-__global__ __launch_bounds__(256) void trsv_newton_kernel(const ThetaDesc *__restrict__ td) {
+// Solve L x = x in place (forward substitution), same blocking from the top.
+// The block's rows against the solved head: thread (row i, column phase p)
+// sums columns j = p, p+4, ... (each column read is 64 contiguous values).
+template <typename T>
+__device__ void trsv_l_block(const T *__restrict__ L, int ld, int np, double *x, double *sred4, double (*D)[65]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int i0 = 0; i0 < np; i0 += 64) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int j = w; j < i0; j += 4) s += (double)L[(size_t)j * ld + i0 + lane] * x[j];
+    sred4[w * 64 + lane] = s;
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int r = e & 63, c = e >> 6;
+      D[r][c] = (double)L[(size_t)(i0 + c) * ld + i0 + r];
+    }
+    __syncthreads();
+    if (w == 0) {
+      double rhs = x[i0 + lane] - ((sred4[lane] + sred4[64 + lane]) + (sred4[128 + lane] + sred4[192 + lane]));
+      double xm = 0.0;
+      for (int c = 0; c < 64; ++c) {
+        const double xc = __shfl(rhs, c, 64) / D[c][c];
+        if (lane == c) xm = xc;
+        if (lane > c) rhs -= D[lane][c] * xc;
+      }
+      x[i0 + lane] = xm;
+    }
+    __syncthreads();
+  }
+}
+
+// Newton solve x_new = L^{-T} r.  FP64 path: the stopping quantities
+// ||x_new - x||_inf and max(1, ||x_new||_inf) over the n real entries, and
+// x <- x_new.  Mixed path (refine = 1): x_new goes to t.xn for refinement and x
+// (the linearisation point) is kept.
+template <typename T>
+__global__ __launch_bounds__(256) void trsv_newton_kernel(const ThetaDesc *__restrict__ td, int refine) {
   const ThetaDesc t = td[blockIdx.x];
   __shared__ double sred[64];
   __shared__ double sh[4];
-  trsv_lt_block(t.W, t.ldw, t.n_pad, t.r, sred);
+  __shared__ double D[64][65];
+  trsv_lt_block<T>((const T *)t.W, t.ldw, t.n_pad, t.r, sred, D);
+  if (refine) {
+    for (int i = threadIdx.x; i < t.n_pad; i += 256) t.xn[i] = i < t.n ? t.r[i] : 0.0;
+    return;
+  }
   double st = 0.0, sc = 0.0, bad = 0.0;
   for (int i = threadIdx.x; i < t.n; i += 256) {
     const double xn = t.r[i], xo = t.x[i];
@@ -74,12 +114,36 @@ __global__ __launch_bounds__(256) void trsv_newton_kernel(const ThetaDesc *__res
   }
 }
 
-// Kriging solve after the small factorisation: w from the border row, then
-// lambda = L_S^{-T} w; also log|S| = 2 sum log (L_S)_ii and ||w||^2.
+// Accept the refined iterate: Newton stopping quantities and x <- xn.
+__global__ __launch_bounds__(256) void newton_accept_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sh[4];
+  double st = 0.0, sc = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < t.n; i += 256) {
+    const double xn = t.xn[i], xo = t.x[i];
+    if (!isfinite(xn)) bad = 1.0;
+    st = fmax(st, fabs(xn - xo));
+    sc = fmax(sc, fabs(xn));
+  }
+  st = block_max256(st, sh);
+  sc = block_max256(sc, sh);
+  bad = block_sum256(bad, sh);
+  for (int i = threadIdx.x; i < t.n_pad; i += 256) t.x[i] = i < t.n ? t.xn[i] : 0.0;
+  if (threadIdx.x == 0) {
+    t.dres[DRES_STEP] = st;
+    t.dres[DRES_SCALE] = fmax(1.0, sc);
+    if (bad > 0.0) t.dres[DRES_NONFINITE] = 1.0;
+  }
+}
+
+// Kriging solve after the small (FP64) factorisation: w from the border row,
+// then lambda = L_S^{-T} w; also log|S| = 2 sum log (L_S)_ii, ||w||^2 and the
+// numerical-rank flag.
 __global__ __launch_bounds__(256) void kriging_solve_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.x];
   __shared__ double sred[64];
   __shared__ double sh[4];
+  __shared__ double D[64][65];
   const int kp = t.k_pad, k = t.k;
   double lds_ = 0.0, w2 = 0.0, dmin = INFINITY, dmax = 0.0;
   for (int i = threadIdx.x; i < kp; i += 256) {
@@ -97,7 +161,7 @@ __global__ __launch_bounds__(256) void kriging_solve_kernel(const ThetaDesc *__r
   w2 = block_sum256(w2, sh);
   dmin = -block_max256(-dmin, sh);
   dmax = block_max256(dmax, sh);
-  trsv_lt_block(t.S, t.lds, kp, t.lam, sred);
+  trsv_lt_block<double>(t.S, t.lds, kp, t.lam, sred, D);
   if (threadIdx.x == 0) {
     t.dres[DRES_LOGDET_S] = 2.0 * lds_;
     t.dres[DRES_WNORM2] = w2;
@@ -106,32 +170,102 @@ __global__ __launch_bounds__(256) void kriging_solve_kernel(const ThetaDesc *__r
   }
 }
 
-// r_c = z_c - sum_a lambda_a (G L^{-T})_{a,c}: the kriging-corrected right-hand
-// side for x = L^{-T} (L^{-1} b - L^{-1} C^T lambda).  z is the factored b row.
-__global__ __launch_bounds__(256) void rhs_kernel(const ThetaDesc *__restrict__ td) {
+// r_c = z_c - sum_a lambda_a (G L^{-T})_{a,c}.  Newton (from_z = 0): z is the
+// factored b row and lambda the kriging multipliers, giving the corrected
+// right-hand side of x = L^{-T}(L^{-1} b - L^{-1} C^T lambda).  Refinement
+// (from_z = 1): z = L^{-1} r1 and lambda = dlambda.
+template <typename T>
+__global__ __launch_bounds__(256) void rhs_kernel(const ThetaDesc *__restrict__ td, int from_z) {
   const ThetaDesc t = td[blockIdx.y];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int c0 = blockIdx.x * 64 + w * 16;
   if (c0 >= t.n_pad) return;
   const int k = t.k, np = t.n_pad;
+  const double *lam = from_z ? t.dlam : t.lam;
   for (int q = 0; q < 16; ++q) {
     const int c = c0 + q;
-    const double *col = t.W + (size_t)c * t.ldw + np;
+    const T *col = (const T *)t.W + (size_t)c * t.ldw + np;
     double s = 0.0;
-    for (int a = lane; a < k; a += 64) s += t.lam[a] * col[a];
+    for (int a = lane; a < k; a += 64) s += lam[a] * (double)col[a];
     s = wave_sum(s);
-    if (lane == 0) t.r[c] = col[k] - s;
+    if (lane == 0) t.r[c] = (from_z ? t.z[c] : (double)col[k]) - s;
+  }
+}
+
+// Refinement, constrained part: z <- L^{-1} r1 (forward solve), then
+// t = (L^{-1} C^T)^T z - r2 = C Q~^{-1} r1 - r2 and dlambda = S~^{-1} t with the
+// FP64 kriging factor (forward and back substitution).
+template <typename T>
+__global__ __launch_bounds__(256) void kkt_small_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sred4[256];
+  __shared__ double D[64][65];
+  trsv_l_block<T>((const T *)t.W, t.ldw, t.n_pad, t.z, sred4, D);
+  const int k = t.k, kp = t.k_pad, np = t.n_pad;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // 64 border rows at a time; the four waves split the columns
+  for (int a0 = 0; a0 < kp; a0 += 64) {
+    const int a = a0 + lane;
+    double s = 0.0;
+    if (a < k) {
+      const T *row = (const T *)t.W + np + a;
+#pragma unroll 8
+      for (int c = w; c < np; c += 4) s += (double)row[(size_t)c * t.ldw] * t.z[c];
+    }
+    sred4[w * 64 + lane] = s;
+    __syncthreads();
+    if (w == 0 && a < kp)
+      t.dlam[a] = a < k ? ((sred4[lane] + sred4[64 + lane]) + (sred4[128 + lane] + sred4[192 + lane])) - t.rtwo[a]
+                        : 0.0;
+    __syncthreads();
+  }
+  if (kp > 0) {
+    trsv_l_block<double>(t.S, t.lds, kp, t.dlam, sred4, D);
+    trsv_lt_block<double>(t.S, t.lds, kp, t.dlam, sred4, D);
+  }
+}
+
+// Refinement, update: dx = L^{-T} r, xn += dx, lambda += dlambda, and the
+// quantities of the refinement stopping test.
+template <typename T>
+__global__ __launch_bounds__(256) void ir_update_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.x];
+  __shared__ double sred[64];
+  __shared__ double sh[4];
+  __shared__ double D[64][65];
+  trsv_lt_block<T>((const T *)t.W, t.ldw, t.n_pad, t.r, sred, D);
+  double dm = 0.0, xm = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < t.n_pad; i += 256) {
+    double v = 0.0;
+    if (i < t.n) {
+      const double dx = t.r[i];
+      v = t.xn[i] + dx;
+      if (!isfinite(v)) bad = 1.0;
+      dm = fmax(dm, fabs(dx));
+      xm = fmax(xm, fabs(v));
+    }
+    t.xn[i] = v;
+  }
+  for (int a = threadIdx.x; a < t.k; a += 256) t.lam[a] += t.dlam[a];
+  dm = block_max256(dm, sh);
+  xm = block_max256(xm, sh);
+  bad = block_sum256(bad, sh);
+  if (threadIdx.x == 0) {
+    t.dres[DRES_IR_DX] = bad > 0.0 ? INFINITY : dm;
+    t.dres[DRES_IR_X] = fmax(1.0, xm);
   }
 }
 
 // log|Q| = 2 sum_{i<n} log L_ii of the big factor, and the fixed-order sums of
 // the per-column partials (log-likelihood, x^T Q_prior x).
+template <typename T>
 __global__ __launch_bounds__(256) void finish_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.x];
   __shared__ double sh[4];
   double ld = 0.0, ll = 0.0, xq = 0.0;
+  const T *W = (const T *)t.W;
   for (int i = threadIdx.x; i < t.n; i += 256) {
-    ld += log(t.W[(size_t)i * t.ldw + i]);
+    ld += log((double)W[(size_t)i * t.ldw + i]);
     ll += t.part[i];
     xq += t.part[t.ldw + i];
   }
@@ -150,7 +284,7 @@ __global__ __launch_bounds__(256) void copy_in_kernel(const ThetaDesc *__restric
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= t.Nw) return;
-  double *col = t.W + (size_t)c * t.ldw;
+  double *col = (double *)t.W + (size_t)c * t.ldw;
   const double *src = t.Quser + (size_t)c * t.ldquser;
   for (int r = c + threadIdx.x; r < t.Nw; r += 256) col[r] = (r < t.n && c < t.n) ? src[r] : (r == c ? 1.0 : 0.0);
 }
@@ -159,7 +293,7 @@ __global__ __launch_bounds__(256) void copy_out_kernel(const ThetaDesc *__restri
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= t.n) return;
-  const double *col = t.W + (size_t)c * t.ldw;
+  const double *col = (const double *)t.W + (size_t)c * t.ldw;
   double *dst = (double *)t.Quser + (size_t)c * t.ldquser;
   for (int r = c + threadIdx.x; r < t.n; r += 256) dst[r] = col[r];
 }
@@ -172,7 +306,7 @@ __global__ __launch_bounds__(256) void var_small_build_kernel(const ThetaDesc *_
   const int kp = t.k_pad, k = t.k, np = t.n_pad;
   if (c >= kp) return;
   double *col = t.S + (size_t)c * t.lds;
-  const double *sch = t.W + (size_t)(np + c) * t.ldw + np;   // column np + c of the big matrix, from row np
+  const double *sch = (const double *)t.W + (size_t)(np + c) * t.ldw + np;   // column np + c, from row np
   for (int r = c + threadIdx.x; r < t.Ns; r += 256) {
     double v = 0.0;
     if (r < kp) {
@@ -191,7 +325,7 @@ __global__ __launch_bounds__(256) void var_norms_kernel(const ThetaDesc *__restr
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= t.n) return;
   const int np = t.n_pad, kp = t.k_pad;
-  const double *row = t.W + np + kp + i;
+  const double *row = (const double *)t.W + np + kp + i;
   double s = 0.0;
   for (int c = 0; c < np; ++c) { const double v = row[(size_t)c * t.ldw]; s += v * v; }
   double s2 = 0.0;
@@ -203,23 +337,49 @@ __global__ __launch_bounds__(256) void var_norms_kernel(const ThetaDesc *__restr
 }
 
 // ------------------------------------------------------------------ launchers
+#define INLA_DISPATCH_T(prec, KERNEL, ...)                                        \
+  do {                                                                            \
+    if ((prec) == INLA_PREC_FP32) hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__); \
+    else hipLaunchKernelGGL(KERNEL<double>, __VA_ARGS__);                        \
+  } while (0)
+
 void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B) {
   if (B <= 0) return;
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(kriging_solve_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
 }
-void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, int prec) {
   if (B <= 0 || np_max <= 0) return;
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(rhs_kernel, dim3((np_max + 63) / 64, B), dim3(256), 0, ctx.stream, dtd);
+    INLA_DISPATCH_T(prec, rhs_kernel, dim3((np_max + 63) / 64, B), dim3(256), 0, ctx.stream, dtd, from_z);
   });
 }
-void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes) {
+void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int refine, int prec) {
   if (B <= 0) return;
-  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] { hipLaunchKernelGGL(trsv_newton_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
+    INLA_DISPATCH_T(prec, trsv_newton_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd, refine);
+  });
 }
-void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B) {
+void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B) {
   if (B <= 0) return;
-  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(finish_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(newton_accept_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
+}
+void launch_kkt_small(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
+    INLA_DISPATCH_T(prec, kkt_small_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
+    INLA_DISPATCH_T(prec, ir_update_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec) {
+  if (B <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    INLA_DISPATCH_T(prec, finish_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
+  });
 }
 void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
   if (B <= 0 || np_max <= 0) return;

@@ -10,16 +10,22 @@ enum { BORDER_CB = 0,   // border rows [C; b^T]  (Newton / prior / final passes)
 
 __device__ __forceinline__ int round_up_dev(int v, int m) { return (v + m - 1) / m * m; }
 
+// assembly (k_model.hip)
 void launch_expcov_bordered(Ctx &ctx, const ThetaDesc *dtd, int B, int Np_max);
 void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes);
 void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
-                     double bytes);
-void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int Ns_max);
+                     double bytes, int prec);
+void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);
+void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes);
 
+// solves and reductions (k_solve.hip)
 void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B);
-void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
-void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes);
-void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B);
+void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, int prec);
+void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int refine, int prec);
+void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B);
+void launch_kkt_small(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec);
+void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec);
+void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec);
 void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
 void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max);
 void launch_var_small_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max);

@@ -45,7 +45,7 @@ def test_struct_layouts():
     from paper_2311_08050_amd import binding
     assert ctypes.sizeof(binding.Model) == 8 * 4 + 6 * 8
     assert ctypes.sizeof(binding.Opts) == 24
-    assert ctypes.sizeof(binding.Result) == 9 * 8 + 2 * 4
+    assert ctypes.sizeof(binding.Result) == 9 * 8 + 4 * 4
     assert ctypes.sizeof(binding.KStats) == 32
 
 
