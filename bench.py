@@ -2,21 +2,26 @@
 
 Workload: the n = 8192 Poisson space x time interaction model (128 regions x 64
 times, Q_prior = tau (R_t kron Sigma_s(rho)^{-1} + delta I), k = 191 independent
-sum-to-zero constraints), a batch of 64 theta ~ N(theta0, 0.5^2 I), FP64, Newton
-from a zero start.  One step = one inla_laplace_eval over the batch (prior build,
-prior pass, Newton iterations with kriging, final pass at the mode, objective).
-Inputs are synthetic (seeded), resident in HBM before the timed region.
+sum-to-zero constraints), a batch of 64 theta ~ N(theta0, 0.5^2 I).  One step =
+one inla_laplace_eval over the batch (prior build, prior pass, Newton iterations
+with kriging, final pass at the mode, objective).  Inputs are synthetic
+(seeded) and resident in HBM before the timed region.
 
-Prints one JSON line.  The roofline object describes the FP64 MFMA tile-update
-kernel (trailing SYRK/GEMM and panel TRSM of the blocked Cholesky), timed with
-HIP events on the library's stream over the timed region.  cpu_baseline is the
-CPU oracle timed on this host on a bounded sample (one theta of the batch).
+Variants (each timed separately, same batch):
+  fp64        FP64 everywhere, Newton from x = 0
+  fp32        FP32-storage FP32-MFMA factorisations of Q* with FP64 refinement,
+              Newton from x = 0
+The headline `value` is the last variant in --variants.
+
+Prints one JSON line.  The roofline object describes the trailing-update MFMA
+kernel of the headline variant (gemm_update_kernel<T,128,128>), timed with HIP
+events on the library's stream over the timed region.  cpu_baseline is the CPU
+oracle timed on this host on a bounded sample (one theta of the batch).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -25,34 +30,62 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "θ-evals/sec + TFLOP/s vs MFMA peak at n=8192, FP64 vs mixed+warm-start"
-PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(model, theta, gpu_res, gpu_x):
-    """Time the oracle on one theta; also report the GPU's errors against it."""
+def run_variant(lib, binding, dms, thetas, xs, prec, steps, warmup):
     import numpy as np
-    from threadpoolctl import threadpool_info
+    import torch
 
-    from oracle import inla_oracle as O
-
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    for w in range(warmup):
+        res, _ = lib.laplace_eval(dms, thetas, x=xs, prec=prec)
+        log(f"{prec}: warmup {w} done, iters {[r['iters'] for r in res][:8]}...")
+    torch.cuda.synchronize()
+    lib.profile(True)
     t0 = time.perf_counter()
-    ref = O.laplace_eval(model, theta)
+    for s in range(steps):
+        res, _ = lib.laplace_eval(dms, thetas, x=xs, prec=prec)
+        log(f"{prec}: step {s} done")
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    errs = {
-        "objective_rel": abs(gpu_res["objective"] - ref["objective"]) / abs(ref["objective"]),
-        "logdet_qstar_rel": abs(gpu_res["logdet_qstar"] - ref["logdet_qstar"]) / abs(ref["logdet_qstar"]),
-        "logdet_qprior_rel": abs(gpu_res["logdet_qprior"] - ref["logdet_qprior"]) / abs(ref["logdet_qprior"]),
-        "mode_max_abs": float(np.max(np.abs(gpu_x - ref["x"]))),
-        "iters_gpu": gpu_res["iters"], "iters_oracle": ref["iters"],
+    stats = {binding.K_NAMES[c]: lib.profile_get(c) for c in binding.K_NAMES}
+    lib.profile(False)
+    infos = [r["info"] for r in res]
+    assert all(i == 0 for i in infos), infos
+    iters = np.array([r["iters"] for r in res])
+    trail = stats["trail"]
+    achieved = trail["flops"] / (trail["time_ms"] * 1e-3) / 1e12 if trail["time_ms"] > 0 else 0.0
+    fact = ("trail", "panel", "potf2")
+    fact_ms = sum(stats[c]["time_ms"] for c in fact)
+    fact_flops = sum(stats[c]["flops"] for c in fact)
+    peak = PEAK_TFLOPS[prec]
+    return {
+        "value": steps * len(dms) / dt,
+        "ms_per_step": dt / steps * 1e3,
+        "newton_iters": {"mean": float(iters.mean()), "max": int(iters.max()), "min": int(iters.min())},
+        "ir_steps_mean": float(np.mean([r["ir_steps"] for r in res])),
+        "fp64_fallbacks": int(sum(r["fallback"] for r in res)),
+        "roofline": {
+            "bound": "mfma",
+            "kernel": f"gemm_update_kernel<{'double' if prec == 'fp64' else 'float'},128,128> "
+                      f"({prec.upper()} MFMA trailing update of the blocked Cholesky)",
+            "achieved": achieved,
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": achieved / peak,
+            "traffic": None,
+            "launches": trail["launches"],
+            "avg_launch_ms": trail["time_ms"] / max(1, trail["launches"]),
+            "alg_flops_per_launch": trail["flops"] / max(1, trail["launches"]),
+        },
+        "factorization_tflops": fact_flops / (fact_ms * 1e-3) / 1e12 if fact_ms > 0 else 0.0,
+        "kernel_time_ms": {name: st["time_ms"] / steps for name, st in stats.items()},
+        "alg_tflops_end_to_end": sum(st["flops"] for st in stats.values()) / dt / 1e12,
     }
-    return {"value": 1.0 / dt, "unit": "θ-evals/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"1 theta (theta 0 of the batch), full oracle Laplace evaluation at n={model['n']}, "
-                      f"{dt:.1f} s"}, errs
 
 
 def main():
@@ -63,6 +96,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--ns", type=int, default=128)
     ap.add_argument("--nt", type=int, default=64)
+    ap.add_argument("--variants", default="fp64,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -82,75 +116,58 @@ def main():
     dm = binding.DeviceModel(model)
     dms = [dm] * args.batch
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.batch)]
-
-    for w in range(args.warmup):
-        res, _ = lib.laplace_eval(dms, thetas, x=xs)
-        log(f"warmup {w} done, iters {[r['iters'] for r in res][:8]}...")
-    torch.cuda.synchronize()
-    lib.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        res, _ = lib.laplace_eval(dms, thetas, x=xs)
-        log(f"step {s} done")
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    gemm = lib.profile_get(binding.K_TRAIL)
-    stats = {binding.K_NAMES[c]: lib.profile_get(c) for c in binding.K_NAMES}
-    lib.profile(False)
-
-    infos = [r["info"] for r in res]
-    assert all(i == 0 for i in infos), infos
-    iters = np.array([r["iters"] for r in res])
-    evals = args.steps * args.batch
-    value = evals / dt
-    avg_ms = gemm["time_ms"] / max(1, gemm["launches"])
-    achieved = gemm["flops"] / (gemm["time_ms"] * 1e-3) / 1e12 if gemm["time_ms"] > 0 else 0.0
-    # whole-factorisation rate: every kernel of the blocked Cholesky
-    fact = ("trail", "panel", "potf2")
-    fact_ms = sum(stats[c]["time_ms"] for c in fact)
-    fact_flops = sum(stats[c]["flops"] for c in fact)
+    variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    results = {v: run_variant(lib, binding, dms, thetas, xs, v, args.steps, args.warmup) for v in variants}
+    head = variants[-1]
+    hv = results[head]
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": hv["value"],
         "unit": "θ-evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3,
+        "ms_per_step": hv["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"Poisson space-time interaction, n={n} ({args.ns} regions x {args.nt} times), "
                         f"k={k} sum-to-zero constraints, batch {args.batch} theta ~ N(theta0, 0.5^2 I), "
-                        f"FP64, zero start",
-            "n": n, "k": k, "batch": args.batch, "precision": "fp64", "start": "zero",
+                        f"variant {head}",
+            "n": n, "k": k, "batch": args.batch, "variant": head,
         },
-        "roofline": {
-            "bound": "mfma",
-            "kernel": "gemm_update_kernel<128,128> (FP64 MFMA trailing update of the blocked Cholesky)",
-            "achieved": achieved,
-            "peak": PEAK_FP64_MFMA_TFLOPS,
-            "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_MFMA_TFLOPS,
-            "traffic": None,
-            "launches": gemm["launches"],
-            "avg_launch_ms": avg_ms,
-            "alg_flops_per_launch": gemm["flops"] / max(1, gemm["launches"]),
-        },
-        "factorization_tflops": fact_flops / (fact_ms * 1e-3) / 1e12 if fact_ms > 0 else 0.0,
-        "kernel_time_ms": {name: st["time_ms"] / args.steps for name, st in stats.items()},
-        "newton_iters": {"mean": float(iters.mean()), "max": int(iters.max()), "min": int(iters.min())},
-        "alg_tflops_end_to_end": sum(st["flops"] for st in stats.values()) / dt / 1e12,
+        "roofline": hv["roofline"],
+        "variants": results,
     }
+    if "fp64" in results and head != "fp64":
+        out["speedup_vs_fp64"] = hv["value"] / results["fp64"]["value"]
     if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_info
+
+        from oracle import inla_oracle as O
+
         log("cpu baseline: oracle on theta 0")
-        r0, x0 = lib.laplace_eval([dm], thetas[:1])
-        cb, errs = cpu_baseline(model, thetas[0], r0[0], x0[0].cpu().numpy())
-        out["cpu_baseline"] = cb
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        ref = O.laplace_eval(model, thetas[0])
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": 1.0 / dt, "unit": "θ-evals/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"1 theta (theta 0 of the batch), full oracle Laplace evaluation at n={n}, {dt:.1f} s"}
+        errs = {}
+        for v in variants:
+            r0, x0 = lib.laplace_eval([dm], thetas[:1], prec=v)
+            r0 = r0[0]
+            errs[v] = {
+                "objective_rel": abs(r0["objective"] - ref["objective"]) / abs(ref["objective"]),
+                "logdet_qstar_rel": abs(r0["logdet_qstar"] - ref["logdet_qstar"]) / abs(ref["logdet_qstar"]),
+                "logdet_s_rel": abs(r0["logdet_s"] - ref["logdet_s"]) / abs(ref["logdet_s"]),
+                "mode_max_abs": float(np.max(np.abs(x0[0].cpu().numpy() - ref["x"]))),
+                "iters": r0["iters"], "iters_oracle": ref["iters"],
+            }
         out["errors_vs_oracle"] = errs
     print(json.dumps(out), flush=True)
 

@@ -30,7 +30,7 @@ template <typename T> __device__ __forceinline__ __attribute__((address_space(1)
 // for columns [nf, ncols).  Column-major, leading dimension ld >= nrows.
 struct FactorDesc {
   void *A;         // double or float elements (the factorisation's storage type)
-  void *linv;      // NBI x NBI scratch: inverse of the current diagonal block (col-major)
+  void *linv;      // (nf / NBI) x NBI x NBI: inverse of every diagonal block (col-major)
   int *info;       // first failing pivot (1-based), 0 if none
   int ld;
   int nf;          // columns to factor (multiple of PADN)
@@ -66,6 +66,8 @@ struct ThetaDesc {
   double *rtwo;    // [k_pad] constraint residual e - C x (mixed precision)
   double *part;    // [2 * ldw] per-column partial sums (loglik, x'Qx)
   double *dres;    // [16] per-theta device results (see DRES_*)
+  void *linv;      // inverses of the big factor's 64 x 64 diagonal blocks (factor storage type)
+  double *u;       // forward-solve output / refinement correction [n_pad]
   double *out;     // caller's output vector (mode or variances), device
 };
 

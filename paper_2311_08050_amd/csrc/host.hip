@@ -116,7 +116,7 @@ static int g_nb() {
 // Per-theta workspace plan.
 struct Plan {
   ThetaDesc t{};
-  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, bytes = 0;
+  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, off_linv_small = 0, bytes = 0;
   int ns_real = 0;
   bool needs_prior_build = false;
 };
@@ -182,8 +182,11 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
   off += align256(std::max(wbytes, pbytes));
   p.off_S = off; off += align256(sizeof(double) * (size_t)t.lds * std::max(t.k_pad, 1));
   p.off_vec = off;
-  off += align256(sizeof(double) * (size_t)(4 * t.n_pad + 3 * std::max(t.k_pad, 64) + 2 * t.ldw + DRES_COUNT));
-  p.off_linv = off; off += align256(sizeof(double) * NBI * NBI);
+  off += align256(sizeof(double) * (size_t)(5 * t.n_pad + 3 * std::max(t.k_pad, 64) + 2 * t.ldw + DRES_COUNT));
+  // inverses of every 64 x 64 diagonal block: big factor (also used by the prior
+  // build, whose order is at most n_pad) and kriging factor
+  p.off_linv = off; off += align256(sizeof(double) * (size_t)t.n_pad * NBI);
+  p.off_linv_small = off; off += align256(sizeof(double) * (size_t)std::max(t.k_pad, NBI) * NBI);
   p.bytes = off;
   return p;
 }
@@ -199,11 +202,13 @@ static void bind(Plan &p, char *base) {
   t.r = v; v += t.n_pad;
   t.xn = v; v += t.n_pad;
   t.z = v; v += t.n_pad;
+  t.u = v; v += t.n_pad;
   t.lam = v; v += std::max(t.k_pad, 64);
   t.dlam = v; v += std::max(t.k_pad, 64);
   t.rtwo = v; v += std::max(t.k_pad, 64);
   t.part = v; v += 2 * t.ldw;
   t.dres = v;
+  t.linv = (void *)(base + p.off_linv);
 }
 
 // State shared by the passes of one call.
@@ -263,7 +268,8 @@ static int run_factor(Batch &b, const std::vector<int> &ids, int which, Mode mod
   std::vector<HostFactor> fs;
   for (int i : ids) {
     const Plan &p = b.plans[i];
-    HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (void *)(b.bases[i] + p.off_linv), mode);
+    const size_t lo = which == F_SMALL ? p.off_linv_small : p.off_linv;
+    HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (void *)(b.bases[i] + lo), mode);
     if (h.d.nf > 0) fs.push_back(h);
   }
   return factor_batch(b.ctx, fs, g_nb(), prec);
@@ -336,8 +342,10 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
   if ((rc = run_factor(b, ids, F_SMALL, MODE_LAPLACE))) return rc;
   launch_kriging_solve(b.ctx, d, B);
   if (pass == PASS_NEWTON) {
-    launch_rhs(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad), 0, prec);
-    launch_trsv(b.ctx, d, B, tbytes, prec != INLA_PREC_FP64, prec);
+    const int npm = max_over(b, ids, &ThetaDesc::n_pad);
+    launch_rhs(b.ctx, d, B, npm, 0, prec);
+    launch_trsv_bwd(b.ctx, d, B, npm, V_R, V_XN, tbytes, prec);
+    if (prec == INLA_PREC_FP64) launch_newton_accept(b.ctx, d, B);
   } else {
     launch_finish(b.ctx, d, B, prec);
   }
@@ -361,12 +369,15 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
       rb += 8.0 * (double)t.n * t.n;
       tb += esz * (double)t.n * t.n;
     }
-    launch_kkt_residual(b.ctx, d, B, max_over(b, act, &ThetaDesc::n_pad), max_over(b, act, &ThetaDesc::k_pad), rb);
-    launch_kkt_small(b.ctx, d, B, 0.5 * tb, prec);
-    launch_rhs(b.ctx, d, B, max_over(b, act, &ThetaDesc::n_pad), 1, prec);
-    launch_ir_update(b.ctx, d, B, 0.5 * tb, prec);
+    const int npm = max_over(b, act, &ThetaDesc::n_pad), kpm = max_over(b, act, &ThetaDesc::k_pad);
+    launch_kkt_residual(b.ctx, d, B, npm, kpm, rb);
+    launch_trsv_fwd(b.ctx, d, B, npm, V_Z, V_U, 0.5 * tb, prec);
+    launch_ir_correct(b.ctx, d, B, kpm, prec);
+    launch_rhs(b.ctx, d, B, npm, 1, prec);
+    launch_trsv_bwd(b.ctx, d, B, npm, V_R, V_U, 0.5 * tb, prec);
+    launch_ir_update(b.ctx, d, B);
     for (int i : act) steps[i] += 1;
-    if (s % 2 == 0 || s == max_ir) {
+    {
       int rc;
       if ((rc = readback(b))) return rc;
       std::vector<int> next;
@@ -515,13 +526,19 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   // first assembly: a non-finite W or b sets the flag).
   std::vector<int> active = ok, done, redo;
   std::vector<char> failed(B, 0);
-  std::vector<int> irsteps(B, 0);
+  std::vector<int> irsteps(B, 0), last_ir(B, 0);
+  std::vector<double> prev_step(B, INFINITY), prev_scale(B, 1.0);
   for (int it = 1; it <= max_iter && !active.empty(); ++it) {
     if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
     if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
     if (mixed) {
-      std::vector<int> nconv;
-      if ((rc = refine(b, active, prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
+      // Inexact Newton far from the mode; refinement to FP64 accuracy once the
+      // previous step is below 1e-3 of the iterate's scale.
+      std::vector<int> ref, nconv;
+      // (a Gaussian likelihood's single Newton step is exact, so it is always refined)
+      for (int i : active)
+        if (b.plans[i].t.lik == LIK_GAUSSIAN || prev_step[i] <= 1e-3 * prev_scale[i]) ref.push_back(i);
+      if ((rc = refine(b, ref, prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
       for (int i : nconv) { failed[i] = 1; redo.push_back(i); }
       std::vector<int> keep;
       for (int i : active) if (!failed[i]) keep.push_back(i);
@@ -540,7 +557,12 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       if (inf[F_BIG]) { res[i].info = inf[F_BIG]; failed[i] = 1; continue; }
       if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; failed[i] = 1; continue; }
       res[i].step = dr[DRES_STEP];
-      const bool conv = b.plans[i].t.lik == LIK_GAUSSIAN || dr[DRES_STEP] <= tol * dr[DRES_SCALE];
+      prev_step[i] = dr[DRES_STEP];
+      prev_scale[i] = dr[DRES_SCALE];
+      const bool refined = !mixed || irsteps[i] > last_ir[i];
+      last_ir[i] = irsteps[i];
+      // a mixed-precision step only counts once it was refined to FP64 accuracy
+      const bool conv = refined && (b.plans[i].t.lik == LIK_GAUSSIAN || dr[DRES_STEP] <= tol * dr[DRES_SCALE]);
       if (conv) done.push_back(i);
       else if (it == max_iter) { res[i].info = INLA_INFO_NEWTON_MAXIT; done.push_back(i); }
       else next.push_back(i);
@@ -557,7 +579,19 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     std::vector<int> fin;
     for (int i : done) if (!failed[i]) fin.push_back(i);
     if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
-    if ((rc = run_pass(b, fin, PASS_FINAL, prec))) return fail(rc);
+    if (mixed) {
+      // The last Newton factorisation was taken at an iterate within the Newton
+      // tolerance (1e-11) of the mode; its log-dets differ from a refactorisation
+      // at the mode by far less than the FP32 factor's own error, so it is reused.
+      ThetaDesc *d = upload_td(b, fin);
+      if (!fin.empty() && !d) return fail(INLA_ERR_NOMEM);
+      double by = 0;
+      for (int i : fin) by += 8.0 * b.plans[i].t.n * (double)b.plans[i].t.n;
+      launch_objective_terms(ctx, d, (int)fin.size(), max_over(b, fin, &ThetaDesc::n_pad), by);
+      launch_finish(ctx, d, (int)fin.size(), prec);
+    } else if ((rc = run_pass(b, fin, PASS_FINAL, prec))) {
+      return fail(rc);
+    }
     if ((rc = readback(b))) return fail(rc);
     for (int i : fin) {
       const int *inf = &b.hinfo[4 * i];
@@ -707,7 +741,7 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
     int e = s;
     for (; e < B; ++e) {
       const int np = round_up(std::max(n[e], 1), PADN);
-      const size_t need = align256(8ull * np * np) + align256(8ull * (2 * np + 64 + 2 * np + DRES_COUNT)) + align256(8 * NBI * NBI);
+      const size_t need = align256(8ull * np * np) + align256(8ull * (2 * np + 64 + 2 * np + DRES_COUNT)) + align256(8ull * np * NBI);
       if (e > s && tot + need > cap) break;
       tot += need;
     }
@@ -725,7 +759,7 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
       size_t off = 0;
       p.off_W = off; off += align256(8ull * t.n_pad * t.n_pad);
       p.off_vec = off; off += align256(8ull * (2 * t.n_pad + 64 + 2 * t.ldw + DRES_COUNT));
-      p.off_linv = off; off += align256(8 * NBI * NBI);
+      p.off_linv = off; off += align256(8ull * t.n_pad * NBI);
       p.bytes = off;
       offs[i] = total; total += off;
     }

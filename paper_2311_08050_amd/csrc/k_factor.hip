@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
     }
     __syncthreads();
   }
-  __attribute__((address_space(1))) T *Li = gptr((T *)d.linv);
+  // every diagonal block keeps its inverse (the triangular solves reuse them)
+  __attribute__((address_space(1))) T *Li = gptr((T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
   for (int e = tid; e < NBI * NBI; e += 256) {
     const int r = e & (NBI - 1), c = e >> 6;
     if (r >= c) Ad[(size_t)c * d.ld + r] = (T)M[r][c];
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
   gcT *Bg;
   int ldb;
-  if (kind == KIND_TRSM) { Bg = gptr((const T *)d.linv); ldb = NBI; }
+  if (kind == KIND_TRSM) { Bg = gptr((const T *)d.linv) + (size_t)(j / NBI) * NBI * NBI; ldb = NBI; }
   else { Bg = gptr((const T *)d.A) + (size_t)ks * ld + col0; ldb = ld; }
   gT *Cg = gptr((T *)d.A) + (size_t)col0 * ld + row0;
   const int K = ke - ks;

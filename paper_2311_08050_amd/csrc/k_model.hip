@@ -228,6 +228,41 @@ __global__ __launch_bounds__(256) void kkt_residual_kernel(const ThetaDesc *__re
   }
 }
 
+// Objective terms at the mode without re-assembling: x^T Q_prior x (symmetric
+// Q_prior, whole-column products) and log pi(y | eta) into the per-column partial
+// sums read by the finish kernel.  Used when the last Newton factorisation is
+// reused for log|Q*|.
+__global__ __launch_bounds__(256) void objective_terms_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = blockIdx.x * 64 + w * 16;
+  if (i0 >= t.n_pad) return;
+  const int n = t.n;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  const double *Q0 = t.Qp + (size_t)i0 * t.ldqp;
+  for (int j = lane; j < n; j += 64) {
+    const double xj = t.x[j];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += Q0[(size_t)q * t.ldqp + j] * xj;
+  }
+  for (int q = 0; q < 16; ++q) {
+    const int i = i0 + q;
+    const double s = wave_sum(acc[q]);
+    if (lane == 0) {
+      double ll = 0.0, xq = 0.0;
+      if (i < n) {
+        double g, W;
+        lik_point(t, i, t.x[i], g, W, ll);
+        xq = t.x[i] * s;
+      }
+      t.part[i] = ll;
+      t.part[t.ldw + i] = xq;
+    }
+  }
+}
+
 // r2 = e - C xn, one wave per constraint row (zero on padded rows).
 __global__ __launch_bounds__(256) void constraint_residual_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
@@ -273,6 +308,12 @@ void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int
       hipLaunchKernelGGL(kriging_build_kernel<float>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
     else
       hipLaunchKernelGGL(kriging_build_kernel<double>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
+void launch_objective_terms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, bytes, [&] {
+    hipLaunchKernelGGL(objective_terms_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd);
   });
 }
 void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes) {

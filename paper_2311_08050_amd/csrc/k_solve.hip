@@ -81,36 +81,73 @@ __device__ void trsv_l_block(const T *__restrict__ L, int ld, int np, double *x,
   }
 }
 
-// Newton solve x_new = L^{-T} r.  FP64 path: the stopping quantities
-// ||x_new - x||_inf and max(1, ||x_new||_inf) over the n real entries, and
-// x <- x_new.  Mixed path (refine = 1): x_new goes to t.xn for refinement and x
-// (the linearisation point) is kept.
+// Vector selectors for the step-wise triangular solves (V_* in model.hpp).
+__device__ __forceinline__ double *vsel(const ThetaDesc &t, int v) {
+  return v == V_X ? t.x : v == V_R ? t.r : v == V_XN ? t.xn : v == V_Z ? t.z : t.u;
+}
+
+// One 64-row block step of the forward solve L z = r for every theta (a launch
+// per block, blocks from the top).  z_b = L_bb^{-1} r_b uses the stored inverse
+// of the diagonal block (a 64 x 64 product, no sequential chain); then the rows
+// below are updated, r_j -= sum_c L[j][i0 + c] z_b[c], 256 rows per workgroup
+// (one thread per row, each column read contiguous across the threads).
 template <typename T>
-__global__ __launch_bounds__(256) void trsv_newton_kernel(const ThetaDesc *__restrict__ td, int refine) {
-  const ThetaDesc t = td[blockIdx.x];
-  __shared__ double sred[64];
-  __shared__ double sh[4];
-  __shared__ double D[64][65];
-  trsv_lt_block<T>((const T *)t.W, t.ldw, t.n_pad, t.r, sred, D);
-  if (refine) {
-    for (int i = threadIdx.x; i < t.n_pad; i += 256) t.xn[i] = i < t.n ? t.r[i] : 0.0;
-    return;
+__global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__restrict__ td, int i0, int src, int dst) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int np = t.n_pad;
+  if (i0 >= np) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const T *L = (const T *)t.W;
+  const T *Li = (const T *)t.linv + (size_t)(i0 / 64) * 4096;
+  double *r = vsel(t, src), *z = vsel(t, dst);
+  __shared__ double zb[64];
+  if (w == 0) {
+    double s = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < 64; ++c) s += (double)Li[c * 64 + lane] * r[i0 + c];
+    zb[lane] = s;
+    if (blockIdx.x == 0) z[i0 + lane] = s;
   }
-  double st = 0.0, sc = 0.0, bad = 0.0;
-  for (int i = threadIdx.x; i < t.n; i += 256) {
-    const double xn = t.r[i], xo = t.x[i];
-    if (!isfinite(xn)) bad = 1.0;
-    st = fmax(st, fabs(xn - xo));
-    sc = fmax(sc, fabs(xn));
+  __syncthreads();
+  const int j = i0 + 64 + blockIdx.x * 256 + tid;
+  if (j < np) {
+    double s = 0.0;
+#pragma unroll 16
+    for (int c = 0; c < 64; ++c) s += (double)L[(size_t)(i0 + c) * t.ldw + j] * zb[c];
+    r[j] -= s;
   }
-  st = block_max256(st, sh);
-  sc = block_max256(sc, sh);
-  bad = block_sum256(bad, sh);
-  for (int i = threadIdx.x; i < t.n_pad; i += 256) t.x[i] = i < t.n ? t.r[i] : 0.0;
-  if (threadIdx.x == 0) {
-    t.dres[DRES_STEP] = st;
-    t.dres[DRES_SCALE] = fmax(1.0, sc);
-    if (bad > 0.0) t.dres[DRES_NONFINITE] = 1.0;
+}
+
+// One 64-row block step of the back solve L^T x = r (blocks from the bottom):
+// x_b = L_bb^{-T} r_b with the stored inverse, then the columns above are
+// updated, r_j -= sum_m L[i0 + m][j] x_b[m]; a wave handles 16 columns, its
+// lanes the 64 contiguous rows of each.
+template <typename T>
+__global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__restrict__ td, int i0, int src, int dst) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int np = t.n_pad;
+  if (i0 >= np) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const T *L = (const T *)t.W;
+  const T *Li = (const T *)t.linv + (size_t)(i0 / 64) * 4096;
+  double *r = vsel(t, src), *x = vsel(t, dst);
+  __shared__ double xb[64];
+  if (w == 0) {
+    double s = 0.0;
+    const T *col = Li + lane * 64;
+#pragma unroll 8
+    for (int c = 0; c < 64; ++c) s += (double)col[c] * r[i0 + c];
+    xb[lane] = s;
+    if (blockIdx.x == 0) x[i0 + lane] = s;
+  }
+  __syncthreads();
+  const int j0 = blockIdx.x * 64 + w * 16;
+  const double xm = xb[lane];
+  for (int q = 0; q < 16; ++q) {
+    const int j = j0 + q;
+    if (j >= i0) break;
+    const double s = wave_sum((double)L[(size_t)j * t.ldw + i0 + lane] * xm);
+    if (lane == 0) r[j] -= s;
   }
 }
 
@@ -173,7 +210,7 @@ __global__ __launch_bounds__(256) void kriging_solve_kernel(const ThetaDesc *__r
 // r_c = z_c - sum_a lambda_a (G L^{-T})_{a,c}.  Newton (from_z = 0): z is the
 // factored b row and lambda the kriging multipliers, giving the corrected
 // right-hand side of x = L^{-T}(L^{-1} b - L^{-1} C^T lambda).  Refinement
-// (from_z = 1): z = L^{-1} r1 and lambda = dlambda.
+// (from_z = 1): u = L^{-1} r1 and lambda = dlambda.
 template <typename T>
 __global__ __launch_bounds__(256) void rhs_kernel(const ThetaDesc *__restrict__ td, int from_z) {
   const ThetaDesc t = td[blockIdx.y];
@@ -188,57 +225,55 @@ __global__ __launch_bounds__(256) void rhs_kernel(const ThetaDesc *__restrict__ 
     double s = 0.0;
     for (int a = lane; a < k; a += 64) s += lam[a] * (double)col[a];
     s = wave_sum(s);
-    if (lane == 0) t.r[c] = (from_z ? t.z[c] : (double)col[k]) - s;
+    if (lane == 0) t.r[c] = (from_z ? t.u[c] : (double)col[k]) - s;
   }
 }
 
-// Refinement, constrained part: z <- L^{-1} r1 (forward solve), then
-// t = (L^{-1} C^T)^T z - r2 = C Q~^{-1} r1 - r2 and dlambda = S~^{-1} t with the
-// FP64 kriging factor (forward and back substitution).
+// Refinement, constrained part 1: t = (L^{-1} C^T)^T u - r2 = C Q~^{-1} r1 - r2 with
+// u = L^{-1} r1, into dlam.  A workgroup per 64 border rows; the four waves split
+// the columns, each column read is 64 contiguous border values.
 template <typename T>
-__global__ __launch_bounds__(256) void kkt_small_kernel(const ThetaDesc *__restrict__ td) {
+__global__ __launch_bounds__(256) void border_gemv_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int a = blockIdx.x * 64 + (threadIdx.x & 63), w = threadIdx.x >> 6;
+  __shared__ double part[4][64];
+  if (blockIdx.x * 64 >= t.k_pad) return;
+  const int np = t.n_pad;
+  double s = 0.0;
+  if (a < t.k) {
+    const T *row = (const T *)t.W + np + a;
+#pragma unroll 8
+    for (int c = w; c < np; c += 4) s += (double)row[(size_t)c * t.ldw] * t.u[c];
+  }
+  part[w][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (w == 0) {
+    const int l = threadIdx.x;
+    t.dlam[a] = a < t.k ? ((part[0][l] + part[1][l]) + (part[2][l] + part[3][l])) - t.rtwo[a] : 0.0;
+  }
+}
+
+// Refinement, constrained part 2: dlambda = S~^{-1} t with the FP64 kriging factor.
+__global__ __launch_bounds__(256) void kriging_correct_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.x];
   __shared__ double sred4[256];
   __shared__ double D[64][65];
-  trsv_l_block<T>((const T *)t.W, t.ldw, t.n_pad, t.z, sred4, D);
-  const int k = t.k, kp = t.k_pad, np = t.n_pad;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  // 64 border rows at a time; the four waves split the columns
-  for (int a0 = 0; a0 < kp; a0 += 64) {
-    const int a = a0 + lane;
-    double s = 0.0;
-    if (a < k) {
-      const T *row = (const T *)t.W + np + a;
-#pragma unroll 8
-      for (int c = w; c < np; c += 4) s += (double)row[(size_t)c * t.ldw] * t.z[c];
-    }
-    sred4[w * 64 + lane] = s;
-    __syncthreads();
-    if (w == 0 && a < kp)
-      t.dlam[a] = a < k ? ((sred4[lane] + sred4[64 + lane]) + (sred4[128 + lane] + sred4[192 + lane])) - t.rtwo[a]
-                        : 0.0;
-    __syncthreads();
-  }
-  if (kp > 0) {
-    trsv_l_block<double>(t.S, t.lds, kp, t.dlam, sred4, D);
-    trsv_lt_block<double>(t.S, t.lds, kp, t.dlam, sred4, D);
+  if (t.k_pad > 0) {
+    trsv_l_block<double>(t.S, t.lds, t.k_pad, t.dlam, sred4, D);
+    trsv_lt_block<double>(t.S, t.lds, t.k_pad, t.dlam, sred4, D);
   }
 }
 
-// Refinement, update: dx = L^{-T} r, xn += dx, lambda += dlambda, and the
+// Refinement, update: xn += dx (dx in u), lambda += dlambda, and the
 // quantities of the refinement stopping test.
-template <typename T>
 __global__ __launch_bounds__(256) void ir_update_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.x];
-  __shared__ double sred[64];
   __shared__ double sh[4];
-  __shared__ double D[64][65];
-  trsv_lt_block<T>((const T *)t.W, t.ldw, t.n_pad, t.r, sred, D);
   double dm = 0.0, xm = 0.0, bad = 0.0;
   for (int i = threadIdx.x; i < t.n_pad; i += 256) {
     double v = 0.0;
     if (i < t.n) {
-      const double dx = t.r[i];
+      const double dx = t.u[i];
       v = t.xn[i] + dx;
       if (!isfinite(v)) bad = 1.0;
       dm = fmax(dm, fabs(dx));
@@ -353,27 +388,39 @@ void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, i
     INLA_DISPATCH_T(prec, rhs_kernel, dim3((np_max + 63) / 64, B), dim3(256), 0, ctx.stream, dtd, from_z);
   });
 }
-void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int refine, int prec) {
-  if (B <= 0) return;
-  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
-    INLA_DISPATCH_T(prec, trsv_newton_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd, refine);
-  });
+void launch_trsv_fwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec) {
+  if (B <= 0 || np_max <= 0) return;
+  for (int i0 = 0; i0 < np_max; i0 += 64) {
+    const int gx = std::max(1, (np_max - i0 - 64 + 255) / 256);
+    ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(np_max - i0) / np_max * 2.0 / np_max, [&] {
+      INLA_DISPATCH_T(prec, trsv_fwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
+    });
+  }
+}
+void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec) {
+  if (B <= 0 || np_max <= 0) return;
+  for (int i0 = np_max - 64; i0 >= 0; i0 -= 64) {
+    const int gx = std::max(1, (i0 + 63) / 64);
+    ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(i0 + 64) / np_max * 2.0 / np_max, [&] {
+      INLA_DISPATCH_T(prec, trsv_bwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
+    });
+  }
 }
 void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B) {
   if (B <= 0) return;
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(newton_accept_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
 }
-void launch_kkt_small(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec) {
+void launch_ir_correct(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec) {
   if (B <= 0) return;
-  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
-    INLA_DISPATCH_T(prec, kkt_small_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
-  });
+  if (kp_max > 0)
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      INLA_DISPATCH_T(prec, border_gemv_kernel, dim3(kp_max / 64, B), dim3(256), 0, ctx.stream, dtd);
+    });
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(kriging_correct_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
 }
-void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec) {
+void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B) {
   if (B <= 0) return;
-  ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
-    INLA_DISPATCH_T(prec, ir_update_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
-  });
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(ir_update_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
 }
 void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec) {
   if (B <= 0) return;

@@ -16,15 +16,18 @@ void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, do
 void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
                      double bytes, int prec);
 void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);
+void launch_objective_terms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes);
 void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes);
 
 // solves and reductions (k_solve.hip)
 void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, int prec);
-void launch_trsv(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int refine, int prec);
+enum { V_X = 0, V_R = 1, V_XN = 2, V_Z = 3, V_U = 4 };   // vector selectors of the solves
+void launch_trsv_fwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
+void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
 void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B);
-void launch_kkt_small(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec);
-void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B, double bytes, int prec);
+void launch_ir_correct(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);
+void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec);
 void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
 void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max);
