@@ -107,7 +107,10 @@ typedef struct inla_opts {
   int32_t prec;      /* INLA_PREC_FP64 or INLA_PREC_FP32                             */
   int32_t max_iter;  /* <= 0: 50                                                     */
   double tol;        /* <= 0: 1e-11                                                  */
-  int32_t start;     /* 0: start from x = 0; 1: start from the vectors in x_inout    */
+  int32_t start;     /* 0: start from x = 0; 1: start from the vectors in x (a warm
+                        start, e.g. inla_mlp_predict_modes or a previous mode).  A warm
+                        start that fails or exceeds max_iter is retried from x = 0
+                        with the default budget (result.fallback bit 1).          */
   int32_t reserved;
 } inla_opts;
 
@@ -125,7 +128,8 @@ typedef struct inla_result {
   int32_t iters;        /* Newton iterations taken                                   */
   int32_t info;         /* INLA_INFO_* or leading-minor index                        */
   int32_t ir_steps;     /* mixed precision: refinement steps summed over iterations  */
-  int32_t fallback;     /* 1 if the theta was re-evaluated in FP64                    */
+  int32_t fallback;     /* bit 0: re-evaluated in FP64 (refinement did not converge);
+                           bit 1: warm start failed, re-evaluated from x = 0          */
 } inla_result;
 
 /* ------------------------------------------------------------ lifecycle */
@@ -184,6 +188,44 @@ int inla_laplace_eval(inla_handle *h, int32_t B, const inla_model *models, const
  *   info     host [B] outputs (0, leading-minor index, or INLA_INFO_CONSTRAINT_RANK) */
 int inla_marginal_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta,
                       int32_t ldtheta, const double *const *x_mode, double *const *var, int32_t *info);
+
+/* ------------------------------------------------------------ learned warm start */
+/* A multilayer perceptron u -> x0 that predicts the Newton mode from the
+ * normalised hyperparameters u = (theta - centre) / scale, trained on modes the
+ * method itself produced.  It only supplies a start vector: the Newton iteration
+ * of inla_laplace_eval (opts.start = 1) still decides the result, and a failed
+ * warm start falls back to x = 0.
+ *   h1 = GELU(W1 u + b1), h2 = GELU(W2 h1 + b2), x0 = W3 h2 + b3,
+ *   GELU(z) = z (1 + erf(z / sqrt 2)) / 2, FP32.
+ * Parameters are one flat FP32 device array: W1 (H x I, row-major), b1 (H),
+ * W2 (H x H), b2 (H), W3 (O x H), b3 (O).  All array arguments are device
+ * memory unless marked host; calls complete before returning. */
+typedef struct inla_mlp inla_mlp;
+/* Create an I -> H -> H -> O network on the handle's device and stream; weights
+ * uniform(+-sqrt(6/fan_in)) (last layer +-sqrt(3/H)) from a counter-based
+ * generator seeded by `seed`, zero biases, zero Adam moments. */
+int inla_mlp_create(inla_handle *h, int32_t n_in, int32_t n_hidden, int32_t n_out, uint64_t seed, inla_mlp **m);
+int inla_mlp_destroy(inla_mlp *m);
+/* Number of FP32 parameters (host output). */
+int inla_mlp_num_params(const inla_mlp *m, int64_t *count);
+/* Copy the flat parameter array out / in (set also clears the Adam state). */
+int inla_mlp_get_params(inla_mlp *m, float *dst);
+int inla_mlp_set_params(inla_mlp *m, const float *src);
+/* y (B x O, row-major) = network(x (B x I, row-major)). */
+int inla_mlp_forward(inla_mlp *m, int32_t B, const float *x, float *y);
+/* Mean-squared-error loss over all B x O outputs against target (B x O, FP64,
+ * e.g. modes written by inla_constrained_mode into rows of one array) and its
+ * gradient with respect to every parameter (flat layout, written to grad if not
+ * NULL); *loss (host) receives the loss if loss is not NULL. */
+int inla_mlp_grad(inla_mlp *m, int32_t B, const float *x, const double *target, float *grad, double *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
+ * mean-squared-error loss of a batch; *loss (host) receives the loss before the step. */
+int inla_mlp_train_step(inla_mlp *m, int32_t B, const float *x, const double *target, float lr, double *loss);
+/* Warm starts for inla_laplace_eval: theta (host, B x ldtheta, ldtheta <= 8)
+ * normalised with centre[I], scale[I] (host), predicted modes written as FP64
+ * into x[b] (host array of B device pointers to O doubles). */
+int inla_mlp_predict_modes(inla_mlp *m, int32_t B, const double *theta, int32_t ldtheta, const double *centre,
+                           const double *scale, double *const *x);
 
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */

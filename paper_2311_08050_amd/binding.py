@@ -31,6 +31,8 @@ K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "as
 EXPORTS = [
     "inla_create", "inla_destroy", "inla_set_stream", "inla_logdet", "inla_constrained_mode",
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
+    "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
+    "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
 ]
 
 
@@ -80,6 +82,16 @@ def load_library(path: str = LIBPATH):
     lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
     lib.inla_profile.argtypes = [P, i32]
     lib.inla_profile_get.argtypes = [P, i32, C.POINTER(KStats)]
+    pf = C.c_void_p
+    lib.inla_mlp_create.argtypes = [P, i32, i32, i32, C.c_uint64, C.POINTER(P)]
+    lib.inla_mlp_destroy.argtypes = [P]
+    lib.inla_mlp_num_params.argtypes = [P, C.POINTER(C.c_int64)]
+    lib.inla_mlp_get_params.argtypes = [P, pf]
+    lib.inla_mlp_set_params.argtypes = [P, pf]
+    lib.inla_mlp_forward.argtypes = [P, i32, pf, pf]
+    lib.inla_mlp_grad.argtypes = [P, i32, pf, pf, pf, pd]
+    lib.inla_mlp_train_step.argtypes = [P, i32, pf, pf, C.c_float, pd]
+    lib.inla_mlp_predict_modes.argtypes = [P, i32, pd, i32, pd, pd, C.POINTER(P)]
     lib.inla_version.restype = C.c_char_p
     for name in EXPORTS:
         if name != "inla_version":
@@ -213,3 +225,71 @@ class Library:
         s = KStats()
         self._check(self.lib.inla_profile_get(self.h, kclass, C.byref(s)), "inla_profile_get")
         return {"launches": s.launches, "time_ms": s.time_ms, "flops": s.flops, "bytes": s.bytes}
+
+
+class Mlp:
+    """The warm-start network (I -> H -> H -> O, GELU, FP32) living on the GPU."""
+
+    def __init__(self, library: "Library", n_in: int, n_hidden: int, n_out: int, seed: int = 0):
+        self.L = library
+        self.lib = library.lib
+        self.dims = (n_in, n_hidden, n_out)
+        self.m = C.c_void_p()
+        Library._check(self.lib.inla_mlp_create(library.h, n_in, n_hidden, n_out, seed, C.byref(self.m)),
+                       "inla_mlp_create")
+        cnt = C.c_int64()
+        Library._check(self.lib.inla_mlp_num_params(self.m, C.byref(cnt)), "inla_mlp_num_params")
+        self.num_params = cnt.value
+
+    def __del__(self):
+        try:
+            if self.m and self.m.value:
+                self.lib.inla_mlp_destroy(self.m)
+                self.m = C.c_void_p()
+        except Exception:
+            pass
+
+    def get_params(self):
+        t = self.L.torch.empty(self.num_params, dtype=self.L.torch.float32, device="cuda")
+        Library._check(self.lib.inla_mlp_get_params(self.m, t.data_ptr()), "inla_mlp_get_params")
+        return t
+
+    def set_params(self, t):
+        t = t.to(dtype=self.L.torch.float32, device="cuda").contiguous()
+        Library._check(self.lib.inla_mlp_set_params(self.m, t.data_ptr()), "inla_mlp_set_params")
+
+    def forward(self, x):
+        x = x.to(dtype=self.L.torch.float32, device="cuda").contiguous()
+        y = self.L.torch.empty((x.shape[0], self.dims[2]), dtype=self.L.torch.float32, device="cuda")
+        Library._check(self.lib.inla_mlp_forward(self.m, x.shape[0], x.data_ptr(), y.data_ptr()), "inla_mlp_forward")
+        return y
+
+    def grad(self, x, target):
+        x = x.to(dtype=self.L.torch.float32, device="cuda").contiguous()
+        target = target.to(dtype=self.L.torch.float64, device="cuda").contiguous()
+        g = self.L.torch.empty(self.num_params, dtype=self.L.torch.float32, device="cuda")
+        loss = C.c_double()
+        Library._check(self.lib.inla_mlp_grad(self.m, x.shape[0], x.data_ptr(), target.data_ptr(), g.data_ptr(),
+                                              C.byref(loss)), "inla_mlp_grad")
+        return loss.value, g
+
+    def train_step(self, x, target, lr=1e-3):
+        """x: float32 (B x I) device tensor, target: float64 (B x O) device tensor."""
+        loss = C.c_double()
+        Library._check(self.lib.inla_mlp_train_step(self.m, x.shape[0], x.data_ptr(), target.data_ptr(), lr,
+                                                    C.byref(loss)), "inla_mlp_train_step")
+        return loss.value
+
+    def predict_modes(self, theta, centre, scale, x=None):
+        theta = np.ascontiguousarray(np.atleast_2d(np.asarray(theta, dtype=np.float64)))
+        B = theta.shape[0]
+        centre = np.ascontiguousarray(centre, dtype=np.float64)
+        scale = np.ascontiguousarray(scale, dtype=np.float64)
+        if x is None:
+            x = [self.L.torch.empty(self.dims[2], dtype=self.L.torch.float64, device="cuda") for _ in range(B)]
+        ptrs = (C.c_void_p * B)(*[t.data_ptr() for t in x])
+        pd = C.POINTER(C.c_double)
+        Library._check(self.lib.inla_mlp_predict_modes(self.m, B, theta.ctypes.data_as(pd), theta.shape[1],
+                                                       centre.ctypes.data_as(pd), scale.ctypes.data_as(pd), ptrs),
+                       "inla_mlp_predict_modes")
+        return x

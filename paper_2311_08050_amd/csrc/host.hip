@@ -683,6 +683,10 @@ struct inla_handle {
   Ctx ctx;
 };
 
+namespace inla {
+hipStream_t handle_stream(inla_handle *h) { return h->ctx.stream; }
+}  // namespace inla
+
 extern "C" {
 
 const char *inla_version(void) { return "inla_dense 0.1 (gfx950, fp64 mfma)"; }
@@ -816,6 +820,36 @@ static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, con
     rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
                     x + c.first, opts, res + c.first, laplace);
     if (rc) return rc;
+  }
+  // A warm start (start == 1) that fails (non-finite, no convergence within
+  // opts->max_iter, or a failed pivot) is retried from x = 0 with the default
+  // iteration budget.
+  if (opts && opts->start == 1) {
+    std::vector<int> redo;
+    for (int i = 0; i < B; ++i) {
+      const int inf = res[i].info;
+      if (inf == INLA_INFO_NEWTON_MAXIT || inf == INLA_INFO_NONFINITE || inf > 0) redo.push_back(i);
+    }
+    if (!redo.empty()) {
+      std::vector<inla_model> m2;
+      std::vector<double> th2;
+      std::vector<double *> x2;
+      for (int i : redo) {
+        m2.push_back(models[i]);
+        th2.insert(th2.end(), theta + (size_t)i * ldtheta, theta + (size_t)(i + 1) * ldtheta);
+        x2.push_back(x[i]);
+      }
+      inla_opts o2 = *opts;
+      o2.start = 0;
+      o2.max_iter = 0;
+      std::vector<inla_result> r2(redo.size());
+      rc = mode_or_eval(h, (int)redo.size(), m2.data(), th2.data(), ldtheta, x2.data(), &o2, r2.data(), laplace);
+      if (rc) return rc;
+      for (size_t q = 0; q < redo.size(); ++q) {
+        res[redo[q]] = r2[q];
+        res[redo[q]].fallback |= 2;
+      }
+    }
   }
   return INLA_OK;
 }

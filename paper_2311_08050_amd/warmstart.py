@@ -1,0 +1,55 @@
+"""Training driver of the learned warm start (the network and its kernels live
+in the C-ABI library; this module only sequences calls).
+
+The training set is a batch of hyperparameter points solved by the method
+itself (inla_constrained_mode writes the modes straight into the rows of one
+FP64 device array, which are the regression targets).  Inputs are the
+normalised points u = (theta - centre) / scale, prepared on the host.  Batches
+are contiguous slices of the (already randomly drawn) training set.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+
+def solve_modes(lib, dmodel, thetas, prec="fp32", batch=64):
+    """Modes of `dmodel` at each theta (rows of one (N x n) float64 device tensor)."""
+    import torch
+
+    N, n = len(thetas), dmodel.n
+    X = torch.zeros((N, n), dtype=torch.float64, device="cuda")
+    iters = []
+    for s in range(0, N, batch):
+        e = min(N, s + batch)
+        res, _ = lib.constrained_mode([dmodel] * (e - s), thetas[s:e], x=[X[i] for i in range(s, e)], prec=prec)
+        bad = [r["info"] for r in res if r["info"] != 0]
+        if bad:
+            raise RuntimeError(f"training targets: Newton failed with info {bad}")
+        iters += [r["iters"] for r in res]
+    return X, iters
+
+
+def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, lr=1e-3, seed=0, prec="fp32"):
+    """Solve the training points, fit the network, return (mlp, info dict)."""
+    import torch
+
+    from .binding import Mlp
+
+    t0 = time.perf_counter()
+    X, iters = solve_modes(lib, dmodel, thetas, prec=prec)
+    t_solve = time.perf_counter() - t0
+    U = torch.tensor(((np.asarray(thetas) - centre) / scale).astype(np.float32), device="cuda")
+    mlp = Mlp(lib, U.shape[1], hidden, dmodel.n, seed=seed)
+    N = len(thetas)
+    losses = []
+    t1 = time.perf_counter()
+    for ep in range(epochs):
+        tot = 0.0
+        for s in range(0, N - batch + 1, batch):
+            tot += mlp.train_step(U[s:s + batch], X[s:s + batch], lr)
+        losses.append(tot / max(1, N // batch))
+    t_train = time.perf_counter() - t1
+    return mlp, {"solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
+                 "zero_start_iters_mean": float(np.mean(iters)), "n_train": N, "epochs": epochs}
