@@ -11,6 +11,9 @@ Variants (each timed separately, same batch):
   fp64        FP64 everywhere, Newton from x = 0
   fp32        FP32-storage FP32-MFMA factorisations of Q* with FP64 refinement,
               Newton from x = 0
+  fp32+mlp    as fp32, Newton started from the learned warm start (the network's
+              prediction runs inside the timed step; its one-time training on
+              modes of separately drawn theta is reported, not timed)
 The headline `value` is the last variant in --variants.
 
 Prints one JSON line.  The roofline object describes the trailing-update MFMA
@@ -31,25 +34,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "θ-evals/sec + TFLOP/s vs MFMA peak at n=8192, FP64 vs mixed+warm-start"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+MLP_TRAIN = {"n_train": 512, "epochs": 300, "hidden": 256, "lr": 1e-3, "seed": 91}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_variant(lib, binding, dms, thetas, xs, prec, steps, warmup):
+def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None):
     import numpy as np
     import torch
 
+    prec = variant.split("+")[0]
+
+    def step():
+        if warm is None:
+            return lib.laplace_eval(dms, thetas, x=xs, prec=prec)
+        mlp, centre, scale, max_iter = warm
+        mlp.predict_modes(thetas, centre, scale, x=xs)
+        return lib.laplace_eval(dms, thetas, x=xs, start=1, max_iter=max_iter, prec=prec)
+
     for w in range(warmup):
-        res, _ = lib.laplace_eval(dms, thetas, x=xs, prec=prec)
-        log(f"{prec}: warmup {w} done, iters {[r['iters'] for r in res][:8]}...")
+        res, _ = step()
+        log(f"{variant}: warmup {w} done, iters {[r['iters'] for r in res][:8]}...")
     torch.cuda.synchronize()
     lib.profile(True)
     t0 = time.perf_counter()
     for s in range(steps):
-        res, _ = lib.laplace_eval(dms, thetas, x=xs, prec=prec)
-        log(f"{prec}: step {s} done")
+        res, _ = step()
+        log(f"{variant}: step {s} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = {binding.K_NAMES[c]: lib.profile_get(c) for c in binding.K_NAMES}
@@ -60,15 +73,17 @@ def run_variant(lib, binding, dms, thetas, xs, prec, steps, warmup):
     trail = stats["trail"]
     achieved = trail["flops"] / (trail["time_ms"] * 1e-3) / 1e12 if trail["time_ms"] > 0 else 0.0
     fact = ("trail", "panel", "potf2")
+    key = prec
     fact_ms = sum(stats[c]["time_ms"] for c in fact)
     fact_flops = sum(stats[c]["flops"] for c in fact)
-    peak = PEAK_TFLOPS[prec]
+    peak = PEAK_TFLOPS[key]
     return {
         "value": steps * len(dms) / dt,
         "ms_per_step": dt / steps * 1e3,
         "newton_iters": {"mean": float(iters.mean()), "max": int(iters.max()), "min": int(iters.min())},
         "ir_steps_mean": float(np.mean([r["ir_steps"] for r in res])),
-        "fp64_fallbacks": int(sum(r["fallback"] for r in res)),
+        "fp64_fallbacks": int(sum(r["fallback"] & 1 for r in res)),
+        "zero_start_fallbacks": int(sum((r["fallback"] >> 1) & 1 for r in res)),
         "roofline": {
             "bound": "mfma",
             "kernel": f"gemm_update_kernel<{'double' if prec == 'fp64' else 'float'},128,128> "
@@ -96,7 +111,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--ns", type=int, default=128)
     ap.add_argument("--nt", type=int, default=64)
-    ap.add_argument("--variants", default="fp64,fp32")
+    ap.add_argument("--variants", default="fp64,fp32,fp32+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -117,7 +132,21 @@ def main():
     dms = [dm] * args.batch
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.batch)]
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
-    results = {v: run_variant(lib, binding, dms, thetas, xs, v, args.steps, args.warmup) for v in variants}
+    results, train_info = {}, None
+    for v in variants:
+        warm = None
+        if v.endswith("+mlp"):
+            from paper_2311_08050_amd import warmstart
+            centre, scale = synth.kron_theta0(args.nt), np.full(4, 0.5)
+            train = synth.normal_batch(centre, MLP_TRAIN["n_train"], 0.5, seed=MLP_TRAIN["seed"])
+            log(f"training the warm start on {len(train)} theta")
+            mlp, train_info = warmstart.train(lib, dm, train, centre, scale, hidden=MLP_TRAIN["hidden"],
+                                              epochs=MLP_TRAIN["epochs"], lr=MLP_TRAIN["lr"], prec=v.split("+")[0])
+            log(f"warm start trained: {train_info}")
+            # a warm start that needs more iterations than the zero-start median is
+            # re-solved from zero (counted in zero_start_fallbacks)
+            warm = (mlp, centre, scale, int(np.ceil(train_info["zero_start_iters_mean"])))
+        results[v] = run_variant(lib, binding, dms, thetas, xs, v, args.steps, args.warmup, warm)
     head = variants[-1]
     hv = results[head]
     out = {
@@ -131,7 +160,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head == "fp64" else "f32+f64",
+        "dtype": "f64" if head.startswith("fp64") else "f32+f64",
         "data": "synthetic",
         "config": {
             "workload": f"Poisson space-time interaction, n={n} ({args.ns} regions x {args.nt} times), "
@@ -142,6 +171,8 @@ def main():
         "roofline": hv["roofline"],
         "variants": results,
     }
+    if train_info is not None:
+        out["warm_start_training"] = dict(train_info, **MLP_TRAIN)
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = hv["value"] / results["fp64"]["value"]
     if not args.no_cpu_baseline:
@@ -159,7 +190,11 @@ def main():
             "sample": f"1 theta (theta 0 of the batch), full oracle Laplace evaluation at n={n}, {dt:.1f} s"}
         errs = {}
         for v in variants:
-            r0, x0 = lib.laplace_eval([dm], thetas[:1], prec=v)
+            if v.endswith("+mlp"):
+                x0 = mlp.predict_modes(thetas[:1], centre, scale)
+                r0, x0 = lib.laplace_eval([dm], thetas[:1], x=x0, start=1, prec=v.split("+")[0])
+            else:
+                r0, x0 = lib.laplace_eval([dm], thetas[:1], prec=v.split("+")[0])
             r0 = r0[0]
             errs[v] = {
                 "objective_rel": abs(r0["objective"] - ref["objective"]) / abs(ref["objective"]),
