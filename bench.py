@@ -41,6 +41,62 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def traffic_from_profile(kernel_source, summary_md):
+    """HBM bytes per launch of the trailing-update kernel from the committed
+    counter summary (its `kernel_source_sha256:` and `traffic_bytes_per_launch:`
+    lines), or None if the summary is missing or was taken on a different
+    kernel source."""
+    import hashlib
+    try:
+        with open(summary_md) as f:
+            lines = f.read().splitlines()
+        with open(kernel_source, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for ln in lines:
+        ln = ln.strip().lstrip("-* ").replace("`", "")
+        if ":" in ln:
+            key, val = ln.split(":", 1)
+            fields[key.strip()] = val.strip()
+    if fields.get("kernel_source_sha256") != digest:
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def rocprof_window(csv_path, bench_json):
+    """Average a rocprofv3 per-dispatch CSV (kernel trace or counter collection)
+    over the timed region: the last `launches` dispatches of the roofline kernel
+    named in the JSON line that the profiled bench run printed."""
+    import csv
+
+    with open(bench_json) as f:
+        roof = json.loads([ln for ln in f if ln.startswith("{")][-1])["roofline"]
+    name = roof["kernel"].split(" ")[0].replace("inla::", "")
+    nlast = int(roof["launches"])
+    rows = []
+    with open(csv_path) as f:
+        for row in csv.DictReader(f):
+            if row["Kernel_Name"].replace(" ", "").split("(")[0].endswith(name):
+                key = int(row.get("Dispatch_Id") or row["Correlation_Id"])
+                if "Counter_Value" in row:
+                    rows.append((key, float(row["Counter_Value"]), row["Counter_Name"]))
+                else:
+                    rows.append((key, (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-6, "duration_ms"))
+    rows.sort()
+    win = [v for _, v, _ in rows[-nlast:]]
+    what = rows[0][2] if rows else "none"
+    return {"kernel": name, "dispatches_in_csv": len(rows), "window": len(win), "quantity": what,
+            "window_mean": sum(win) / len(win) if win else None,
+            "all_mean": sum(v for _, v, _ in rows) / len(rows) if rows else None,
+            "bench_avg_launch_ms": roof["avg_launch_ms"], "bench_launches": roof["launches"],
+            "bench_alg_bytes_per_launch": roof.get("alg_bytes_per_launch")}
+
+
 def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None):
     import numpy as np
     import torch
@@ -65,8 +121,10 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
         log(f"{variant}: step {s} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    stats = {binding.K_NAMES[c]: lib.profile_get(c) for c in binding.K_NAMES}
+    # counters per precision: a mixed variant files its FP64 prior pass under fp64
+    stats_by = {p: {binding.K_NAMES[c]: lib.profile_get(c, p) for c in binding.K_NAMES} for p in ("fp64", "fp32")}
     lib.profile(False)
+    stats = stats_by[prec]
     infos = [r["info"] for r in res]
     assert all(i == 0 for i in infos), infos
     iters = np.array([r["iters"] for r in res])
@@ -96,10 +154,12 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
             "launches": trail["launches"],
             "avg_launch_ms": trail["time_ms"] / max(1, trail["launches"]),
             "alg_flops_per_launch": trail["flops"] / max(1, trail["launches"]),
+            "alg_bytes_per_launch": trail["bytes"] / max(1, trail["launches"]),
         },
         "factorization_tflops": fact_flops / (fact_ms * 1e-3) / 1e12 if fact_ms > 0 else 0.0,
-        "kernel_time_ms": {name: st["time_ms"] / steps for name, st in stats.items()},
-        "alg_tflops_end_to_end": sum(st["flops"] for st in stats.values()) / dt / 1e12,
+        "kernel_time_ms": {p: {name: st["time_ms"] / steps for name, st in sb.items() if st["launches"]}
+                           for p, sb in stats_by.items()},
+        "alg_tflops_end_to_end": sum(st["flops"] for sb in stats_by.values() for st in sb.values()) / dt / 1e12,
     }
 
 
@@ -113,7 +173,15 @@ def main():
     ap.add_argument("--nt", type=int, default=64)
     ap.add_argument("--variants", default="fp64,fp32,fp32+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rocprof-window", metavar="CSV",
+                    help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
+    ap.add_argument("--bench-json", metavar="FILE", help="the JSON line printed by the profiled bench run")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.rocprof_window:
+        print(json.dumps(rocprof_window(args.rocprof_window, args.bench_json)))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -124,6 +192,16 @@ def main():
     from paper_2311_08050_amd import binding, synth
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nbytes = 1 << 30
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy": {"bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                                             "copies": 3}}), flush=True)
+        return
     model, thetas = synth.headline(B=args.batch, n_s=args.ns, n_t=args.nt)
     n, k = model["n"], model["C"].shape[0]
     log(f"workload n={n} k={k} batch={args.batch}")
@@ -149,6 +227,11 @@ def main():
         results[v] = run_variant(lib, binding, dms, thetas, xs, v, args.steps, args.warmup, warm)
     head = variants[-1]
     hv = results[head]
+    for v in variants:
+        pv = v.split("+")[0]
+        results[v]["roofline"]["traffic"] = traffic_from_profile(
+            os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"),
+            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64_traffic.md"))
     out = {
         "metric": METRIC,
         "value": hv["value"],

@@ -246,9 +246,13 @@ typedef struct inla_kstats {
 /* Turn per-launch event timing on (1) or off (0); turning it on clears the
  * counters.  Timing adds an event pair per launch. */
 int inla_profile(inla_handle *h, int32_t enable);
-/* Read the counters of kernel class `kclass` (collected up to the last
- * completed call). */
-int inla_profile_get(inla_handle *h, int32_t kclass, inla_kstats *out);
+/* Read the counters of kernel class `kclass` for the launches enqueued by
+ * passes run at precision `prec` (INLA_PREC_FP64 or INLA_PREC_FP32), collected
+ * up to the last completed call.  A mixed-precision evaluation files its FP64
+ * prior pass under INLA_PREC_FP64 and its Newton and final passes (including
+ * their FP64 residual kernels) under INLA_PREC_FP32.  Returns -2 for an unknown
+ * class, -3 for an unknown precision, -4 for a null `out`. */
+int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *out);
 
 /* Library version string. */
 const char *inla_version(void);

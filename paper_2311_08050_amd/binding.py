@@ -81,7 +81,7 @@ def load_library(path: str = LIBPATH):
         f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
     lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
     lib.inla_profile.argtypes = [P, i32]
-    lib.inla_profile_get.argtypes = [P, i32, C.POINTER(KStats)]
+    lib.inla_profile_get.argtypes = [P, i32, i32, C.POINTER(KStats)]
     pf = C.c_void_p
     lib.inla_mlp_create.argtypes = [P, i32, i32, i32, C.c_uint64, C.POINTER(P)]
     lib.inla_mlp_destroy.argtypes = [P]
@@ -221,9 +221,9 @@ class Library:
     def profile(self, on: bool):
         self._check(self.lib.inla_profile(self.h, 1 if on else 0), "inla_profile")
 
-    def profile_get(self, kclass):
+    def profile_get(self, kclass, prec="fp64"):
         s = KStats()
-        self._check(self.lib.inla_profile_get(self.h, kclass, C.byref(s)), "inla_profile_get")
+        self._check(self.lib.inla_profile_get(self.h, kclass, PREC[prec], C.byref(s)), "inla_profile_get")
         return {"launches": s.launches, "time_ms": s.time_ms, "flops": s.flops, "bytes": s.bytes}
 
 

@@ -62,7 +62,7 @@ void Ctx::launch(int cls, double flops, double bytes, const std::function<void()
   (void)hipEventRecord(a, stream);
   f();
   (void)hipEventRecord(b, stream);
-  pending.push_back({a, b, cls, flops, bytes});
+  pending.push_back({a, b, cls, prec_tag == INLA_PREC_FP32 ? 1 : 0, flops, bytes});
   if (pending.size() >= 8192) harvest();
 }
 
@@ -72,10 +72,11 @@ void Ctx::harvest() {
   for (auto &p : pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
-      stats[p.cls].launches += 1;
-      stats[p.cls].time_ms += ms;
-      stats[p.cls].flops += p.flops;
-      stats[p.cls].bytes += p.bytes;
+      inla_kstats &s = stats[p.cls][p.prec];
+      s.launches += 1;
+      s.time_ms += ms;
+      s.flops += p.flops;
+      s.bytes += p.bytes;
     }
     event_pool.push_back(p.a);
     event_pool.push_back(p.b);
@@ -323,6 +324,7 @@ static int prior_build(Batch &b, const std::vector<int> &ids) {
 // right-hand side and back-substitute, or (prior / final) reduce the log-dets.
 enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2 };
 static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) {
+  PrecScope tag(b.ctx, prec);
   if (ids.empty()) return 0;
   ThetaDesc *d = upload_td(b, ids);
   if (!d) return INLA_ERR_NOMEM;
@@ -357,6 +359,7 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
 // Returns the thetas whose refinement did not reach ||dx|| <= tol_ir * max(1, ||x||).
 static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, double tol_ir, std::vector<int> &failed,
                   std::vector<int> &steps) {
+  PrecScope tag(b.ctx, prec);
   std::vector<int> act = ids;
   const double esz = prec == INLA_PREC_FP32 ? 4.0 : 8.0;
   for (int s = 1; s <= max_ir && !act.empty(); ++s) {
@@ -583,6 +586,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       // The last Newton factorisation was taken at an iterate within the Newton
       // tolerance (1e-11) of the mode; its log-dets differ from a refactorisation
       // at the mode by far less than the FP32 factor's own error, so it is reused.
+      PrecScope tag(ctx, prec);
       ThetaDesc *d = upload_td(b, fin);
       if (!fin.empty() && !d) return fail(INLA_ERR_NOMEM);
       double by = 0;
@@ -885,16 +889,19 @@ int inla_profile(inla_handle *h, int32_t enable) {
   if (!h) return -1;
   h->ctx.harvest();
   h->ctx.prof = enable != 0;
-  if (enable) for (auto &s : h->ctx.stats) s = inla_kstats{};
+  if (enable)
+    for (auto &row : h->ctx.stats)
+      for (auto &s : row) s = inla_kstats{};
   return INLA_OK;
 }
 
-int inla_profile_get(inla_handle *h, int32_t kclass, inla_kstats *out) {
+int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *out) {
   if (!h) return -1;
   if (kclass < 0 || kclass >= INLA_K_COUNT) return -2;
-  if (!out) return -3;
+  if (prec != INLA_PREC_FP64 && prec != INLA_PREC_FP32) return -3;
+  if (!out) return -4;
   h->ctx.harvest();
-  *out = h->ctx.stats[kclass];
+  *out = h->ctx.stats[kclass][prec == INLA_PREC_FP32 ? 1 : 0];
   return INLA_OK;
 }
 

@@ -33,8 +33,9 @@ struct Ctx {
   size_t ring_size = 0, ring_off = 0;
   // profiling
   bool prof = false;
-  inla_kstats stats[INLA_K_COUNT] = {};
-  struct Pending { hipEvent_t a, b; int cls; double flops, bytes; };
+  int prec_tag = INLA_PREC_FP64;  // precision of the pass being enqueued
+  inla_kstats stats[INLA_K_COUNT][2] = {};
+  struct Pending { hipEvent_t a, b; int cls, prec; double flops, bytes; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   hipError_t last = hipSuccess;
@@ -50,6 +51,14 @@ struct Ctx {
   void harvest();
   int check();
   ~Ctx();
+};
+
+// Tags the launches enqueued in its scope with a precision for the profiling counters.
+struct PrecScope {
+  Ctx &c;
+  int old;
+  PrecScope(Ctx &ctx, int prec) : c(ctx), old(ctx.prec_tag) { c.prec_tag = prec; }
+  ~PrecScope() { c.prec_tag = old; }
 };
 
 // Library entry points implemented in other translation units.

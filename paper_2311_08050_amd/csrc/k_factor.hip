@@ -442,6 +442,7 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
 }
 
 int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec) {
+  PrecScope tag(ctx, prec);
   if (prec == INLA_PREC_FP32) return factor_batch_t<float>(ctx, fs, nb);
   return factor_batch_t<double>(ctx, fs, nb);
 }
