@@ -86,68 +86,140 @@ __device__ __forceinline__ double *vsel(const ThetaDesc &t, int v) {
   return v == V_X ? t.x : v == V_R ? t.r : v == V_XN ? t.xn : v == V_Z ? t.z : t.u;
 }
 
+// y = M v (trans = 0) or y = M^T v (trans = 1) for a 64 x 64 block M stored
+// column-major at Mg (element (m, c) at Mg[c * 64 + m]); v and y live in LDS.
+// The block is staged through LDS with one coalesced load per thread and
+// element, then each wave sums a quarter of the columns.  All 256 threads take
+// part; returns after a barrier.
+template <typename T>
+__device__ __forceinline__ void block64_apply(const T *__restrict__ Mg, const double *v, int trans, double *y,
+                                              T (*sM)[65], double (*part)[64]) {
+  const int tid = threadIdx.x, m = tid & 63, w = tid >> 6;
+  const auto *g = gptr(Mg);
+  T e[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) e[q] = g[q * 256 + tid];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) sM[(q * 256 + tid) >> 6][tid & 63] = e[q];
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int cc = 0; cc < 16; ++cc) {
+    const int c = 16 * w + cc;
+    s += (double)(trans ? sM[m][c] : sM[c][m]) * v[c];
+  }
+  part[w][m] = s;
+  __syncthreads();
+  if (tid < 64) y[tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+  __syncthreads();
+}
+
 // One 64-row block step of the forward solve L z = r for every theta (a launch
-// per block, blocks from the top).  z_b = L_bb^{-1} r_b uses the stored inverse
-// of the diagonal block (a 64 x 64 product, no sequential chain); then the rows
-// below are updated, r_j -= sum_c L[j][i0 + c] z_b[c], 256 rows per workgroup
-// (one thread per row, each column read contiguous across the threads).
+// per block, blocks from the top).  On entry z_b = L_bb^{-1} r_b is already in
+// z (written by the previous step; the first step forms it from the stored
+// inverse of the diagonal block).  The rows below are updated,
+// r_j -= sum_c L[j][i0 + c] z_b[c], 256 rows per workgroup (one thread per row,
+// each column read contiguous across the threads).  The workgroup holding the
+// next block's rows finalises them and forms z_{b+1} for the next launch.
 template <typename T>
 __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__restrict__ td, int i0, int src, int dst) {
   const ThetaDesc t = td[blockIdx.y];
   const int np = t.n_pad;
   if (i0 >= np) return;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const T *L = (const T *)t.W;
-  const T *Li = (const T *)t.linv + (size_t)(i0 / 64) * 4096;
-  double *r = vsel(t, src), *z = vsel(t, dst);
-  __shared__ double zb[64];
-  if (w == 0) {
-    double s = 0.0;
-#pragma unroll 8
-    for (int c = 0; c < 64; ++c) s += (double)Li[c * 64 + lane] * r[i0 + c];
-    zb[lane] = s;
-    if (blockIdx.x == 0) z[i0 + lane] = s;
+  const int tid = threadIdx.x;
+  const auto *L = gptr((const T *)t.W);
+  const T *linv = (const T *)t.linv;
+  auto *r = gptr(vsel(t, src));
+  auto *z = gptr(vsel(t, dst));
+  __shared__ double smem[64 * 65];
+  T(*sM)[65] = reinterpret_cast<T(*)[65]>(smem);
+  __shared__ double part[4][64];
+  __shared__ double zb[64], rb[64], zn[64];
+  if (i0 == 0) {
+    if (tid < 64) rb[tid] = r[tid];
+    __syncthreads();
+    block64_apply(linv, rb, 0, zb, sM, part);
+    if (blockIdx.x == 0 && tid < 64) z[tid] = zb[tid];
+  } else {
+    if (tid < 64) zb[tid] = z[i0 + tid];
+    __syncthreads();
   }
-  __syncthreads();
   const int j = i0 + 64 + blockIdx.x * 256 + tid;
+  double nv = 0.0;
   if (j < np) {
     double s = 0.0;
 #pragma unroll 16
     for (int c = 0; c < 64; ++c) s += (double)L[(size_t)(i0 + c) * t.ldw + j] * zb[c];
-    r[j] -= s;
+    nv = r[j] - s;
+    r[j] = nv;
+  }
+  if (blockIdx.x == 0 && i0 + 64 < np) {
+    if (tid < 64) rb[tid] = nv;
+    __syncthreads();
+    block64_apply(linv + (size_t)(i0 / 64 + 1) * 4096, rb, 0, zn, sM, part);
+    if (tid < 64) z[i0 + 64 + tid] = zn[tid];
   }
 }
 
-// One 64-row block step of the back solve L^T x = r (blocks from the bottom):
-// x_b = L_bb^{-T} r_b with the stored inverse, then the columns above are
-// updated, r_j -= sum_m L[i0 + m][j] x_b[m]; a wave handles 16 columns, its
-// lanes the 64 contiguous rows of each.
+// One 64-row block step of the back solve L^T x = r (blocks from the bottom).
+// On entry x_b = L_bb^{-T} r_b is already in x (the bottom block of a theta
+// forms it from the stored inverse).  The columns above are updated,
+// r_j -= sum_m L[i0 + m][j] x_b[m]: a workgroup takes 64 columns, a wave 16 of
+// them with its lanes on the 64 contiguous rows of each; the 16 x 64 products
+// are summed per column through LDS.  The workgroup holding the columns just
+// above the block finalises them and forms x_{b-1} for the next launch.
 template <typename T>
 __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__restrict__ td, int i0, int src, int dst) {
   const ThetaDesc t = td[blockIdx.y];
   const int np = t.n_pad;
   if (i0 >= np) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const T *L = (const T *)t.W;
-  const T *Li = (const T *)t.linv + (size_t)(i0 / 64) * 4096;
-  double *r = vsel(t, src), *x = vsel(t, dst);
-  __shared__ double xb[64];
-  if (w == 0) {
-    double s = 0.0;
-    const T *col = Li + lane * 64;
-#pragma unroll 8
-    for (int c = 0; c < 64; ++c) s += (double)col[c] * r[i0 + c];
-    xb[lane] = s;
-    if (blockIdx.x == 0) x[i0 + lane] = s;
+  const auto *L = gptr((const T *)t.W);
+  const T *linv = (const T *)t.linv;
+  auto *r = gptr(vsel(t, src));
+  auto *x = gptr(vsel(t, dst));
+  // the staged diagonal block and the product tile are never live together
+  __shared__ double smem[64 * 65];
+  T(*sM)[65] = reinterpret_cast<T(*)[65]>(smem);
+  double(*prod)[65] = reinterpret_cast<double(*)[65]>(smem);
+  __shared__ double part[4][64];
+  __shared__ double xb[64], rb[64], xn[64];
+  if (i0 + 64 == np) {
+    if (tid < 64) rb[tid] = r[i0 + tid];
+    __syncthreads();
+    block64_apply(linv + (size_t)(i0 / 64) * 4096, rb, 1, xb, sM, part);
+    if (blockIdx.x == 0 && tid < 64) x[i0 + tid] = xb[tid];
+  } else {
+    if (tid < 64) xb[tid] = x[i0 + tid];
+    __syncthreads();
   }
-  __syncthreads();
-  const int j0 = blockIdx.x * 64 + w * 16;
+  const int g = blockIdx.x;
+  if (64 * g >= i0) return;
   const double xm = xb[lane];
-  for (int q = 0; q < 16; ++q) {
-    const int j = j0 + q;
-    if (j >= i0) break;
-    const double s = wave_sum((double)L[(size_t)j * t.ldw + i0 + lane] * xm);
-    if (lane == 0) r[j] -= s;
+  const int j0 = 64 * g + 16 * w;
+  T v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) v[q] = L[(size_t)(j0 + q) * t.ldw + i0 + lane];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) prod[16 * w + q][lane] = (double)v[q] * xm;
+  __syncthreads();
+  const int cc = tid >> 2, p = tid & 3;
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) s += prod[cc][16 * p + i];
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  const int jc = 64 * g + cc;
+  double nv = 0.0;
+  if (p == 0) {
+    nv = r[jc] - s;
+    r[jc] = nv;
+  }
+  if (64 * g + 64 == i0) {
+    if (p == 0) rb[cc] = nv;
+    __syncthreads();
+    block64_apply(linv + (size_t)(i0 / 64 - 1) * 4096, rb, 1, xn, sM, part);
+    if (tid < 64) x[i0 - 64 + tid] = xn[tid];
   }
 }
 

@@ -1,0 +1,180 @@
+"""The workload configurations at their full sizes, in one library call each:
+
+* uneven batch: 64 theta with n drawn from {1024, 2048, 3000, 4096, 6144}
+  (Poisson space x time interaction models, k = n_s + n_t - 1), FP64;
+* n = 16384 (128 regions x 128 times, k = 255), FP64 and mixed precision;
+* the learned warm start at n = 4096 (128 x 32): trained on 2000 theta solved
+  by the plain FP64 method, tested on 64 held-out theta in mixed precision.
+
+At these sizes the oracle runs on sampled theta only (one per distinct n up to
+3000); everything else is checked by properties that hold at any size: the
+Kronecker closed form of log|Q_prior|, C x* = e, and stationarity of the
+constrained mode (Q_prior x* - grad log pi(y | x*) lies in the row space of C).
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from oracle import inla_oracle as O
+from paper_2311_08050_amd import synth
+
+pytestmark = pytest.mark.gpu
+RTOL = 1e-9
+LOGDET_RTOL = 2e-6   # mixed precision (FP32 factor) bound on log-determinants and the objective
+
+
+def say(msg):
+    print(f"[gpu-configs] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+def kron_logdet_closed_form(model, th):
+    """log|tau (R_t kron Sigma_s^{-1} + delta I)| from the eigenvalues of R_t and Sigma_s."""
+    lam = np.linalg.eigvalsh(O.rw1_structure(model["n_t"]))
+    tau, rho, delta = math.exp(th[0]), math.exp(th[1]), math.exp(th[2])
+    mu = np.linalg.eigvalsh(O.expcov(model["coords"], rho))
+    return float(np.sum(np.log(tau * (lam[:, None] / mu[None, :] + delta))))
+
+
+def stationarity_residual(model, th, x, Qp=None):
+    """Relative residual of Q_prior x - g(x) = C^T lambda (least-squares lambda),
+    g the Poisson log-likelihood gradient at eta = beta0 + x."""
+    if Qp is None:
+        Qp = O.prior_precision(model, th)
+    g = model["y"] - model["E"] * np.exp(th[3] + x)
+    v = Qp @ x - g
+    lam, *_ = np.linalg.lstsq(model["C"].T, v, rcond=None)
+    return np.max(np.abs(v - model["C"].T @ lam)) / max(1.0, np.max(np.abs(Qp @ x)))
+
+
+@pytest.mark.timeout(600)
+def test_uneven_batch_configuration(lib):
+    from paper_2311_08050_amd.binding import DeviceModel
+    models, thetas = synth.uneven_batch(B=64, seed=3)
+    dms, seen = [], {}
+    for m in models:
+        if id(m) not in seen:
+            seen[id(m)] = DeviceModel(m)
+        dms.append(seen[id(m)])
+    ns = sorted({m["n"] for m in models})
+    say(f"uneven batch: 64 theta, n in {ns}, FP64, one call")
+    t0 = time.perf_counter()
+    res, xs = lib.laplace_eval(dms, thetas)
+    say(f"uneven batch: {time.perf_counter() - t0:.2f} s, iterations {[r['iters'] for r in res]}")
+    for b, (m, th) in enumerate(zip(models, thetas)):
+        r = res[b]
+        assert r["info"] == 0 and 2 <= r["iters"] <= 12, (b, r)
+        assert rel(r["logdet_qprior"], kron_logdet_closed_form(m, th)) <= 1e-10, b
+        x = xs[b].cpu().numpy()
+        assert np.max(np.abs(m["C"] @ x)) <= 1e-10, b
+    # oracle on the first theta of each distinct n up to 3000
+    done = set()
+    for b, (m, th) in enumerate(zip(models, thetas)):
+        if m["n"] > 3000 or m["n"] in done:
+            continue
+        done.add(m["n"])
+        say(f"uneven batch: oracle on theta {b} (n={m['n']})")
+        ref = O.laplace_eval(m, th)
+        assert ref["info"] == 0 and abs(res[b]["iters"] - ref["iters"]) <= 1
+        for key in ("objective", "logdet_qprior", "logdet_sprior", "ese", "logdet_qstar", "logdet_s", "xqx", "loglik"):
+            assert rel(res[b][key], ref[key]) <= RTOL, (b, key, res[b][key], ref[key])
+        x = xs[b].cpu().numpy()
+        assert np.max(np.abs(x - ref["x"])) / max(1.0, np.max(np.abs(ref["x"]))) <= RTOL
+    assert len(done) == 3
+    # the larger sizes: stationarity of the mode on one theta each
+    for nn in (4096, 6144):
+        b = next(i for i, m in enumerate(models) if m["n"] == nn)
+        say(f"uneven batch: stationarity of theta {b} (n={nn})")
+        assert stationarity_residual(models[b], thetas[b], xs[b].cpu().numpy()) <= 1e-9
+
+
+@pytest.mark.timeout(900)
+def test_n16384_fp64_and_mixed(lib):
+    from paper_2311_08050_amd.binding import DeviceModel
+    model = synth.kron_poisson(128, 128, seed=4)
+    th0 = synth.kron_theta0(128)
+    dm = DeviceModel(model)
+    say("n=16384 k=255: FP64 at theta0")
+    r64, x64 = lib.laplace_eval([dm], th0[None, :], prec="fp64")
+    r64, x64 = r64[0], x64[0].cpu().numpy()
+    assert r64["info"] == 0 and 2 <= r64["iters"] <= 12, r64
+    assert rel(r64["logdet_qprior"], kron_logdet_closed_form(model, th0)) <= 1e-10
+    assert np.max(np.abs(model["C"] @ x64)) <= 1e-10
+    say("n=16384: stationarity on the CPU")
+    assert stationarity_residual(model, th0, x64) <= 1e-9
+    say("n=16384: mixed precision (FP32 factorisations, FP64 refinement)")
+    r32, x32 = lib.laplace_eval([dm], th0[None, :], prec="fp32")
+    r32, x32 = r32[0], x32[0].cpu().numpy()
+    assert r32["info"] == 0 and r32["fallback"] == 0
+    mode_err = np.max(np.abs(x32 - x64)) / max(1.0, np.max(np.abs(x64)))
+    say(f"n=16384 FP32 vs FP64: mode {mode_err:.2e}, log|Q*| {rel(r32['logdet_qstar'], r64['logdet_qstar']):.2e}, "
+        f"log|S| {rel(r32['logdet_s'], r64['logdet_s']):.2e}, objective {rel(r32['objective'], r64['objective']):.2e}")
+    assert mode_err <= RTOL
+    assert rel(r32["logdet_qstar"], r64["logdet_qstar"]) <= LOGDET_RTOL
+    assert rel(r32["objective"], r64["objective"]) <= LOGDET_RTOL
+    # the 9-point finite-difference batch (theta0 and theta0 +- h e_j), both precisions
+    h = 0.01
+    batch = np.stack([th0] + [th0 + s * h * np.eye(4)[j] for j in range(4) for s in (1, -1)])
+    for prec in ("fp64", "fp32"):
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rb, _ = lib.laplace_eval([dm] * 9, batch, prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(r["info"] == 0 for r in rb)
+        say(f"n=16384 9-point batch {prec}: {9 / dt:.2f} theta-evals/s, iterations {[r['iters'] for r in rb]}")
+        if prec == "fp64":
+            assert abs(rb[0]["objective"] - r64["objective"]) <= 1e-12 * abs(r64["objective"])
+            ref_obj = [r["objective"] for r in rb]
+        else:
+            assert max(rel(r["objective"], o) for r, o in zip(rb, ref_obj)) <= LOGDET_RTOL
+
+
+@pytest.mark.timeout(900)
+def test_warm_start_configuration_n4096(lib):
+    import torch
+    from paper_2311_08050_amd import warmstart
+    from paper_2311_08050_amd.binding import DeviceModel
+    model = synth.kron_poisson(128, 32, seed=50)       # n = 4096, k = 159
+    dm = DeviceModel(model)
+    th0 = synth.kron_theta0(32)
+    scale = np.full(4, 0.5)
+    train = synth.normal_batch(th0, 2000, 0.5, seed=51)
+    test = synth.normal_batch(th0, 64, 0.5, seed=52)
+    say("n=4096 warm start: 2000 training theta solved in FP64, then training")
+    mlp, info = warmstart.train(lib, dm, train, th0, scale, hidden=256, epochs=60, batch=64, lr=1e-3, prec="fp64")
+    say(f"training: {info}")
+    assert info["loss_last"] < 0.05 * info["loss_first"], info
+    runs = {}
+    for start in ("zero", "warm"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if start == "zero":
+            r, x = lib.laplace_eval([dm] * 64, test, prec="fp32")
+        else:
+            xw = mlp.predict_modes(test, th0, scale)
+            r, x = lib.laplace_eval([dm] * 64, test, x=xw, start=1, prec="fp32")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        runs[start] = (r, x)
+        say(f"mixed precision, {start} start: mean Newton iterations {np.mean([q['iters'] for q in r]):.2f}, "
+            f"{64 / dt:.1f} theta-evals/s")
+    (r0, x0), (rw, xw) = runs["zero"], runs["warm"]
+    assert np.mean([q["iters"] for q in rw]) < np.mean([q["iters"] for q in r0]) - 1.0
+    for b in range(64):
+        assert r0[b]["info"] == 0 and rw[b]["info"] == 0
+        a, c = xw[b].cpu().numpy(), x0[b].cpu().numpy()
+        assert np.max(np.abs(a - c)) <= 1e-10 * max(1.0, np.max(np.abs(c))), b
+        assert rel(rw[b]["objective"], r0[b]["objective"]) <= LOGDET_RTOL, b
+    say("n=4096: oracle on held-out theta 0")
+    ref = O.laplace_eval(model, test[0])
+    assert np.max(np.abs(xw[0].cpu().numpy() - ref["x"])) / max(1.0, np.max(np.abs(ref["x"]))) <= RTOL
+    assert rel(rw[0]["objective"], ref["objective"]) <= LOGDET_RTOL
