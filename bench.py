@@ -11,14 +11,16 @@ Variants (each timed separately, same batch):
   fp64        FP64 everywhere, Newton from x = 0
   fp32        FP32-storage FP32-MFMA factorisations of Q* with FP64 refinement,
               Newton from x = 0
-  fp32+mlp    as fp32, Newton started from the learned warm start (the network's
-              prediction runs inside the timed step; its one-time training on
-              modes of separately drawn theta is reported, not timed)
+  bf16        as fp32, but the unrefined Newton steps factor with BF16 trailing
+              operands (FP32 accumulation)
+  fp32+mlp,   as fp32 / bf16, Newton started from the learned warm start (the
+  bf16+mlp    network's prediction runs inside the timed step; its one-time
+              training on modes of separately drawn theta is reported, not timed)
 The headline `value` is the last variant in --variants.
 
-Prints one JSON line.  The roofline object describes the trailing-update MFMA
-kernel of the headline variant (gemm_update_kernel<T,128,128>), timed with HIP
-events on the library's stream over the timed region.  cpu_baseline is the CPU
+Prints one JSON line.  The roofline object describes the dominant trailing-update
+MFMA kernel of the headline variant, timed with HIP events on the library's
+stream over the timed region.  cpu_baseline is the CPU
 oracle timed on this host on a bounded sample (one theta of the batch).
 """
 from __future__ import annotations
@@ -33,7 +35,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "θ-evals/sec + TFLOP/s vs MFMA peak at n=8192, FP64 vs mixed+warm-start"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks
+TRAIL_KERNEL = {"fp64": "gemm_update_kernel<double,128,128>", "fp32": "gemm_update_kernel<float,128,128>",
+                "bf16": "trail_bf16_kernel<128,128>"}
 MLP_TRAIN = {"n_train": 512, "epochs": 300, "hidden": 256, "lr": 1e-3, "seed": 91}
 
 
@@ -122,16 +126,19 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # counters per precision: a mixed variant files its FP64 prior pass under fp64
-    stats_by = {p: {binding.K_NAMES[c]: lib.profile_get(c, p) for c in binding.K_NAMES} for p in ("fp64", "fp32")}
+    stats_by = {p: {binding.K_NAMES[c]: lib.profile_get(c, p) for c in binding.K_NAMES}
+                for p in ("fp64", "fp32", "bf16")}
     lib.profile(False)
-    stats = stats_by[prec]
+    # the dominant trailing-update kernel of the variant (a BF16 variant runs
+    # both BF16 and FP32 trailing updates; the prior pass is FP64 in every variant)
+    key = max(("fp32", "bf16") if prec != "fp64" else ("fp64",), key=lambda p: stats_by[p]["trail"]["time_ms"])
+    stats = stats_by[key]
     infos = [r["info"] for r in res]
     assert all(i == 0 for i in infos), infos
     iters = np.array([r["iters"] for r in res])
     trail = stats["trail"]
     achieved = trail["flops"] / (trail["time_ms"] * 1e-3) / 1e12 if trail["time_ms"] > 0 else 0.0
-    fact = ("trail", "panel", "potf2")
-    key = prec
+    fact = ("trail", "panel", "potf2", "border")
     fact_ms = sum(stats[c]["time_ms"] for c in fact)
     fact_flops = sum(stats[c]["flops"] for c in fact)
     peak = PEAK_TFLOPS[key]
@@ -144,18 +151,24 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
         "zero_start_fallbacks": int(sum((r["fallback"] >> 1) & 1 for r in res)),
         "roofline": {
             "bound": "mfma",
-            "kernel": f"gemm_update_kernel<{'double' if prec == 'fp64' else 'float'},128,128> "
-                      f"({prec.upper()} MFMA trailing update of the blocked Cholesky)",
+            "kernel": f"{TRAIL_KERNEL[key]} ({key.upper()} MFMA trailing update of the blocked Cholesky)",
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": None,
+            "precision": key,
             "launches": trail["launches"],
             "avg_launch_ms": trail["time_ms"] / max(1, trail["launches"]),
             "alg_flops_per_launch": trail["flops"] / max(1, trail["launches"]),
             "alg_bytes_per_launch": trail["bytes"] / max(1, trail["launches"]),
         },
+        "trail_kernels": {
+            p: {"kernel": TRAIL_KERNEL[p], "launches": sb["trail"]["launches"],
+                "avg_launch_ms": sb["trail"]["time_ms"] / sb["trail"]["launches"],
+                "achieved_tflops": sb["trail"]["flops"] / (sb["trail"]["time_ms"] * 1e-3) / 1e12,
+                "frac_of_peak": sb["trail"]["flops"] / (sb["trail"]["time_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[p]}
+            for p, sb in stats_by.items() if sb["trail"]["launches"] and sb["trail"]["time_ms"] > 0},
         "factorization_tflops": fact_flops / (fact_ms * 1e-3) / 1e12 if fact_ms > 0 else 0.0,
         "kernel_time_ms": {p: {name: st["time_ms"] / steps for name, st in sb.items() if st["launches"]}
                            for p, sb in stats_by.items()},
@@ -164,6 +177,8 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
 
 
 def main():
+    import faulthandler
+    faulthandler.enable()   # a crash in native code prints the Python stack that led to it
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -171,7 +186,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--ns", type=int, default=128)
     ap.add_argument("--nt", type=int, default=64)
-    ap.add_argument("--variants", default="fp64,fp32,fp32+mlp")
+    ap.add_argument("--variants", default="fp64,fp32,bf16,fp32+mlp,bf16+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rocprof-window", metavar="CSV",
                     help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
@@ -210,17 +225,22 @@ def main():
     dms = [dm] * args.batch
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.batch)]
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
-    results, train_info = {}, None
+    results, train_info, trained = {}, None, {}
     for v in variants:
         warm = None
         if v.endswith("+mlp"):
             from paper_2311_08050_amd import warmstart
+            pv = v.split("+")[0]
             centre, scale = synth.kron_theta0(args.nt), np.full(4, 0.5)
-            train = synth.normal_batch(centre, MLP_TRAIN["n_train"], 0.5, seed=MLP_TRAIN["seed"])
-            log(f"training the warm start on {len(train)} theta")
-            mlp, train_info = warmstart.train(lib, dm, train, centre, scale, hidden=MLP_TRAIN["hidden"],
-                                              epochs=MLP_TRAIN["epochs"], lr=MLP_TRAIN["lr"], prec=v.split("+")[0])
-            log(f"warm start trained: {train_info}")
+            if pv not in trained:
+                # training targets solved in the variant's own precision (its
+                # zero-start iteration mean sets the warm start's iteration cap)
+                train = synth.normal_batch(centre, MLP_TRAIN["n_train"], 0.5, seed=MLP_TRAIN["seed"])
+                log(f"training the warm start on {len(train)} theta ({pv} solves)")
+                trained[pv] = warmstart.train(lib, dm, train, centre, scale, hidden=MLP_TRAIN["hidden"],
+                                              epochs=MLP_TRAIN["epochs"], lr=MLP_TRAIN["lr"], prec=pv)
+                log(f"warm start trained: {trained[pv][1]}")
+            mlp, train_info = trained[pv]
             # a warm start that needs more iterations than the zero-start median is
             # re-solved from zero (counted in zero_start_fallbacks)
             warm = (mlp, centre, scale, int(np.ceil(train_info["zero_start_iters_mean"])))
@@ -228,7 +248,7 @@ def main():
     head = variants[-1]
     hv = results[head]
     for v in variants:
-        pv = v.split("+")[0]
+        pv = results[v]["roofline"]["precision"]
         results[v]["roofline"]["traffic"] = traffic_from_profile(
             os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"),
             os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64_traffic.md"))
@@ -243,7 +263,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if head.startswith("fp64") else "f32+f64",
+        "dtype": {"fp64": "f64", "fp32": "f32+f64", "bf16": "bf16+f32+f64"}[head.split("+")[0]],
         "data": "synthetic",
         "config": {
             "workload": f"Poisson space-time interaction, n={n} ({args.ns} regions x {args.nt} times), "

@@ -70,14 +70,25 @@ enum {
                                      R_t the unscaled first-order random walk on n_t
                                      steps, latent index t*n_s + s */
 };
-/* Precision of the Newton and final-pass factorisations.  FP64: everything in
- * FP64.  FP32: FP32 storage and FP32 MFMA (FP32 accumulate) for the blocked
- * Cholesky of Q*; the prior pass, the log-det sums, the k x k kriging system and
- * the residuals stay FP64, and every Newton solve is refined on the constrained
- * (KKT) system with FP64 residuals until the correction is below 1e-13
- * relative; a theta whose refinement does not converge within its budget is
- * re-evaluated in FP64 and flagged in inla_result.fallback. */
-enum { INLA_PREC_FP64 = 0, INLA_PREC_FP32 = 1 };
+/* Precision of the Newton and final-pass factorisations (extension to the
+ * paper's FP64 method).
+ *  FP64: everything in FP64.
+ *  FP32: FP32 storage and FP32 MFMA (FP32 accumulate) for the blocked Cholesky
+ *        of Q*.  The prior pass, the log-det sums, the k x k kriging system and
+ *        the residuals stay FP64.  Newton is run inexactly while far from the
+ *        mode; once the previous step is below 1e-3 of the iterate's scale (and
+ *        always for a Gaussian likelihood) the constrained (KKT) solve is refined
+ *        with FP64 residuals until the correction is below 1e-13 relative, and
+ *        only a refined step can end the iteration.  The last Newton factor
+ *        gives log|Q*|.  A theta whose refinement does not converge within its
+ *        budget is re-evaluated in FP64 and flagged in inla_result.fallback.
+ *  BF16: as FP32, but the factorisations of the unrefined Newton steps round
+ *        the panel operands of the trailing update of Q* to BF16 (FP32 storage,
+ *        FP32 accumulation; the border rows keep FP32 operands), and each such
+ *        step takes one refinement step with its own factor; refined steps, and
+ *        so the factor giving log|Q*|, use FP32.  inla_logdet with BF16 uses
+ *        BF16 trailing updates throughout. */
+enum { INLA_PREC_FP64 = 0, INLA_PREC_FP32 = 1, INLA_PREC_BF16 = 2, INLA_PREC_COUNT = 3 };
 
 typedef struct inla_handle inla_handle;
 
@@ -104,7 +115,7 @@ typedef struct inla_model {
  * "Gaussian Approximation"; the paper leaves norm and tolerance open, here
  * ||x_new - x||_inf <= tol * max(1, ||x_new||_inf)). */
 typedef struct inla_opts {
-  int32_t prec;      /* INLA_PREC_FP64 or INLA_PREC_FP32                             */
+  int32_t prec;      /* INLA_PREC_FP64, INLA_PREC_FP32 or INLA_PREC_BF16             */
   int32_t max_iter;  /* <= 0: 50                                                     */
   double tol;        /* <= 0: 1e-11                                                  */
   int32_t start;     /* 0: start from x = 0; 1: start from the vectors in x (a warm
@@ -151,10 +162,15 @@ int inla_set_stream(inla_handle *h, void *stream);
  *   Q        host [B] of device pointers, column-major, lower triangle read; on
  *            return the lower triangle holds L_b (strict upper triangle untouched)
  *   ldq      host [B] leading dimensions (>= max(1, n_b))
+ *   prec     INLA_PREC_FP64, or INLA_PREC_FP32 / INLA_PREC_BF16 for a factor
+ *            stored in FP32 (trailing updates with FP32 or BF16 operands, FP32
+ *            accumulation; the log-sum of the diagonal in FP64).  The returned
+ *            L is the factor converted to FP64.
  *   logdet   host [B] output
  *   info     host [B] output: 0, or j > 0 if the leading minor j is not positive
- *            definite (then logdet is NaN and Q_b holds a partial factor). */
-int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq,
+ *            definite (then logdet is NaN and Q_b holds a partial factor).
+ * Returns INLA_ERR_UNSUPPORTED for an unknown precision. */
+int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq, int32_t prec,
                 double *logdet, int32_t *info);
 
 /* Constrained Newton mode of the Gaussian approximation for B theta points
@@ -235,7 +251,9 @@ enum {
   INLA_K_POTF2 = 2,     /* diagonal-block factorisation and inversion                     */
   INLA_K_ASSEMBLE = 3,  /* prior build, Q* / border assembly, likelihood                  */
   INLA_K_SOLVE = 4,     /* triangular solves, kriging system, reductions                  */
-  INLA_K_COUNT = 5
+  INLA_K_BORDER = 5,    /* trailing update of the border rows when it runs apart from the
+                           factored rows (FP32 operands beside a BF16 trailing update) */
+  INLA_K_COUNT = 6
 };
 typedef struct inla_kstats {
   int64_t launches;  /* kernel launches recorded                              */
@@ -247,10 +265,11 @@ typedef struct inla_kstats {
  * counters.  Timing adds an event pair per launch. */
 int inla_profile(inla_handle *h, int32_t enable);
 /* Read the counters of kernel class `kclass` for the launches enqueued by
- * passes run at precision `prec` (INLA_PREC_FP64 or INLA_PREC_FP32), collected
+ * passes run at precision `prec` (an INLA_PREC_* value), collected
  * up to the last completed call.  A mixed-precision evaluation files its FP64
  * prior pass under INLA_PREC_FP64 and its Newton and final passes (including
- * their FP64 residual kernels) under INLA_PREC_FP32.  Returns -2 for an unknown
+ * their FP64 residual kernels) under INLA_PREC_FP32, except the BF16-trailing
+ * factorisations of a BF16 evaluation, filed under INLA_PREC_BF16.  Returns -2 for an unknown
  * class, -3 for an unknown precision, -4 for a null `out`. */
 int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *out);
 

@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libinla_dense.so")
 
 LIK = {"gaussian": 0, "poisson": 1}
 PRIOR = {"dense": 0, "expcov": 1, "kron": 2}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 N_PRIOR_PARAMS = {"dense": 0, "expcov": 2, "kron": 3}
 
 INFO_OK = 0
@@ -24,8 +24,9 @@ INFO_NEWTON_MAXIT = -1
 INFO_CONSTRAINT_RANK = -2
 INFO_NONFINITE = -3
 
-K_TRAIL, K_PANEL, K_POTF2, K_ASSEMBLE, K_SOLVE = 0, 1, 2, 3, 4
-K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve"}
+K_TRAIL, K_PANEL, K_POTF2, K_ASSEMBLE, K_SOLVE, K_BORDER = 0, 1, 2, 3, 4, 5
+K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve",
+           K_BORDER: "border"}
 
 # Symbols declared by include/inla_dense.h
 EXPORTS = [
@@ -76,7 +77,7 @@ def load_library(path: str = LIBPATH):
     lib.inla_create.argtypes = [C.POINTER(P), P]
     lib.inla_destroy.argtypes = [P]
     lib.inla_set_stream.argtypes = [P, P]
-    lib.inla_logdet.argtypes = [P, i32, pi32, C.POINTER(P), pi32, pd, pi32]
+    lib.inla_logdet.argtypes = [P, i32, pi32, C.POINTER(P), pi32, i32, pd, pi32]
     for f in (lib.inla_constrained_mode, lib.inla_laplace_eval):
         f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
     lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
@@ -167,17 +168,18 @@ class Library:
             raise LibraryError(f"{what} returned {rc}")
 
     # ------------------------------------------------------------- entry points
-    def logdet(self, mats):
+    def logdet(self, mats, prec="fp64"):
         """log|Q_b| for a list of square float64 device tensors (C-order symmetric
         matrices; C order is the column-major transpose, identical for symmetric
-        input).  Overwrites their lower (column-major) triangle with L."""
+        input).  Overwrites their lower (column-major) triangle with L (the FP32
+        factor converted to FP64 for prec "fp32" or "bf16")."""
         B = len(mats)
         n = (C.c_int32 * B)(*[int(m.shape[0]) for m in mats])
         ld = (C.c_int32 * B)(*[max(1, int(m.shape[0])) for m in mats])
         ptrs = (C.c_void_p * B)(*[m.data_ptr() for m in mats])
         out = (C.c_double * B)()
         info = (C.c_int32 * B)()
-        rc = self.lib.inla_logdet(self.h, B, n, ptrs, ld, out, info)
+        rc = self.lib.inla_logdet(self.h, B, n, ptrs, ld, PREC[prec], out, info)
         self._check(rc, "inla_logdet")
         return np.array(out[:]), np.array(info[:], dtype=np.int32)
 

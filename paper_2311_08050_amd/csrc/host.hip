@@ -62,7 +62,7 @@ void Ctx::launch(int cls, double flops, double bytes, const std::function<void()
   (void)hipEventRecord(a, stream);
   f();
   (void)hipEventRecord(b, stream);
-  pending.push_back({a, b, cls, prec_tag == INLA_PREC_FP32 ? 1 : 0, flops, bytes});
+  pending.push_back({a, b, cls, prec_tag, flops, bytes});
   if (pending.size() >= 8192) harvest();
 }
 
@@ -322,14 +322,16 @@ static int prior_build(Batch &b, const std::vector<int> &ids) {
 // One pass: assemble the bordered matrix at the current x, factor it, build and
 // factor the kriging system, solve it; then (Newton) form the corrected
 // right-hand side and back-substitute, or (prior / final) reduce the log-dets.
-enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2 };
+// PASS_STEP: a Newton step in correction form (factor and kriging system only;
+// the correction itself is one refinement step from the current iterate).
+enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2, PASS_STEP = 3 };
 static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) {
   PrecScope tag(b.ctx, prec);
   if (ids.empty()) return 0;
   ThetaDesc *d = upload_td(b, ids);
   if (!d) return INLA_ERR_NOMEM;
   const int B = (int)ids.size();
-  const double esz = prec == INLA_PREC_FP32 ? 4.0 : 8.0;
+  const double esz = prec != INLA_PREC_FP64 ? 4.0 : 8.0;
   double abytes = 0, tbytes = 0;
   for (int i : ids) {
     const ThetaDesc &t = b.plans[i].t;
@@ -348,6 +350,8 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
     launch_rhs(b.ctx, d, B, npm, 0, prec);
     launch_trsv_bwd(b.ctx, d, B, npm, V_R, V_XN, tbytes, prec);
     if (prec == INLA_PREC_FP64) launch_newton_accept(b.ctx, d, B);
+  } else if (pass == PASS_STEP) {
+    launch_restart(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad));
   } else {
     launch_finish(b.ctx, d, B, prec);
   }
@@ -361,7 +365,7 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
                   std::vector<int> &steps) {
   PrecScope tag(b.ctx, prec);
   std::vector<int> act = ids;
-  const double esz = prec == INLA_PREC_FP32 ? 4.0 : 8.0;
+  const double esz = prec != INLA_PREC_FP64 ? 4.0 : 8.0;
   for (int s = 1; s <= max_ir && !act.empty(); ++s) {
     ThetaDesc *d = upload_td(b, act);
     if (!d) return INLA_ERR_NOMEM;
@@ -489,6 +493,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   const bool warm = opts && opts->start == 1;
   const int prec = opts ? opts->prec : INLA_PREC_FP64;
   const bool mixed = prec != INLA_PREC_FP64;
+  const int ref_prec = prec == INLA_PREC_BF16 ? INLA_PREC_FP32 : prec;   // refined steps and the final pass
   const int max_ir = 10;
   const double tol_ir = 1e-13;
   std::vector<int> all, ok;
@@ -529,19 +534,38 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   // first assembly: a non-finite W or b sets the flag).
   std::vector<int> active = ok, done, redo;
   std::vector<char> failed(B, 0);
-  std::vector<int> irsteps(B, 0), last_ir(B, 0);
+  std::vector<int> irsteps(B, 0), last_ir(B, 0), far_ir(B, 0);
   std::vector<double> prev_step(B, INFINITY), prev_scale(B, 1.0);
   for (int it = 1; it <= max_iter && !active.empty(); ++it) {
     if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
-    if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
-    if (mixed) {
+    if (!mixed) {
+      if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
+    } else {
       // Inexact Newton far from the mode; refinement to FP64 accuracy once the
-      // previous step is below 1e-3 of the iterate's scale.
-      std::vector<int> ref, nconv;
-      // (a Gaussian likelihood's single Newton step is exact, so it is always refined)
+      // previous step is below 1e-3 of the iterate's scale (a Gaussian
+      // likelihood's single Newton step is exact, so it is always refined).
+      // In BF16 mode the unrefined steps factor with BF16 trailing operands and
+      // the refined ones with FP32.
+      std::vector<int> ref, far, nconv;
       for (int i : active)
-        if (b.plans[i].t.lik == LIK_GAUSSIAN || prev_step[i] <= 1e-3 * prev_scale[i]) ref.push_back(i);
-      if ((rc = refine(b, ref, prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
+        (b.plans[i].t.lik == LIK_GAUSSIAN || prev_step[i] <= 1e-3 * prev_scale[i] ? ref : far).push_back(i);
+      if (prec == INLA_PREC_BF16) {
+        // Solved for the whole next iterate, a step with a BF16 factor would
+        // carry an error of order kappa u_bf16 |x| that never shrinks with the
+        // step, so these steps are taken in correction form: x + the solution
+        // of the KKT system with the FP64 residual at x (one refinement step
+        // from x), whose error is of order kappa u_bf16 times the step.  Such
+        // steps do not count as refined ones.
+        if (!far.empty()) {
+          std::vector<int> unconv;
+          if ((rc = run_pass(b, far, PASS_STEP, INLA_PREC_BF16))) return fail(rc);
+          if ((rc = refine(b, far, INLA_PREC_BF16, 1, 0.0, unconv, far_ir))) return fail(rc);
+        }
+        if (!ref.empty() && (rc = run_pass(b, ref, PASS_NEWTON, ref_prec))) return fail(rc);
+      } else if ((rc = run_pass(b, active, PASS_NEWTON, prec))) {
+        return fail(rc);
+      }
+      if ((rc = refine(b, ref, ref_prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
       for (int i : nconv) { failed[i] = 1; redo.push_back(i); }
       std::vector<int> keep;
       for (int i : active) if (!failed[i]) keep.push_back(i);
@@ -586,13 +610,13 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       // The last Newton factorisation was taken at an iterate within the Newton
       // tolerance (1e-11) of the mode; its log-dets differ from a refactorisation
       // at the mode by far less than the FP32 factor's own error, so it is reused.
-      PrecScope tag(ctx, prec);
+      PrecScope tag(ctx, ref_prec);
       ThetaDesc *d = upload_td(b, fin);
       if (!fin.empty() && !d) return fail(INLA_ERR_NOMEM);
       double by = 0;
       for (int i : fin) by += 8.0 * b.plans[i].t.n * (double)b.plans[i].t.n;
       launch_objective_terms(ctx, d, (int)fin.size(), max_over(b, fin, &ThetaDesc::n_pad), by);
-      launch_finish(ctx, d, (int)fin.size(), prec);
+      launch_finish(ctx, d, (int)fin.size(), ref_prec);
     } else if ((rc = run_pass(b, fin, PASS_FINAL, prec))) {
       return fail(rc);
     }
@@ -613,7 +637,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   } else {
     if (hipStreamSynchronize(ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
   }
-  for (int i = 0; i < B; ++i) res[i].ir_steps = irsteps[i];
+  for (int i = 0; i < B; ++i) res[i].ir_steps = irsteps[i] + far_ir[i];
   ctx.harvest();
   teardown(b);
   if ((rc = ctx.check())) return rc;
@@ -724,22 +748,25 @@ int inla_set_stream(inla_handle *h, void *stream) {
   return INLA_OK;
 }
 
-int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq, double *logdet,
-                int32_t *info) {
+int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq, int32_t prec,
+                double *logdet, int32_t *info) {
   if (!h) return -1;
   if (B < 0) return -2;
   if (B == 0) return INLA_OK;
   if (!n) return -3;
   if (!Q) return -4;
   if (!ldq) return -5;
-  if (!logdet) return -6;
-  if (!info) return -7;
+  if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
+  if (!logdet) return -7;
+  if (!info) return -8;
   for (int i = 0; i < B; ++i) {
     if (n[i] < 0) return -3;
     if (n[i] > 0 && !Q[i]) return -4;
     if (ldq[i] < std::max(1, n[i])) return -5;
   }
   Ctx &ctx = h->ctx;
+  PrecScope tag(ctx, prec);
+  const size_t esz = prec == INLA_PREC_FP64 ? 8 : 4;
   // one chunk per memory budget
   const size_t cap = budget(ctx);
   int s = 0;
@@ -749,7 +776,7 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
     int e = s;
     for (; e < B; ++e) {
       const int np = round_up(std::max(n[e], 1), PADN);
-      const size_t need = align256(8ull * np * np) + align256(8ull * (2 * np + 64 + 2 * np + DRES_COUNT)) + align256(8ull * np * NBI);
+      const size_t need = align256(esz * np * np) + align256(8ull * (2 * np + 64 + 2 * np + DRES_COUNT)) + align256(esz * np * NBI);
       if (e > s && tot + need > cap) break;
       tot += need;
     }
@@ -765,9 +792,9 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
       t.Quser = Q[s + i]; t.ldquser = ldq[s + i];
       t.ldw = t.Nw = t.Ncw = t.n_pad;
       size_t off = 0;
-      p.off_W = off; off += align256(8ull * t.n_pad * t.n_pad);
+      p.off_W = off; off += align256(esz * t.n_pad * t.n_pad);
       p.off_vec = off; off += align256(8ull * (2 * t.n_pad + 64 + 2 * t.ldw + DRES_COUNT));
-      p.off_linv = off; off += align256(8ull * t.n_pad * NBI);
+      p.off_linv = off; off += align256(esz * t.n_pad * NBI);
       p.bytes = off;
       offs[i] = total; total += off;
     }
@@ -794,10 +821,10 @@ int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, c
     if (!ids2.empty()) {
       ThetaDesc *d = upload_td(b, ids2);
       if (!d) { teardown(b); return INLA_ERR_NOMEM; }
-      launch_copy_in(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n_pad));
-      if ((rc = run_factor(b, ids2, F_BIG, MODE_LOGDET))) { teardown(b); return rc; }
-      launch_finish(ctx, d, (int)ids2.size(), INLA_PREC_FP64);
-      launch_copy_out(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n));
+      launch_copy_in(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n_pad), prec);
+      if ((rc = run_factor(b, ids2, F_BIG, MODE_LOGDET, prec))) { teardown(b); return rc; }
+      launch_finish(ctx, d, (int)ids2.size(), prec);
+      launch_copy_out(ctx, d, (int)ids2.size(), max_over(b, ids2, &ThetaDesc::n), prec);
     }
     if ((rc = readback(b))) { teardown(b); return rc; }
     for (int i = 0; i < Bc; ++i) {
@@ -819,7 +846,7 @@ static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, con
   if (B == 0) return INLA_OK;
   if (!x) return -6;
   for (int i = 0; i < B; ++i) if (!x[i]) return -6;
-  if (opts && opts->prec != INLA_PREC_FP64 && opts->prec != INLA_PREC_FP32) return INLA_ERR_UNSUPPORTED;
+  if (opts && (opts->prec < 0 || opts->prec >= INLA_PREC_COUNT)) return INLA_ERR_UNSUPPORTED;
   for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
     rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
                     x + c.first, opts, res + c.first, laplace);
@@ -898,10 +925,10 @@ int inla_profile(inla_handle *h, int32_t enable) {
 int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *out) {
   if (!h) return -1;
   if (kclass < 0 || kclass >= INLA_K_COUNT) return -2;
-  if (prec != INLA_PREC_FP64 && prec != INLA_PREC_FP32) return -3;
+  if (prec < 0 || prec >= INLA_PREC_COUNT) return -3;
   if (!out) return -4;
   h->ctx.harvest();
-  *out = h->ctx.stats[kclass][prec == INLA_PREC_FP32 ? 1 : 0];
+  *out = h->ctx.stats[kclass][prec];
   return INLA_OK;
 }
 

@@ -34,7 +34,7 @@ struct Ctx {
   // profiling
   bool prof = false;
   int prec_tag = INLA_PREC_FP64;  // precision of the pass being enqueued
-  inla_kstats stats[INLA_K_COUNT][2] = {};
+  inla_kstats stats[INLA_K_COUNT][INLA_PREC_COUNT] = {};
   struct Pending { hipEvent_t a, b; int cls, prec; double flops, bytes; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;

@@ -140,6 +140,88 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
   if (tid == 0 && fail != 0 && *d.info == 0) *d.info = j + fail;
 }
 
+// Tile of one update launch for blockIdx.x: rows/columns of the C tile and the
+// K range [ks, ke).  TRSM launches enumerate row tiles of the block column;
+// PANEL and TRAIL launches enumerate the lower-triangular tiles of the updated
+// block (square part first, then the rectangle below).  Returns false when the
+// workgroup has no tile, its tile reads identity border rows (or columns)
+// that are still zero over [ks, ke), or the row selection excludes it
+// (sel: 0 every tile, 1 tiles of the factored rows (row < nf), 2 tiles of the
+// border rows (row >= nf)).
+__device__ __forceinline__ bool update_tile(const FactorDesc &d, int kind, int p0, int nb, int j, int TM, int TN,
+                                            int sel, int &row0, int &col0, int &ks, int &ke) {
+  if (j >= d.nf) return false;
+  const int pend = min(p0 + nb, d.nf);
+  int r0, c0, cend;
+  if (kind == KIND_TRSM) {
+    r0 = j + NBI; c0 = j; cend = j + NBI; ks = j; ke = j + NBI;
+  } else if (kind == KIND_PANEL) {
+    r0 = j + NBI; c0 = j + NBI; cend = pend; ks = j; ke = j + NBI;
+  } else {
+    r0 = pend; c0 = pend; cend = d.ncols; ks = p0; ke = pend;
+  }
+  if (r0 >= d.nrows || c0 >= cend) return false;
+  const int nr = (d.nrows - r0) / TM;
+  int I, J;
+  if (kind == KIND_TRSM) {
+    if ((int)blockIdx.x >= nr) return false;
+    I = blockIdx.x; J = 0;
+  } else {
+    const int nc = (cend - c0) / TN;
+    const int tri = nc * (nc + 1) / 2;
+    const int t = blockIdx.x;
+    if (t >= tri + (nr - nc) * nc) return false;
+    if (t < tri) {
+      int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while (i * (i + 1) / 2 > t) --i;
+      while ((i + 1) * (i + 2) / 2 <= t) ++i;
+      I = i; J = t - i * (i + 1) / 2;
+    } else {
+      const int u = t - tri;
+      I = nc + u / nc; J = u % nc;
+    }
+  }
+  row0 = r0 + I * TM;
+  col0 = c0 + J * TN;
+  if ((sel == 1 && row0 >= d.nf) || (sel == 2 && row0 < d.nf)) return false;
+  if (row0 >= d.id_row0 && row0 - d.id_row0 >= ke) return false;
+  if (kind != KIND_TRSM && col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return false;
+  return true;
+}
+
+// C -= acc for one wave's BM x BN accumulator blocks (tile coordinates from rl,
+// cl).  A tile that straddles the diagonal touches only its lower triangle.
+template <typename T, int BM, int BN, typename Acc, typename RL, typename CL>
+__device__ __forceinline__ void subtract_tile(__attribute__((address_space(1))) T *Cg, int ld, Acc (&acc)[BM][BN],
+                                              RL rl, CL cl, bool diag_tile, int row0, int col0) {
+  if (!diag_tile) {
+#pragma unroll
+    for (int a = 0; a < BM; ++a) {
+      T cv[BN][4];
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cv[b][v] = Cg[(size_t)cl(b, v) * ld + rl(a, v)];
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = cv[b][v] - acc[a][b][v];
+    }
+  } else {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (row0 + rl(a, v) >= col0 + cl(b, v)) {
+            __attribute__((address_space(1))) T *p = Cg + (size_t)cl(b, v) * ld + rl(a, v);
+            *p = *p - acc[a][b][v];
+          }
+        }
+  }
+}
+
 // --------------------------------------------------------------------------
 // MFMA tile update.  C(TM x TN) = or -= A(TM x K) B(TN x K)^T, A and B read from
 // column-major storage (element (r, k) at base[k*ld + r]).
@@ -157,7 +239,7 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
 // --------------------------------------------------------------------------
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
-                                                             int p0, int nb, int j) {
+                                                             int p0, int nb, int j, int sel) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int KCH = F64 ? 16 : 32;            // K chunk staged per LDS buffer
   constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte global load
@@ -175,41 +257,8 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   __shared__ __attribute__((aligned(16))) T Bs[2][KCH][TN + PAD];
 
   const FactorDesc d = descs[blockIdx.y];
-  if (j >= d.nf) return;
-  const int pend = min(p0 + nb, d.nf);
-  int r0, c0, cend, ks, ke;
-  if (kind == KIND_TRSM) {
-    r0 = j + NBI; c0 = j; cend = j + NBI; ks = j; ke = j + NBI;
-  } else if (kind == KIND_PANEL) {
-    r0 = j + NBI; c0 = j + NBI; cend = pend; ks = j; ke = j + NBI;
-  } else {
-    r0 = pend; c0 = pend; cend = d.ncols; ks = p0; ke = pend;
-  }
-  if (r0 >= d.nrows || c0 >= cend) return;
-  const int nr = (d.nrows - r0) / TM;
-  int I, J;
-  if (kind == KIND_TRSM) {
-    if ((int)blockIdx.x >= nr) return;
-    I = blockIdx.x; J = 0;
-  } else {
-    const int nc = (cend - c0) / TN;
-    const int tri = nc * (nc + 1) / 2;
-    const int t = blockIdx.x;
-    if (t >= tri + (nr - nc) * nc) return;
-    if (t < tri) {
-      int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (i * (i + 1) / 2 > t) --i;
-      while ((i + 1) * (i + 2) / 2 <= t) ++i;
-      I = i; J = t - i * (i + 1) / 2;
-    } else {
-      const int u = t - tri;
-      I = nc + u / nc; J = u % nc;
-    }
-  }
-  const int row0 = r0 + I * TM, col0 = c0 + J * TN;
-  // identity border rows (or columns) that are still zero over [ks, ke) contribute nothing
-  if (row0 >= d.id_row0 && row0 - d.id_row0 >= ke) return;
-  if (kind != KIND_TRSM && col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return;
+  int row0, col0, ks, ke;
+  if (!update_tile(d, kind, p0, nb, j, TM, TN, sel, row0, col0, ks, ke)) return;
 
   const int ld = d.ld;
   gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
@@ -295,33 +344,111 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
       for (int b = 0; b < BN; ++b)
 #pragma unroll
         for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = acc[a][b][v];
-  } else if (!diag_tile) {
-#pragma unroll
-    for (int a = 0; a < BM; ++a) {
-      T cv[BN][4];
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) cv[b][v] = Cg[(size_t)cl(b, v) * ld + rl(a, v)];
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = cv[b][v] - acc[a][b][v];
-    }
   } else {
-    // diagonal tile: only the lower triangle (row >= col) is touched
-#pragma unroll
-    for (int a = 0; a < BM; ++a)
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          if (row0 + rl(a, v) >= col0 + cl(b, v)) {
-            gT *p = Cg + (size_t)cl(b, v) * ld + rl(a, v);
-            *p = *p - acc[a][b][v];
-          }
-        }
+    subtract_tile<T, BM, BN>(Cg, ld, acc, rl, cl, diag_tile, row0, col0);
   }
+}
+
+// --------------------------------------------------------------------------
+// Trailing update with BF16 operands: FP32 storage, the panel values rounded to
+// BF16 (round to nearest even) on their way into LDS, v_mfma_f32_16x16x32_bf16
+// with FP32 accumulation, FP32 read-modify-write of C.  That instruction takes
+// in lane l the row (l%16) of A and the column (l%16) of B^T at the eight k
+// values 8(l/16) .. 8(l/16)+7, and returns D rows 4(l/16)+v of column (l%16)
+// (the FP32 layout, so the epilogue is shared).
+//
+// Staging: a K chunk of 64 is 8 groups of 8 k values.  Thread (row quad q,
+// group g) loads four consecutive rows at the group's 8 k values with 16-byte
+// loads (a half-wave covers 512 contiguous bytes per k), transposes them in
+// registers and writes each row's eight BF16 values as one 16-byte LDS entry.
+// LDS holds entry [g][row] at slot row ^ ((row >> 4) & 3): the four rows a
+// lane writes per instruction and the sixteen rows a quarter-wave reads then
+// fall into distinct 16-byte slots of a 256-byte bank window.
+// --------------------------------------------------------------------------
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ int bf_slot(int r) { return r ^ ((r >> 4) & 3); }
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__restrict__ descs, int p0, int nb) {
+  constexpr int KCH = 64, KG = KCH / 8;
+  constexpr int WM = 2, WN = 2, WTM = TM / WM, WTN = TN / WN, BM = WTM / 16, BN = WTN / 16;
+  constexpr int QA = TM / 4, QB = TN / 4;              // row quads per K group
+  static_assert(QA * KG == 256 && QB * KG == 256, "one row quad of A and of B per thread");
+  typedef __attribute__((address_space(1))) float gT;
+  typedef __attribute__((address_space(1))) const float gcT;
+  typedef __attribute__((address_space(1))) const f4 gcf4;
+  __shared__ bf8 As[2][KG][TM];
+  __shared__ bf8 Bs[2][KG][TN];
+
+  const FactorDesc d = descs[blockIdx.y];
+  int row0, col0, ks, ke;
+  if (!update_tile(d, KIND_TRAIL, p0, nb, p0, TM, TN, 1, row0, col0, ks, ke)) return;
+  const int ld = d.ld;
+  gcT *Ag = gptr((const float *)d.A) + (size_t)ks * ld + row0;
+  gcT *Bg = gptr((const float *)d.A) + (size_t)ks * ld + col0;
+  gT *Cg = gptr((float *)d.A) + (size_t)col0 * ld + row0;
+  const int K = ke - ks;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w / WN, wn = w % WN;
+  const int g = lane >> 4, li = lane & 15;
+  const int qa = tid % QA, ga = tid / QA, qb = tid % QB, gb = tid / QB;
+
+  f4 acc[BM][BN];
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b) acc[a][b] = f4{0, 0, 0, 0};
+
+  f4 ra[8], rb[8];
+  auto gload = [&](int kc) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ra[i] = *reinterpret_cast<gcf4 *>(Ag + (size_t)(kc + 8 * ga + i) * ld + 4 * qa);
+      rb[i] = *reinterpret_cast<gcf4 *>(Bg + (size_t)(kc + 8 * gb + i) * ld + 4 * qb);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      bf8 va, vb;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        va[i] = (__bf16)ra[i][rr];
+        vb[i] = (__bf16)rb[i][rr];
+      }
+      As[buf][ga][bf_slot(4 * qa + rr)] = va;
+      Bs[buf][gb][bf_slot(4 * qb + rr)] = vb;
+    }
+  };
+
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int kc = 0; kc < K; kc += KCH) {
+    const bool more = kc + KCH < K;
+    if (more) gload(kc + KCH);
+#pragma unroll
+    for (int s = 0; s < KCH / 32; ++s) {
+      bf8 ya[BM], xb[BN];
+#pragma unroll
+      for (int a = 0; a < BM; ++a) ya[a] = As[buf][4 * s + g][bf_slot(wm * WTM + a * 16 + li)];
+#pragma unroll
+      for (int b = 0; b < BN; ++b) xb[b] = Bs[buf][4 * s + g][bf_slot(wn * WTN + b * 16 + li)];
+#pragma unroll
+      for (int a = 0; a < BM; ++a)
+#pragma unroll
+        for (int b = 0; b < BN; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ya[a], xb[b], acc[a][b], 0, 0, 0);
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  auto rl = [&](int a, int v) { return wm * WTM + a * 16 + 4 * g + v; };
+  auto cl = [&](int b, int v) { (void)v; return wn * WTN + b * 16 + li; };
+  subtract_tile<float, BM, BN>(Cg, ld, acc, rl, cl, row0 < col0 + TN, row0, col0);
 }
 
 // --------------------------------------------------------------------------
@@ -361,7 +488,7 @@ static int tiles_for(const FactorDesc &d, int kind, int p0, int nb, int j, int T
 }
 
 template <typename T>
-static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
+static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, bool bf16_trail) {
   const int B = (int)fs.size();
   if (B == 0) return 0;
   const double esz = sizeof(T);
@@ -414,13 +541,13 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
         if (gx == 0) continue;
         ctx.launch(INLA_K_PANEL, fl, by, [&] {
           hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
-                             nb, j);
+                             nb, j, 0);
         });
       }
     }
     const int act = active(p0);
     int gx = 0;
-    double fl = 0, by = 0;
+    double fl = 0, by = 0, fl_q = 0, by_q = 0;   // all tiles; tiles of the factored rows only
     for (int i = 0; i < act; ++i) {
       const HostFactor &h = fs[order[i]];
       gx = std::max(gx, tiles_for(h.d, KIND_TRAIL, p0, nb, p0, 128));
@@ -431,20 +558,39 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb) {
         fl += 2.0 * trap_elems(nr, nc) * kr;
         by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
       }
+      const double nq = std::max(0, h.n_real - pend);
+      fl_q += 2.0 * trap_elems(nq, nq) * kr;
+      by_q += nq > 0 ? 2.0 * esz * trap_elems(nq, nq) + esz * 2.0 * nq * kr : 0.0;
     }
-    if (gx > 0)
-      ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-        hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
-                           KIND_TRAIL, p0, nb, p0);
-      });
+    if (gx > 0) {
+      bool split = false;
+      if constexpr (std::is_same<T, float>::value) split = bf16_trail;
+      if (split) {
+        // BF16 operands for the factored rows only: the border rows carry the
+        // constraint rows and the right-hand side, whose Schur block (C Q^{-1}
+        // C^T and C Q^{-1} b) arises by cancellation and keeps FP32 operands
+        ctx.launch(INLA_K_TRAIL, fl_q, by_q, [&] {
+          hipLaunchKernelGGL((trail_bf16_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, p0, nb);
+        });
+        ctx.launch(INLA_K_BORDER, fl - fl_q, by - by_q, [&] {
+          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                             KIND_TRAIL, p0, nb, p0, 2);
+        });
+      } else {
+        ctx.launch(INLA_K_TRAIL, fl, by, [&] {
+          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                             KIND_TRAIL, p0, nb, p0, 0);
+        });
+      }
+    }
   }
   return ctx.check();
 }
 
 int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec) {
   PrecScope tag(ctx, prec);
-  if (prec == INLA_PREC_FP32) return factor_batch_t<float>(ctx, fs, nb);
-  return factor_batch_t<double>(ctx, fs, nb);
+  if (prec == INLA_PREC_FP64) return factor_batch_t<double>(ctx, fs, nb, false);
+  return factor_batch_t<float>(ctx, fs, nb, prec == INLA_PREC_BF16);
 }
 
 }  // namespace inla

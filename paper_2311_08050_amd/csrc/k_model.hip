@@ -293,7 +293,7 @@ void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_
                      double bytes, int prec) {
   if (B <= 0 || N_max <= 0) return;
   ctx.launch(INLA_K_ASSEMBLE, 0.0, bytes, [&] {
-    if (prec == INLA_PREC_FP32)
+    if (prec != INLA_PREC_FP64)
       hipLaunchKernelGGL(assemble_kernel<float>, dim3(N_max, B), dim3(256), 0, ctx.stream, dtd, with_lik, want_xqx,
                          border);
     else
@@ -304,7 +304,7 @@ void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_
 void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec) {
   if (B <= 0 || kp_max <= 0) return;
   ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
-    if (prec == INLA_PREC_FP32)
+    if (prec != INLA_PREC_FP64)
       hipLaunchKernelGGL(kriging_build_kernel<float>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);
     else
       hipLaunchKernelGGL(kriging_build_kernel<double>, dim3(kp_max, B), dim3(256), 0, ctx.stream, dtd);

@@ -223,6 +223,14 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
   }
 }
 
+// A Newton step taken in correction form starts its new iterate at the current
+// one (xn <- x); one refinement step then adds the constrained correction.
+__global__ __launch_bounds__(256) void restart_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < t.n_pad) t.xn[i] = t.x[i];
+}
+
 // Accept the refined iterate: Newton stopping quantities and x <- xn.
 __global__ __launch_bounds__(256) void newton_accept_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.x];
@@ -386,23 +394,26 @@ __global__ __launch_bounds__(256) void finish_kernel(const ThetaDesc *__restrict
   }
 }
 
-// Caller matrix (t.Quser, ld t.ldquser, order n) -> working matrix, identity padded.
+// Caller matrix (t.Quser, ld t.ldquser, order n) -> working matrix (storage T),
+// identity padded.
+template <typename T>
 __global__ __launch_bounds__(256) void copy_in_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= t.Nw) return;
-  double *col = (double *)t.W + (size_t)c * t.ldw;
+  T *col = (T *)t.W + (size_t)c * t.ldw;
   const double *src = t.Quser + (size_t)c * t.ldquser;
-  for (int r = c + threadIdx.x; r < t.Nw; r += 256) col[r] = (r < t.n && c < t.n) ? src[r] : (r == c ? 1.0 : 0.0);
+  for (int r = c + threadIdx.x; r < t.Nw; r += 256) col[r] = (T)((r < t.n && c < t.n) ? src[r] : (r == c ? 1.0 : 0.0));
 }
-// Factor -> caller matrix (lower triangle only).
+// Factor -> caller matrix (lower triangle only, as FP64).
+template <typename T>
 __global__ __launch_bounds__(256) void copy_out_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
   if (c >= t.n) return;
-  const double *col = (const double *)t.W + (size_t)c * t.ldw;
+  const T *col = (const T *)t.W + (size_t)c * t.ldw;
   double *dst = (double *)t.Quser + (size_t)c * t.ldquser;
-  for (int r = c + threadIdx.x; r < t.n; r += 256) dst[r] = col[r];
+  for (int r = c + threadIdx.x; r < t.n; r += 256) dst[r] = (double)col[r];
 }
 
 // Marginal variances, small system: S = -Schur(C, C) with the border rows
@@ -446,7 +457,7 @@ __global__ __launch_bounds__(256) void var_norms_kernel(const ThetaDesc *__restr
 // ------------------------------------------------------------------ launchers
 #define INLA_DISPATCH_T(prec, KERNEL, ...)                                        \
   do {                                                                            \
-    if ((prec) == INLA_PREC_FP32) hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__); \
+    if ((prec) != INLA_PREC_FP64) hipLaunchKernelGGL(KERNEL<float>, __VA_ARGS__); \
     else hipLaunchKernelGGL(KERNEL<double>, __VA_ARGS__);                        \
   } while (0)
 
@@ -478,6 +489,12 @@ void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src,
     });
   }
 }
+void launch_restart(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+  if (B <= 0 || np_max <= 0) return;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(restart_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dtd);
+  });
+}
 void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B) {
   if (B <= 0) return;
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] { hipLaunchKernelGGL(newton_accept_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd); });
@@ -500,13 +517,17 @@ void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec) {
     INLA_DISPATCH_T(prec, finish_kernel, dim3(B), dim3(256), 0, ctx.stream, dtd);
   });
 }
-void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
+void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int prec) {
   if (B <= 0 || np_max <= 0) return;
-  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] { hipLaunchKernelGGL(copy_in_kernel, dim3(np_max, B), dim3(256), 0, ctx.stream, dtd); });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    INLA_DISPATCH_T(prec, copy_in_kernel, dim3(np_max, B), dim3(256), 0, ctx.stream, dtd);
+  });
 }
-void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max) {
+void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max, int prec) {
   if (B <= 0 || n_max <= 0) return;
-  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] { hipLaunchKernelGGL(copy_out_kernel, dim3(n_max, B), dim3(256), 0, ctx.stream, dtd); });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    INLA_DISPATCH_T(prec, copy_out_kernel, dim3(n_max, B), dim3(256), 0, ctx.stream, dtd);
+  });
 }
 void launch_var_small_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max) {
   if (B <= 0 || kp_max <= 0) return;

@@ -25,12 +25,13 @@ void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, i
 enum { V_X = 0, V_R = 1, V_XN = 2, V_Z = 3, V_U = 4 };   // vector selectors of the solves
 void launch_trsv_fwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
 void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
+void launch_restart(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
 void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_ir_correct(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);
 void launch_ir_update(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_finish(Ctx &ctx, const ThetaDesc *dtd, int B, int prec);
-void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
-void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max);
+void launch_copy_in(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int prec);
+void launch_copy_out(Ctx &ctx, const ThetaDesc *dtd, int B, int n_max, int prec);
 void launch_var_small_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max);
 void launch_var_norms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
 

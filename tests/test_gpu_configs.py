@@ -119,11 +119,38 @@ def test_n16384_fp64_and_mixed(lib):
     assert mode_err <= RTOL
     assert rel(r32["logdet_qstar"], r64["logdet_qstar"]) <= LOGDET_RTOL
     assert rel(r32["objective"], r64["objective"]) <= LOGDET_RTOL
+    say("n=16384: BF16 trailing operands on the unrefined Newton steps")
+    rbf, xbf = lib.laplace_eval([dm], th0[None, :], prec="bf16")
+    rbf, xbf = rbf[0], xbf[0].cpu().numpy()
+    assert rbf["info"] == 0 and rbf["fallback"] == 0
+    mode_err = np.max(np.abs(xbf - x64)) / max(1.0, np.max(np.abs(x64)))
+    say(f"n=16384 BF16 vs FP64: mode {mode_err:.2e}, log|Q*| {rel(rbf['logdet_qstar'], r64['logdet_qstar']):.2e}, "
+        f"objective {rel(rbf['objective'], r64['objective']):.2e}, iterations {rbf['iters']} (FP64 {r64['iters']})")
+    assert mode_err <= RTOL
+    assert rel(rbf["logdet_qstar"], r64["logdet_qstar"]) <= LOGDET_RTOL
+    assert rel(rbf["objective"], r64["objective"]) <= LOGDET_RTOL
+    # log|Q*| at the mode from a single factorisation in each precision (BF16:
+    # trailing operands BF16 throughout), against the FP64 factorisation
+    import torch
+    Q = O.prior_precision(model, th0)
+    Q[np.diag_indices_from(Q)] += model["E"] * np.exp(th0[3] + x64)
+    Qd = torch.tensor(Q).cuda()
+    del Q
+    lds = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        ld, inf = lib.logdet([Qd.clone()], prec=prec)
+        assert inf[0] == 0
+        lds[prec] = ld[0]
+    say(f"n=16384 log|Q*| relative error vs FP64 factorisation: FP32 {rel(lds['fp32'], lds['fp64']):.2e}, "
+        f"BF16 trailing {rel(lds['bf16'], lds['fp64']):.2e}")
+    assert rel(lds["fp64"], r64["logdet_qstar"]) <= 1e-10
+    assert rel(lds["fp32"], lds["fp64"]) <= 1e-6
+    assert rel(lds["bf16"], lds["fp64"]) <= 1e-4
+    del Qd
     # the 9-point finite-difference batch (theta0 and theta0 +- h e_j), both precisions
     h = 0.01
     batch = np.stack([th0] + [th0 + s * h * np.eye(4)[j] for j in range(4) for s in (1, -1)])
-    for prec in ("fp64", "fp32"):
-        import torch
+    for prec in ("fp64", "fp32", "bf16"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rb, _ = lib.laplace_eval([dm] * 9, batch, prec=prec)

@@ -84,3 +84,54 @@ def test_fp32_matches_fp64_path_on_the_same_gpu(lib):
         a, c = x32[b].cpu().numpy(), x64[b].cpu().numpy()
         assert np.max(np.abs(a - c)) <= MODE_RTOL * max(1.0, np.max(np.abs(c)))
         assert rel(r32[b]["objective"], r64[b]["objective"]) <= LOGDET_RTOL
+
+
+# ---------------------------------------------------------------- BF16 trailing
+# Unrefined Newton steps factor with BF16 trailing operands; refined steps and
+# the factor behind log|Q*| are FP32, so the FP32 bounds above still apply.  A
+# BF16 step is a less exact Newton step, so the iteration count may exceed the
+# oracle's by up to two.
+BF16_LOGDET_RTOL = 1e-4   # log-det of a factorisation with BF16 trailing operands throughout
+
+
+@pytest.mark.parametrize("shape", [(40, 9), (100, 30)])
+def test_bf16_laplace_against_oracle(lib, shape):
+    from paper_2311_08050_amd import binding
+    m = synth.kron_poisson(*shape, seed=11)
+    th0 = synth.kron_theta0(shape[1])
+    thetas = np.stack([th0, th0 + np.array([0.3, -0.2, 0.4, 0.1])])
+    say(f"bf16 kron {shape}")
+    lib.profile(True)
+    res, xs = lib.laplace_eval(dev_models([m, m]), thetas, prec="bf16")
+    bf = lib.profile_get(binding.K_TRAIL, "bf16")
+    lib.profile(False)
+    # with n within one 512-wide panel there is no trailing update of Q* itself
+    # (the correction-form steps still run); beyond it the BF16 kernel must run
+    assert (bf["launches"] > 0) == (m["n"] > 512), bf
+    for b in range(2):
+        ref = O.laplace_eval(m, thetas[b])
+        r, x = res[b], xs[b].cpu().numpy()
+        assert r["info"] == 0 and r["fallback"] == 0 and r["ir_steps"] >= 1
+        assert ref["iters"] - 1 <= r["iters"] <= ref["iters"] + 2, (r["iters"], ref["iters"])
+        assert np.max(np.abs(x - ref["x"])) / max(1.0, np.max(np.abs(ref["x"]))) <= MODE_RTOL
+        for key in ("logdet_qprior", "logdet_sprior", "ese"):
+            assert rel(r[key], ref[key]) <= 1e-9, key
+        assert rel(r["logdet_qstar"], ref["logdet_qstar"]) <= LOGDET_RTOL
+        assert rel(r["logdet_s"], ref["logdet_s"]) <= LOGDET_S_RTOL
+        assert rel(r["objective"], ref["objective"]) <= LOGDET_RTOL
+
+
+def test_logdet_precisions_on_posterior_precision(lib):
+    """log|Q*| of the posterior precision at the mode (n = 2048: several panels,
+    trailing updates of every size) in FP64, FP32 and with BF16 trailing operands."""
+    import torch
+    m = synth.kron_poisson(64, 32, seed=12)
+    th = synth.kron_theta0(32) + np.array([0.2, -0.1, 0.3, 0.0])
+    ref = O.laplace_eval(m, th)
+    Q = O.prior_precision(m, th) + np.diag(m["E"] * np.exp(th[3] + ref["x"]))
+    ld_ref, _, info = O.logdet(Q)
+    assert info == 0
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6), ("bf16", BF16_LOGDET_RTOL)):
+        ld, inf = lib.logdet([torch.tensor(Q).cuda()], prec=prec)
+        say(f"logdet {prec}: relative error {abs(ld[0] - ld_ref) / abs(ld_ref):.2e}")
+        assert inf[0] == 0 and abs(ld[0] - ld_ref) <= tol * abs(ld_ref), (prec, ld[0], ld_ref)
