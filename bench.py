@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "θ-evals/sec + TFLOP/s vs MFMA peak at n=8192, FP64 vs mixed+warm-start"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks
-TRAIL_KERNEL = {"fp64": "gemm_update_kernel<double,128,128>", "fp32": "gemm_update_kernel<float,128,128>",
+TRAIL_KERNEL = {"fp64": "gemm_update_kernel<double,128,128,0>", "fp32": "gemm_update_kernel<float,128,128,0>",
                 "bf16": "trail_bf16_kernel<128,128>"}
 MLP_TRAIN = {"n_train": 512, "epochs": 300, "hidden": 256, "lr": 1e-3, "seed": 91}
 
@@ -72,14 +72,19 @@ def traffic_from_profile(kernel_source, summary_md):
         return None
 
 
-def rocprof_window(csv_path, bench_json):
+def rocprof_window(csv_path, bench_json, precision=None):
     """Average a rocprofv3 per-dispatch CSV (kernel trace or counter collection)
-    over the timed region: the last `launches` dispatches of the roofline kernel
-    named in the JSON line that the profiled bench run printed."""
+    over the timed region: the last `launches` dispatches of the headline's
+    roofline kernel (or of its trailing-update kernel of `precision`) named in
+    the JSON line that the profiled bench run printed."""
     import csv
 
     with open(bench_json) as f:
-        roof = json.loads([ln for ln in f if ln.startswith("{")][-1])["roofline"]
+        line = json.loads([ln for ln in f if ln.startswith("{")][-1])
+    roof = line["roofline"]
+    if precision:
+        tk = line["variants"][line["config"]["variant"]]["trail_kernels"][precision]
+        roof = {"kernel": tk["kernel"], "launches": tk["launches"], "avg_launch_ms": tk["avg_launch_ms"]}
     name = roof["kernel"].split(" ")[0].replace("inla::", "")
     nlast = int(roof["launches"])
     rows = []
@@ -191,11 +196,13 @@ def main():
     ap.add_argument("--rocprof-window", metavar="CSV",
                     help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
     ap.add_argument("--bench-json", metavar="FILE", help="the JSON line printed by the profiled bench run")
+    ap.add_argument("--window-precision", choices=("fp64", "fp32", "bf16"),
+                    help="window the trailing-update kernel of this precision instead of the roofline kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (HBM counter calibration)")
     args = ap.parse_args()
     if args.rocprof_window:
-        print(json.dumps(rocprof_window(args.rocprof_window, args.bench_json)))
+        print(json.dumps(rocprof_window(args.rocprof_window, args.bench_json, args.window_precision)))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))

@@ -237,9 +237,11 @@ __device__ __forceinline__ void subtract_tile(__attribute__((address_space(1))) 
 // sub-chunk.  LDS rows are padded by 4 elements so that each read is free of
 // bank conflicts.
 // --------------------------------------------------------------------------
-template <typename T, int TM, int TN>
+// SEL (row selection of update_tile) is a template parameter so that the
+// border-row launch beside a BF16 trailing update is a kernel of its own.
+template <typename T, int TM, int TN, int SEL>
 __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
-                                                             int p0, int nb, int j, int sel) {
+                                                             int p0, int nb, int j) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int KCH = F64 ? 16 : 32;            // K chunk staged per LDS buffer
   constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte global load
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 
   const FactorDesc d = descs[blockIdx.y];
   int row0, col0, ks, ke;
-  if (!update_tile(d, kind, p0, nb, j, TM, TN, sel, row0, col0, ks, ke)) return;
+  if (!update_tile(d, kind, p0, nb, j, TM, TN, SEL, row0, col0, ks, ke)) return;
 
   const int ld = d.ld;
   gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
@@ -540,18 +542,20 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, b
         }
         if (gx == 0) continue;
         ctx.launch(INLA_K_PANEL, fl, by, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
-                             nb, j, 0);
+          hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind,
+                             p0, nb, j);
         });
       }
     }
     const int act = active(p0);
     int gx = 0;
     double fl = 0, by = 0, fl_q = 0, by_q = 0;   // all tiles; tiles of the factored rows only
+    bool rows_q = false;                          // some theta still has factored rows below the panel
     for (int i = 0; i < act; ++i) {
       const HostFactor &h = fs[order[i]];
       gx = std::max(gx, tiles_for(h.d, KIND_TRAIL, p0, nb, p0, 128));
       const int pend = std::min(p0 + nb, h.d.nf);
+      rows_q = rows_q || pend < h.d.nf;
       const double kr = std::max(0, std::min(pend, h.n_real) - p0);
       const double nc = count_cols_real(h, pend, h.d.ncols), nr = count_rows_real(h, pend);
       if (nc > 0) {
@@ -569,17 +573,18 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, b
         // BF16 operands for the factored rows only: the border rows carry the
         // constraint rows and the right-hand side, whose Schur block (C Q^{-1}
         // C^T and C Q^{-1} b) arises by cancellation and keeps FP32 operands
-        ctx.launch(INLA_K_TRAIL, fl_q, by_q, [&] {
-          hipLaunchKernelGGL((trail_bf16_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, p0, nb);
-        });
+        if (rows_q)
+          ctx.launch(INLA_K_TRAIL, fl_q, by_q, [&] {
+            hipLaunchKernelGGL((trail_bf16_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, p0, nb);
+          });
         ctx.launch(INLA_K_BORDER, fl - fl_q, by - by_q, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
-                             KIND_TRAIL, p0, nb, p0, 2);
+          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 2>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                             KIND_TRAIL, p0, nb, p0);
         });
       } else {
         ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
-                             KIND_TRAIL, p0, nb, p0, 0);
+          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                             KIND_TRAIL, p0, nb, p0);
         });
       }
     }
