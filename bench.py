@@ -193,6 +193,9 @@ def main():
     ap.add_argument("--nt", type=int, default=64)
     ap.add_argument("--variants", default="fp64,fp32,bf16,fp32+mlp,bf16+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="factor with the default panel width and tile instead of tuning them first")
+    ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no hipGraph replays)")
     ap.add_argument("--rocprof-window", metavar="CSV",
                     help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
     ap.add_argument("--bench-json", metavar="FILE", help="the JSON line printed by the profiled bench run")
@@ -232,6 +235,18 @@ def main():
     dms = [dm] * args.batch
     xs = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(args.batch)]
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
+    if args.no_graphs:
+        lib.set_graphs(False)
+    tuning = {}
+    if not args.no_autotune:
+        # one-time setup, not timed: the tuner factors synthetic batches of the
+        # Newton passes' shape (n latent columns, k + 1 border rows)
+        for p in dict.fromkeys(v.split("+")[0] for v in variants):
+            t0 = time.perf_counter()
+            chosen, times = lib.autotune([n] * args.batch, [k + 1] * args.batch, prec=p, reps=2)
+            tuning[p] = {"nb": chosen[0], "tm": chosen[1], "tune_s": time.perf_counter() - t0,
+                         "candidate_ms": {f"nb{c[0]}_tm{c[1]}": round(v, 3) for c, v in times.items()}}
+            log(f"autotune {p}: nb={chosen[0]} tm={chosen[1]} {tuning[p]['candidate_ms']}")
     results, train_info, trained = {}, None, {}
     for v in variants:
         warm = None
@@ -280,6 +295,8 @@ def main():
         },
         "roofline": hv["roofline"],
         "variants": results,
+        "autotune": tuning or None,
+        "graphs": not args.no_graphs,
     }
     if train_info is not None:
         out["warm_start_training"] = dict(train_info, **MLP_TRAIN)

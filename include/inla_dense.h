@@ -273,6 +273,45 @@ int inla_profile(inla_handle *h, int32_t enable);
  * class, -3 for an unknown precision, -4 for a null `out`. */
 int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *out);
 
+/* ------------------------------------------------- graphs and autotuning */
+/* The batched factorisation and the triangular solves are long chains of
+ * dependent launches: per 64-wide diagonal block of a panel, the diagonal-block
+ * factorisation, the panel TRSM and the in-panel update; per 64-row block of a
+ * solve, one step.  With graphs enabled (the default) each such chain is
+ * captured once into a hipGraph, keyed by the sizes that fix its grids, and
+ * replayed; the per-theta pointers and parameters travel in a device argument
+ * block that is refreshed before a replay when it changed.  The trailing
+ * update and the other single launches are enqueued directly.  Results are
+ * identical with and without graphs.  The handle owns the graphs (at most 1024,
+ * least recently used dropped first) and releases them in inla_destroy or
+ * when graphs are turned off.  Returns -1 for a null handle. */
+int inla_set_graphs(inla_handle *h, int32_t enable);
+/* Graphs captured and replayed so far by this handle (host outputs; either may be NULL). */
+int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
+/* Autotuner of the blocked Cholesky.  Times the factorisation of a synthetic
+ * symmetric positive definite batch shaped like B matrices of orders n[b]
+ * with kb[b] border rows (host arrays; use kb = k + 1 for the Newton and final
+ * passes of a model with k constraints) for every candidate (panel width nb in
+ * {128, 256, 512, 1024}) x (trailing tile tm in {64, 128}; 128 only for
+ * INLA_PREC_BF16), one untimed and `reps` timed runs each, and records the
+ * fastest for (prec, padded largest order, batch size rounded up to a power
+ * of two) in the handle's table, which every later factorisation of such a
+ * batch uses.  Outputs (host, each may be NULL): the chosen nb and tm, the
+ * mean time in ms of each candidate in the order above (ms, up to 8 values)
+ * and the candidate count.  Uses the handle's workspace; the batch's matrices
+ * are synthetic, so no caller data is touched.  Without an entry a batch
+ * factorises with nb = 512 and tm = 128.  Returns -2 for B < 1, -3 / -4 for
+ * a null or non-positive n / negative kb, INLA_ERR_UNSUPPORTED for an unknown
+ * precision, -6 for reps < 1. */
+int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb, int32_t prec, int32_t reps,
+                  int32_t *nb, int32_t *tm, double *ms, int32_t *n_cand);
+/* Set (nb, tm) for (prec, largest order n_max, batch size B) directly, or
+ * erase the entry with nb = 0.  nb must be one of the candidates above and tm
+ * 64 or 128 (128 for INLA_PREC_BF16); returns -5 / -6 otherwise. */
+int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t nb, int32_t tm);
+/* The (nb, tm) a factorisation of such a batch uses (host outputs). */
+int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *nb, int32_t *tm);
+
 /* Library version string. */
 const char *inla_version(void);
 

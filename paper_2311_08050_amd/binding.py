@@ -34,7 +34,11 @@ EXPORTS = [
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
+    "inla_set_graphs", "inla_graph_stats", "inla_autotune", "inla_tune_set", "inla_tune_get",
 ]
+# Autotuner candidates in the order inla_autotune reports their times.
+TUNE_CANDIDATES = {p: [(nb, tm) for nb in (128, 256, 512, 1024) for tm in (64, 128) if p != "bf16" or tm == 128]
+                   for p in PREC}
 
 
 class Model(C.Structure):
@@ -93,6 +97,11 @@ def load_library(path: str = LIBPATH):
     lib.inla_mlp_grad.argtypes = [P, i32, pf, pf, pf, pd]
     lib.inla_mlp_train_step.argtypes = [P, i32, pf, pf, C.c_float, pd]
     lib.inla_mlp_predict_modes.argtypes = [P, i32, pd, i32, pd, pd, C.POINTER(P)]
+    lib.inla_set_graphs.argtypes = [P, i32]
+    lib.inla_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pi32, pd, pi32]
+    lib.inla_tune_set.argtypes = [P, i32, i32, i32, i32, i32]
+    lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32, pi32]
     lib.inla_version.restype = C.c_char_p
     for name in EXPORTS:
         if name != "inla_version":
@@ -218,6 +227,37 @@ class Library:
                                         theta.shape[1], xptrs, vptrs, info)
         self._check(rc, "inla_marginal_var")
         return var, np.array(info[:], dtype=np.int32)
+
+    # ------------------------------------------------------------- graphs and tuning
+    def set_graphs(self, on: bool):
+        self._check(self.lib.inla_set_graphs(self.h, 1 if on else 0), "inla_set_graphs")
+
+    def graph_stats(self):
+        cap, rep = C.c_int64(), C.c_int64()
+        self._check(self.lib.inla_graph_stats(self.h, C.byref(cap), C.byref(rep)), "inla_graph_stats")
+        return {"captured": cap.value, "replays": rep.value}
+
+    def autotune(self, ns, kbs, prec="fp64", reps=2):
+        """Tune the factorisation of a batch of orders ``ns`` with border heights
+        ``kbs``; returns the chosen (nb, tm) and each candidate's mean time (ms)."""
+        B = len(ns)
+        n = (C.c_int32 * B)(*[int(v) for v in ns])
+        kb = (C.c_int32 * B)(*[int(v) for v in kbs])
+        nb, tm, nc = C.c_int32(), C.c_int32(), C.c_int32()
+        ms = (C.c_double * 8)()
+        rc = self.lib.inla_autotune(self.h, B, n, kb, PREC[prec], reps, C.byref(nb), C.byref(tm), ms, C.byref(nc))
+        self._check(rc, "inla_autotune")
+        cands = TUNE_CANDIDATES[prec]
+        assert nc.value == len(cands)
+        return (nb.value, tm.value), {c: ms[i] for i, c in enumerate(cands)}
+
+    def tune_set(self, prec, n_max, B, nb, tm):
+        self._check(self.lib.inla_tune_set(self.h, PREC[prec], n_max, B, nb, tm), "inla_tune_set")
+
+    def tune_get(self, prec, n_max, B):
+        nb, tm = C.c_int32(), C.c_int32()
+        self._check(self.lib.inla_tune_get(self.h, PREC[prec], n_max, B, C.byref(nb), C.byref(tm)), "inla_tune_get")
+        return nb.value, tm.value
 
     # ------------------------------------------------------------- profiling
     def profile(self, on: bool):

@@ -29,6 +29,108 @@ void *Ctx::upload(const void *src, size_t bytes) {
   return dst;
 }
 
+int Ctx::upload_to(void *dst, const void *src, size_t bytes) {
+  const size_t padded = align256(bytes);
+  if (padded > ring_size) return INLA_ERR_NOMEM;
+  if (ring_off + padded > ring_size) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return INLA_ERR_HIP;
+    ring_off = 0;
+  }
+  std::memcpy(ring_host + ring_off, src, bytes);
+  if (hipMemcpyAsync(dst, ring_host + ring_off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return INLA_ERR_HIP;
+  ring_off += padded;
+  return INLA_OK;
+}
+
+static constexpr size_t GRAPH_CACHE_MAX = 1024;
+
+int Ctx::sequence(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
+                  const std::function<void(const void *)> &body) {
+  const int rc = sequence_impl(cls, key, args, nbytes, body);
+  if (rc && !sticky) sticky = rc;
+  return rc;
+}
+
+int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
+                       const std::function<void(const void *)> &body) {
+  if (capturing) return INLA_ERR_UNSUPPORTED;   // sequences do not nest
+  if (!graphs) {
+    const void *d = upload(args, nbytes);
+    if (!d) return INLA_ERR_NOMEM;
+    body(d);
+    return check();
+  }
+  auto it = graph_cache.find(key);
+  if (it == graph_cache.end()) {
+    if (!cap_stream && hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) return INLA_ERR_HIP;
+    if (graph_cache.size() >= GRAPH_CACHE_MAX) {
+      auto lru = graph_cache.begin();
+      for (auto q = graph_cache.begin(); q != graph_cache.end(); ++q)
+        if (q->second.used < lru->second.used) lru = q;
+      if (hipStreamSynchronize(stream) != hipSuccess) return INLA_ERR_HIP;
+      (void)hipGraphExecDestroy(lru->second.exec);
+      (void)hipFree(lru->second.dargs);
+      graph_cache.erase(lru);
+    }
+    Graph g;
+    if (hipMalloc(&g.dargs, align256(nbytes)) != hipSuccess) {
+      (void)hipGetLastError();
+      return INLA_ERR_NOMEM;
+    }
+    // capture on the handle's private stream: nothing runs while capturing
+    hipStream_t user = stream;
+    stream = cap_stream;
+    capturing = true;
+    cap_flops = cap_bytes = 0;
+    hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) body(g.dargs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cap_stream, &graph) : e;
+    stream = user;
+    capturing = false;
+    if (e == hipSuccess && e2 == hipSuccess && graph) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    else e = e != hipSuccess ? e : (e2 != hipSuccess ? e2 : hipErrorUnknown);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      last = e;
+      (void)hipGetLastError();
+      (void)hipFree(g.dargs);
+      return INLA_ERR_HIP;
+    }
+    g.flops = cap_flops;
+    g.bytes = cap_bytes;
+    ++graphs_captured;
+    it = graph_cache.emplace(key, std::move(g)).first;
+  }
+  Graph &g = it->second;
+  g.used = ++graph_clock;
+  if (g.last.size() != nbytes || std::memcmp(g.last.data(), args, nbytes) != 0) {
+    int rc = upload_to(g.dargs, args, nbytes);
+    if (rc) return rc;
+    g.last.assign((const char *)args, (const char *)args + nbytes);
+  }
+  hipGraphExec_t ex = g.exec;
+  ++graphs_replayed;
+  hipError_t le = hipSuccess;
+  launch(cls, g.flops, g.bytes, [&] { le = hipGraphLaunch(ex, stream); });
+  if (le != hipSuccess) {
+    last = le;
+    return INLA_ERR_HIP;
+  }
+  return check();
+}
+
+void Ctx::drop_graphs() {
+  if (graph_cache.empty()) return;
+  if (stream) (void)hipStreamSynchronize(stream);
+  else (void)hipDeviceSynchronize();
+  for (auto &kv : graph_cache) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipFree(kv.second.dargs);
+  }
+  graph_cache.clear();
+}
+
 bool Ctx::reserve(size_t bytes) {
   if (bytes <= ws_size) return true;
   if (ws) {
@@ -47,6 +149,12 @@ bool Ctx::reserve(size_t bytes) {
 }
 
 void Ctx::launch(int cls, double flops, double bytes, const std::function<void()> &f) {
+  if (capturing) {
+    cap_flops += flops;
+    cap_bytes += bytes;
+    f();
+    return;
+  }
   if (!prof) {
     f();
     return;
@@ -85,6 +193,11 @@ void Ctx::harvest() {
 }
 
 int Ctx::check() {
+  if (sticky) {
+    const int r = sticky;
+    sticky = 0;
+    return r;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     last = e;
@@ -98,18 +211,24 @@ Ctx::~Ctx() {
   else (void)hipDeviceSynchronize();
   for (auto &p : pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (auto e : event_pool) (void)hipEventDestroy(e);
+  for (auto &kv : graph_cache) {
+    (void)hipGraphExecDestroy(kv.second.exec);
+    (void)hipFree(kv.second.dargs);
+  }
+  if (cap_stream) (void)hipStreamDestroy(cap_stream);
   if (ws) (void)hipFree(ws);
   if (ring) (void)hipFree(ring);
   if (ring_host) (void)hipHostFree(ring_host);
 }
 
 // ------------------------------------------------------------------ planning
+// Panel width forced through the environment (INLA_NB = 128, 256, 512 or 1024);
+// 0 selects the tuned configuration.
 static int g_nb() {
   static int nb = [] {
     const char *s = std::getenv("INLA_NB");
-    int v = s ? std::atoi(s) : 512;
-    if (v != 128 && v != 256 && v != 512) v = 512;
-    return v;
+    const int v = s ? std::atoi(s) : 0;
+    return (v == 128 || v == 256 || v == 512 || v == 1024) ? v : 0;
   }();
   return nb;
 }
@@ -222,6 +341,7 @@ struct Batch {
   std::vector<int> hinfo;
   std::vector<double> hdres;
   double *pin = nullptr;       // pinned staging for results
+  std::vector<ThetaDesc> last_td;   // host copy of the last uploaded descriptor array
   explicit Batch(Ctx &c) : ctx(c) {}
 };
 
@@ -262,6 +382,7 @@ static ThetaDesc *upload_td(Batch &b, const std::vector<int> &ids) {
   std::vector<ThetaDesc> v;
   v.reserve(ids.size());
   for (int i : ids) v.push_back(b.plans[i].t);
+  b.last_td = v;
   return (ThetaDesc *)b.ctx.upload(v.data(), sizeof(ThetaDesc) * v.size());
 }
 
@@ -348,7 +469,7 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
   if (pass == PASS_NEWTON) {
     const int npm = max_over(b, ids, &ThetaDesc::n_pad);
     launch_rhs(b.ctx, d, B, npm, 0, prec);
-    launch_trsv_bwd(b.ctx, d, B, npm, V_R, V_XN, tbytes, prec);
+    launch_trsv_bwd(b.ctx, b.last_td, npm, V_R, V_XN, tbytes, prec);
     if (prec == INLA_PREC_FP64) launch_newton_accept(b.ctx, d, B);
   } else if (pass == PASS_STEP) {
     launch_restart(b.ctx, d, B, max_over(b, ids, &ThetaDesc::n_pad));
@@ -378,10 +499,10 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
     }
     const int npm = max_over(b, act, &ThetaDesc::n_pad), kpm = max_over(b, act, &ThetaDesc::k_pad);
     launch_kkt_residual(b.ctx, d, B, npm, kpm, rb);
-    launch_trsv_fwd(b.ctx, d, B, npm, V_Z, V_U, 0.5 * tb, prec);
+    launch_trsv_fwd(b.ctx, b.last_td, npm, V_Z, V_U, 0.5 * tb, prec);
     launch_ir_correct(b.ctx, d, B, kpm, prec);
     launch_rhs(b.ctx, d, B, npm, 1, prec);
-    launch_trsv_bwd(b.ctx, d, B, npm, V_R, V_U, 0.5 * tb, prec);
+    launch_trsv_bwd(b.ctx, b.last_td, npm, V_R, V_U, 0.5 * tb, prec);
     launch_ir_update(b.ctx, d, B);
     for (int i : act) steps[i] += 1;
     {
@@ -909,6 +1030,67 @@ int inla_marginal_var(inla_handle *h, int32_t B, const inla_model *models, const
                    x_mode + c.first, var + c.first, info + c.first);
     if (rc) return rc;
   }
+  return INLA_OK;
+}
+
+int inla_set_graphs(inla_handle *h, int32_t enable) {
+  if (!h) return -1;
+  h->ctx.graphs = enable != 0;
+  if (!enable) h->ctx.drop_graphs();
+  return INLA_OK;
+}
+
+int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays) {
+  if (!h) return -1;
+  if (captured) *captured = h->ctx.graphs_captured;
+  if (replays) *replays = h->ctx.graphs_replayed;
+  return INLA_OK;
+}
+
+int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb, int32_t prec, int32_t reps,
+                  int32_t *nb, int32_t *tm, double *ms, int32_t *n_cand) {
+  if (!h) return -1;
+  if (B < 1) return -2;
+  if (!n) return -3;
+  if (!kb) return -4;
+  for (int i = 0; i < B; ++i) {
+    if (n[i] < 1) return -3;
+    if (kb[i] < 0) return -4;
+  }
+  if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
+  if (reps < 1) return -6;
+  return autotune(h->ctx, B, n, kb, prec, reps, nb, tm, ms, n_cand);
+}
+
+static bool tune_ok(int prec, int nb, int tm) {
+  const bool nbok = nb == 128 || nb == 256 || nb == 512 || nb == 1024;
+  return nbok && (tm == 128 || (tm == 64 && prec != INLA_PREC_BF16));
+}
+
+int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t nb, int32_t tm) {
+  if (!h) return -1;
+  if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
+  if (n_max < 1) return -3;
+  if (B < 1) return -4;
+  const std::vector<int64_t> key = tune_key(prec, round_up(n_max, PADN), B);
+  if (nb == 0) {
+    h->ctx.tune.erase(key);
+    return INLA_OK;
+  }
+  if (nb != 128 && nb != 256 && nb != 512 && nb != 1024) return -5;
+  if (!tune_ok(prec, nb, tm)) return -6;
+  h->ctx.tune[key] = {nb, tm};
+  return INLA_OK;
+}
+
+int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *nb, int32_t *tm) {
+  if (!h) return -1;
+  if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
+  if (n_max < 1) return -3;
+  if (B < 1) return -4;
+  const std::pair<int, int> c = tuned_config(h->ctx, prec, round_up(n_max, PADN), B);
+  if (nb) *nb = c.first;
+  if (tm) *tm = c.second;
   return INLA_OK;
 }
 

@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <vector>
 
 #include "../../include/inla_dense.h"
@@ -39,10 +40,44 @@ struct Ctx {
   std::vector<Pending> pending;
   std::vector<hipEvent_t> event_pool;
   hipError_t last = hipSuccess;
+  // hipGraph capture of launch-bound kernel sequences (see sequence())
+  bool graphs = true;
+  bool capturing = false;
+  hipStream_t cap_stream = nullptr;
+  double cap_flops = 0, cap_bytes = 0;
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    void *dargs = nullptr;           // device copy of the argument block the graph's kernels read
+    std::vector<char> last;          // argument bytes last copied into dargs
+    double flops = 0, bytes = 0;     // algorithmic work of one replay
+    uint64_t used = 0;
+  };
+  std::map<std::vector<int64_t>, Graph> graph_cache;
+  uint64_t graph_clock = 0;
+  int64_t graphs_captured = 0, graphs_replayed = 0;
+  int sticky = 0;   // first failure of a sequence() whose caller has no return path; reported by check()
+  // autotuned (panel width, trailing tile) per (precision, padded order, batch bucket)
+  std::map<std::vector<int64_t>, std::pair<int, int>> tune;
 
   // Copy a small host array to device memory through the ring; returns the device
   // pointer (valid for work enqueued after this call on `stream`).
   void *upload(const void *src, size_t bytes);
+  // Copy a small host array into device memory `dst` through the pinned ring
+  // (stream-ordered on `stream`).
+  int upload_to(void *dst, const void *src, size_t bytes);
+  // Enqueue a launch-bound kernel sequence.  `body` launches the kernels and
+  // reads its argument block (`args`, `nbytes`) through the device pointer it
+  // is given.  With graphs enabled the sequence is captured once per distinct
+  // `key` (which must determine every launch's grid and scalar arguments) into
+  // a hipGraph that owns a device copy of the argument block; later calls with
+  // the same key copy the current arguments into that block (skipped when they
+  // are unchanged) and replay the graph.  Without graphs the kernels are
+  // launched directly.  Profiling times a replay as one launch of class `cls`.
+  int sequence(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
+               const std::function<void(const void *dargs)> &body);
+  int sequence_impl(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
+                    const std::function<void(const void *dargs)> &body);
+  void drop_graphs();
   // Grow the workspace to at least `bytes`.  Returns false on allocation failure.
   bool reserve(size_t bytes);
   // Launch through a wrapper that records events when profiling.
@@ -62,7 +97,15 @@ struct PrecScope {
 };
 
 // Library entry points implemented in other translation units.
-int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec);
+// nb, tm = 0: the tuned (or default) panel width and trailing tile for this batch.
+int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec, int tm = 0);
+// The configuration factor_batch uses for a batch of `B` factorisations whose
+// largest padded order is `nf_max`.
+std::pair<int, int> tuned_config(const Ctx &ctx, int prec, int nf_max, int B);
+std::vector<int64_t> tune_key(int prec, int nf_max, int B);
+// Time every candidate configuration on a synthetic batch and record the fastest.
+int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, int *nb_out, int *tm_out,
+             double *ms_out, int *n_cand);
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 

@@ -22,6 +22,7 @@
 // Storage and MFMA precision are template parameters: FP64 storage with
 // v_mfma_f64_16x16x4f64, or FP32 storage with v_mfma_f32_16x16x4f32 (FP32
 // accumulate).  Operands are LDS-staged in double-buffered K chunks.
+#include <limits>
 #include <type_traits>
 
 #include "device.hpp"
@@ -489,8 +490,24 @@ static int tiles_for(const FactorDesc &d, int kind, int p0, int nb, int j, int T
   return nc * (nc + 1) / 2 + (nr - nc) * nc;
 }
 
+// Synthetic symmetric positive definite batch for the autotuner: unit-free
+// values, diagonally dominant on the factored columns, small border rows.
 template <typename T>
-static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, bool bf16_trail) {
+__global__ __launch_bounds__(256) void tune_fill_kernel(const FactorDesc *__restrict__ descs) {
+  const FactorDesc d = descs[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.ncols) return;
+  __attribute__((address_space(1))) T *col = gptr((T *)d.A) + (size_t)c * d.ld;
+  for (int r = c + threadIdx.x; r < d.nrows; r += 256) {
+    const uint32_t h = (uint32_t)r * 2654435761u ^ (uint32_t)c * 40503u;
+    const double off = ((double)(h >> 8) / 16777216.0 - 0.5) / (double)d.nf;
+    col[r] = (T)(r == c ? (c < d.nf ? 2.0 : 1.0) : off);
+  }
+  if (c == 0 && threadIdx.x == 0) *d.info = 0;
+}
+
+template <typename T>
+static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int tm, bool bf16_trail) {
   const int B = (int)fs.size();
   if (B == 0) return 0;
   const double esz = sizeof(T);
@@ -508,52 +525,69 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, b
     while (a < B && hd[a].nf > col) ++a;
     return a;
   };
+  // Every grid and scalar argument of a panel's launch sequence follows from
+  // these sizes; the pointers travel in the argument block.
+  std::vector<int64_t> key0 = {0x46414354, (int64_t)sizeof(T), bf16_trail, nb, B};
+  for (int i = 0; i < B; ++i) {
+    const HostFactor &h = fs[order[i]];
+    key0.insert(key0.end(), {h.d.nf, h.d.nrows, h.d.ncols, h.d.id_row0, h.n_real, h.kb_real, h.ks_real});
+  }
   for (int p0 = 0; p0 < nf_max; p0 += nb) {
-    for (int j = p0; j < p0 + nb && j < nf_max; j += NBI) {
-      const int act = active(j);
-      {
-        double fl = 0;
-        for (int i = 0; i < act; ++i) {
-          const HostFactor &h = fs[order[i]];
-          const double kr = std::max(0, std::min(NBI, h.n_real - j));
-          fl += 2.0 * kr * kr * kr / 3.0;
-        }
-        ctx.launch(INLA_K_POTF2, fl, 0.0, [&] {
-          hipLaunchKernelGGL(potf2_inv_kernel<T>, dim3(act), dim3(256), 0, ctx.stream, dd, j);
-        });
-      }
-      for (int kind : {KIND_TRSM, KIND_PANEL}) {
-        int gx = 0;
-        double fl = 0, by = 0;
-        for (int i = 0; i < act; ++i) {
-          const HostFactor &h = fs[order[i]];
-          gx = std::max(gx, tiles_for(h.d, kind, p0, nb, j, 64));
-          const int pend = std::min(p0 + nb, h.d.nf);
-          const double kr = std::max(0, std::min(NBI, h.n_real - j));
-          if (kind == KIND_TRSM) {
-            const double m = count_rows_real(h, j + NBI);
-            fl += m * kr * kr;
-            by += 2.0 * esz * m * kr;
-          } else if (j + NBI < pend) {
-            const double nc = count_cols_real(h, j + NBI, pend), nr = count_rows_real(h, j + NBI);
-            fl += 2.0 * trap_elems(nr, nc) * kr;
-            by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
+    // the panel: potf2_inv, TRSM and in-panel update of every 64-wide block
+    std::vector<int64_t> key = key0;
+    key.push_back(p0);
+    int rc = ctx.sequence(INLA_K_PANEL, key, hd.data(), sizeof(FactorDesc) * B, [&](const void *dv) {
+      const FactorDesc *pd = (const FactorDesc *)dv;
+      for (int j = p0; j < p0 + nb && j < nf_max; j += NBI) {
+        const int act = active(j);
+        {
+          double fl = 0;
+          for (int i = 0; i < act; ++i) {
+            const HostFactor &h = fs[order[i]];
+            const double kr = std::max(0, std::min(NBI, h.n_real - j));
+            fl += 2.0 * kr * kr * kr / 3.0;
           }
+          ctx.launch(INLA_K_POTF2, fl, 0.0, [&] {
+            hipLaunchKernelGGL(potf2_inv_kernel<T>, dim3(act), dim3(256), 0, ctx.stream, pd, j);
+          });
         }
-        if (gx == 0) continue;
-        ctx.launch(INLA_K_PANEL, fl, by, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind,
-                             p0, nb, j);
-        });
+        for (int kind : {KIND_TRSM, KIND_PANEL}) {
+          int gx = 0;
+          double fl = 0, by = 0;
+          for (int i = 0; i < act; ++i) {
+            const HostFactor &h = fs[order[i]];
+            gx = std::max(gx, tiles_for(h.d, kind, p0, nb, j, 64));
+            const int pend = std::min(p0 + nb, h.d.nf);
+            const double kr = std::max(0, std::min(NBI, h.n_real - j));
+            if (kind == KIND_TRSM) {
+              const double m = count_rows_real(h, j + NBI);
+              fl += m * kr * kr;
+              by += 2.0 * esz * m * kr;
+            } else if (j + NBI < pend) {
+              const double nc = count_cols_real(h, j + NBI, pend), nr = count_rows_real(h, j + NBI);
+              fl += 2.0 * trap_elems(nr, nc) * kr;
+              by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
+            }
+          }
+          if (gx == 0) continue;
+          ctx.launch(INLA_K_PANEL, fl, by, [&] {
+            hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, pd,
+                               kind, p0, nb, j);
+          });
+        }
       }
-    }
+    });
+    if (rc) return rc;
+    // the trailing update of everything below and right of the panel
     const int act = active(p0);
+    const bool split = std::is_same<T, float>::value && bf16_trail;
+    const int TT = split ? 128 : tm;   // the BF16 split path has 128 x 128 tiles only
     int gx = 0;
     double fl = 0, by = 0, fl_q = 0, by_q = 0;   // all tiles; tiles of the factored rows only
     bool rows_q = false;                          // some theta still has factored rows below the panel
     for (int i = 0; i < act; ++i) {
       const HostFactor &h = fs[order[i]];
-      gx = std::max(gx, tiles_for(h.d, KIND_TRAIL, p0, nb, p0, 128));
+      gx = std::max(gx, tiles_for(h.d, KIND_TRAIL, p0, nb, p0, TT));
       const int pend = std::min(p0 + nb, h.d.nf);
       rows_q = rows_q || pend < h.d.nf;
       const double kr = std::max(0, std::min(pend, h.n_real) - p0);
@@ -566,36 +600,136 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, b
       fl_q += 2.0 * trap_elems(nq, nq) * kr;
       by_q += nq > 0 ? 2.0 * esz * trap_elems(nq, nq) + esz * 2.0 * nq * kr : 0.0;
     }
-    if (gx > 0) {
-      bool split = false;
-      if constexpr (std::is_same<T, float>::value) split = bf16_trail;
-      if (split) {
-        // BF16 operands for the factored rows only: the border rows carry the
-        // constraint rows and the right-hand side, whose Schur block (C Q^{-1}
-        // C^T and C Q^{-1} b) arises by cancellation and keeps FP32 operands
-        if (rows_q)
-          ctx.launch(INLA_K_TRAIL, fl_q, by_q, [&] {
-            hipLaunchKernelGGL((trail_bf16_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, p0, nb);
-          });
-        ctx.launch(INLA_K_BORDER, fl - fl_q, by - by_q, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 2>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
-                             KIND_TRAIL, p0, nb, p0);
+    if (gx == 0) continue;
+    if (split) {
+      // BF16 operands for the factored rows only: the border rows carry the
+      // constraint rows and the right-hand side, whose Schur block (C Q^{-1}
+      // C^T and C Q^{-1} b) arises by cancellation and keeps FP32 operands
+      if (rows_q)
+        ctx.launch(INLA_K_TRAIL, fl_q, by_q, [&] {
+          hipLaunchKernelGGL((trail_bf16_kernel<128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, p0, nb);
         });
-      } else {
-        ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-          hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
-                             KIND_TRAIL, p0, nb, p0);
-        });
-      }
+      ctx.launch(INLA_K_BORDER, fl - fl_q, by - by_q, [&] {
+        hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 2>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                           KIND_TRAIL, p0, nb, p0);
+      });
+    } else if (TT == 64) {
+      ctx.launch(INLA_K_TRAIL, fl, by, [&] {
+        hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                           KIND_TRAIL, p0, nb, p0);
+      });
+    } else {
+      ctx.launch(INLA_K_TRAIL, fl, by, [&] {
+        hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd,
+                           KIND_TRAIL, p0, nb, p0);
+      });
     }
   }
   return ctx.check();
 }
 
-int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec) {
+// ------------------------------------------------------------------ tuning
+static int b_bucket(int B) {
+  int b = 1;
+  while (b < B) b <<= 1;
+  return b;
+}
+
+std::vector<int64_t> tune_key(int prec, int nf_max, int B) { return {prec, nf_max, b_bucket(B)}; }
+
+std::pair<int, int> tuned_config(const Ctx &ctx, int prec, int nf_max, int B) {
+  auto it = ctx.tune.find(tune_key(prec, nf_max, B));
+  if (it != ctx.tune.end()) return it->second;
+  return {512, 128};
+}
+
+int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec, int tm) {
+  if (fs.empty()) return 0;
   PrecScope tag(ctx, prec);
-  if (prec == INLA_PREC_FP64) return factor_batch_t<double>(ctx, fs, nb, false);
-  return factor_batch_t<float>(ctx, fs, nb, prec == INLA_PREC_BF16);
+  if (nb <= 0 || tm <= 0) {
+    int nf_max = 0;
+    for (const HostFactor &h : fs) nf_max = std::max(nf_max, h.d.nf);
+    const std::pair<int, int> c = tuned_config(ctx, prec, nf_max, (int)fs.size());
+    if (nb <= 0) nb = c.first;
+    if (tm <= 0) tm = c.second;
+  }
+  if (prec == INLA_PREC_FP64) return factor_batch_t<double>(ctx, fs, nb, tm, false);
+  return factor_batch_t<float>(ctx, fs, nb, tm, prec == INLA_PREC_BF16);
+}
+
+// Candidate (panel width, trailing tile) pairs; the BF16 path has one tile size.
+static std::vector<std::pair<int, int>> tune_candidates(int prec) {
+  std::vector<std::pair<int, int>> c;
+  for (int nb : {128, 256, 512, 1024})
+    for (int tm : {64, 128})
+      if (prec != INLA_PREC_BF16 || tm == 128) c.push_back({nb, tm});
+  return c;
+}
+
+int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, int *nb_out, int *tm_out,
+             double *ms_out, int *n_cand) {
+  const size_t esz = prec == INLA_PREC_FP64 ? 8 : 4;
+  std::vector<HostFactor> fs(B);
+  std::vector<size_t> offs(B);
+  size_t total = 0;
+  int nf_max = 0;
+  for (int i = 0; i < B; ++i) {
+    HostFactor &h = fs[i];
+    const int nf = round_up(std::max(n[i], 1), PADN);
+    const int kbp = kb[i] > 0 ? round_up(kb[i], PADN) : 0;
+    h.d.nf = nf; h.d.nrows = h.d.ncols = h.d.ld = nf + kbp;
+    h.d.id_row0 = std::numeric_limits<int>::max();
+    h.n_real = n[i]; h.kb_real = kb[i] > 0 ? kb[i] : 0; h.ks_real = h.kb_real;
+    nf_max = std::max(nf_max, nf);
+    offs[i] = total;
+    total += (esz * (size_t)h.d.ld * h.d.ncols + esz * (size_t)nf * NBI + sizeof(int) + 255) & ~size_t(255);
+  }
+  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  for (int i = 0; i < B; ++i) {
+    char *base = ctx.ws + offs[i];
+    fs[i].d.A = base;
+    fs[i].d.linv = base + esz * (size_t)fs[i].d.ld * fs[i].d.ncols;
+    fs[i].d.info = (int *)((char *)fs[i].d.linv + esz * (size_t)fs[i].d.nf * NBI);
+  }
+  std::vector<FactorDesc> hd(B);
+  int cmax = 0;
+  for (int i = 0; i < B; ++i) { hd[i] = fs[i].d; cmax = std::max(cmax, hd[i].ncols); }
+  const FactorDesc *dd = (const FactorDesc *)ctx.upload(hd.data(), sizeof(FactorDesc) * B);
+  if (!dd) return INLA_ERR_NOMEM;
+  hipEvent_t a, b;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return INLA_ERR_HIP;
+  const bool prof = ctx.prof;
+  ctx.prof = false;
+  const auto cand = tune_candidates(prec);
+  int best = -1, rc = 0;
+  double best_ms = 0;
+  for (size_t c = 0; c < cand.size() && !rc; ++c) {
+    double tot = 0;
+    for (int r = 0; r <= reps && !rc; ++r) {   // one untimed run, then `reps` timed ones
+      if (prec == INLA_PREC_FP64)
+        hipLaunchKernelGGL(tune_fill_kernel<double>, dim3(cmax, B), dim3(256), 0, ctx.stream, dd);
+      else
+        hipLaunchKernelGGL(tune_fill_kernel<float>, dim3(cmax, B), dim3(256), 0, ctx.stream, dd);
+      (void)hipEventRecord(a, ctx.stream);
+      rc = factor_batch(ctx, fs, cand[c].first, prec, cand[c].second);
+      (void)hipEventRecord(b, ctx.stream);
+      if (hipEventSynchronize(b) != hipSuccess) rc = INLA_ERR_HIP;
+      float ms = 0;
+      if (!rc && r > 0 && hipEventElapsedTime(&ms, a, b) == hipSuccess) tot += ms;
+    }
+    const double avg = tot / std::max(1, reps);
+    if (ms_out) ms_out[c] = avg;
+    if (!rc && (best < 0 || avg < best_ms)) { best = (int)c; best_ms = avg; }
+  }
+  ctx.prof = prof;
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc) return rc;
+  ctx.tune[tune_key(prec, nf_max, B)] = cand[best];
+  if (nb_out) *nb_out = cand[best].first;
+  if (tm_out) *tm_out = cand[best].second;
+  if (n_cand) *n_cand = (int)cand.size();
+  return ctx.check();
 }
 
 }  // namespace inla

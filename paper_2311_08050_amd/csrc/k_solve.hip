@@ -2,6 +2,8 @@
 // refinement steps and fixed-order reductions.  One workgroup per theta unless
 // stated otherwise.  Factors may be stored in FP64 or FP32 (template T); every
 // solve accumulates in FP64.
+#include <cmath>
+
 #include "device.hpp"
 #include "host.hpp"
 #include "model.hpp"
@@ -471,23 +473,37 @@ void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, i
     INLA_DISPATCH_T(prec, rhs_kernel, dim3((np_max + 63) / 64, B), dim3(256), 0, ctx.stream, dtd, from_z);
   });
 }
-void launch_trsv_fwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec) {
+void launch_trsv_fwd(Ctx &ctx, const std::vector<ThetaDesc> &htd, int np_max, int src, int dst, double bytes,
+                     int prec) {
+  const int B = (int)htd.size();
   if (B <= 0 || np_max <= 0) return;
-  for (int i0 = 0; i0 < np_max; i0 += 64) {
-    const int gx = std::max(1, (np_max - i0 - 64 + 255) / 256);
-    ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(np_max - i0) / np_max * 2.0 / np_max, [&] {
-      INLA_DISPATCH_T(prec, trsv_fwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
-    });
-  }
+  const std::vector<int64_t> key = {0x54525346, prec != INLA_PREC_FP64, B, np_max, src, dst,
+                                    (int64_t)std::llround(bytes)};
+  (void)ctx.sequence(INLA_K_SOLVE, key, htd.data(), sizeof(ThetaDesc) * B, [&](const void *dv) {
+    const ThetaDesc *dtd = (const ThetaDesc *)dv;
+    for (int i0 = 0; i0 < np_max; i0 += 64) {
+      const int gx = std::max(1, (np_max - i0 - 64 + 255) / 256);
+      ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(np_max - i0) / np_max * 2.0 / np_max, [&] {
+        INLA_DISPATCH_T(prec, trsv_fwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
+      });
+    }
+  });
 }
-void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec) {
+void launch_trsv_bwd(Ctx &ctx, const std::vector<ThetaDesc> &htd, int np_max, int src, int dst, double bytes,
+                     int prec) {
+  const int B = (int)htd.size();
   if (B <= 0 || np_max <= 0) return;
-  for (int i0 = np_max - 64; i0 >= 0; i0 -= 64) {
-    const int gx = std::max(1, (i0 + 63) / 64);
-    ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(i0 + 64) / np_max * 2.0 / np_max, [&] {
-      INLA_DISPATCH_T(prec, trsv_bwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
-    });
-  }
+  const std::vector<int64_t> key = {0x54525342, prec != INLA_PREC_FP64, B, np_max, src, dst,
+                                    (int64_t)std::llround(bytes)};
+  (void)ctx.sequence(INLA_K_SOLVE, key, htd.data(), sizeof(ThetaDesc) * B, [&](const void *dv) {
+    const ThetaDesc *dtd = (const ThetaDesc *)dv;
+    for (int i0 = np_max - 64; i0 >= 0; i0 -= 64) {
+      const int gx = std::max(1, (i0 + 63) / 64);
+      ctx.launch(INLA_K_SOLVE, 0.0, bytes * (double)(i0 + 64) / np_max * 2.0 / np_max, [&] {
+        INLA_DISPATCH_T(prec, trsv_bwd_step_kernel, dim3(gx, B), dim3(256), 0, ctx.stream, dtd, i0, src, dst);
+      });
+    }
+  });
 }
 void launch_restart(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max) {
   if (B <= 0 || np_max <= 0) return;

@@ -23,8 +23,10 @@ void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int 
 void launch_kriging_solve(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_rhs(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int from_z, int prec);
 enum { V_X = 0, V_R = 1, V_XN = 2, V_Z = 3, V_U = 4 };   // vector selectors of the solves
-void launch_trsv_fwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
-void launch_trsv_bwd(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int src, int dst, double bytes, int prec);
+// The triangular solves are sequences of np_max / 64 dependent launches; they
+// take the host copy of the descriptors and run as one graph replay.
+void launch_trsv_fwd(Ctx &ctx, const std::vector<ThetaDesc> &htd, int np_max, int src, int dst, double bytes, int prec);
+void launch_trsv_bwd(Ctx &ctx, const std::vector<ThetaDesc> &htd, int np_max, int src, int dst, double bytes, int prec);
 void launch_restart(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max);
 void launch_newton_accept(Ctx &ctx, const ThetaDesc *dtd, int B);
 void launch_ir_correct(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);

@@ -1,0 +1,164 @@
+"""GPU tests of the batching machinery: hipGraph replay of the launch-bound
+sequences (panel steps of the blocked Cholesky, triangular-solve sweeps) and
+the autotuned (panel width, trailing tile) configurations.
+
+Graph replays must reproduce the directly launched kernels bit for bit (the
+same kernels run with the same arguments in the same order).  Every tuned
+configuration must match the FP64 oracle to the parity bar of the FP64 path
+(1e-12 relative for a log-determinant, 1e-9 for a Laplace evaluation).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import inla_oracle as O
+from paper_2311_08050_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-batching] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev_models(models):
+    from paper_2311_08050_amd.binding import DeviceModel
+    return [DeviceModel(m) for m in models]
+
+
+def rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+KEYS = ("objective", "logdet_qprior", "logdet_sprior", "ese", "logdet_qstar", "logdet_s", "xqx", "loglik",
+        "iters", "info", "ir_steps")
+
+
+def uneven_case():
+    ms = [synth.kron_poisson(40, 9, seed=21), synth.kron_poisson(64, 32, seed=22), synth.kron_poisson(100, 30, seed=23)]
+    models = [ms[0], ms[1], ms[2], ms[1]]
+    thetas = np.stack([synth.kron_theta0(m["n_t"]) + d for m, d in
+                       zip(models, ([0, 0, 0, 0], [0.2, -0.1, 0.3, 0.05], [-0.3, 0.2, 0.0, 0.1], [0.1, 0.1, -0.2, 0.0]))])
+    return models, thetas
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_graph_replays_match_direct_launches(prec):
+    """Three evaluations in a row with graphs (capture, then replays, with the
+    program's own device work and synchronisations between them) against one
+    without graphs: identical bits in every result and mode."""
+    import torch
+
+    from paper_2311_08050_amd import binding
+    models, thetas = uneven_case()
+    dms = dev_models(models)
+    eager = binding.Library()
+    eager.set_graphs(False)
+    say(f"{prec}: direct launches, n={[m['n'] for m in models]}")
+    ref, xref = eager.laplace_eval(dms, thetas, prec=prec)
+    assert eager.graph_stats()["captured"] == 0
+    g = binding.Library()
+    for rep in range(3):
+        say(f"{prec}: graph pass {rep}")
+        res, xs = g.laplace_eval(dms, thetas, prec=prec)
+        junk = torch.randn(1 << 20, device="cuda", dtype=torch.float64)
+        _ = (junk * 2.0).sum().item()   # unrelated device work between replays
+        torch.cuda.synchronize()
+        for b in range(len(models)):
+            for key in KEYS:
+                assert res[b][key] == ref[b][key], (prec, rep, b, key, res[b][key], ref[b][key])
+            assert torch.equal(xs[b], xref[b]), (prec, rep, b)
+        st = g.graph_stats()
+        say(f"{prec}: after pass {rep}: {st}")
+        assert st["captured"] > 0 and st["replays"] > st["captured"]
+    cap = g.graph_stats()["captured"]
+    g.laplace_eval(dms, thetas, prec=prec)
+    assert g.graph_stats()["captured"] == cap, "a repeated call must only replay"
+
+
+def test_graph_replays_marginal_var_and_logdet():
+    import torch
+
+    from paper_2311_08050_amd import binding
+    m = synth.kron_poisson(40, 9, seed=24)
+    th = synth.kron_theta0(9)[None, :]
+    dms = dev_models([m])
+    eager = binding.Library()
+    eager.set_graphs(False)
+    g = binding.Library()
+    _, x = eager.constrained_mode(dms, th)
+    v0, i0 = eager.marginal_var(dms, th, x)
+    for rep in range(2):
+        v1, i1 = g.marginal_var(dms, th, x)
+        assert i0[0] == i1[0] == 0 and torch.equal(v0[0], v1[0]), rep
+    mats = [synth.random_spd(n, seed=300 + n) for n in (100, 700, 1300)]
+    a = [torch.tensor(q).cuda() for q in mats]
+    b = [torch.tensor(q).cuda() for q in mats]
+    l0, f0 = eager.logdet(a)
+    l1, f1 = g.logdet(b)
+    assert np.array_equal(l0, l1) and np.array_equal(f0, f1)
+    for x0, x1 in zip(a, b):
+        assert torch.equal(x0, x1)
+
+
+def test_autotune_chooses_a_candidate_and_every_candidate_is_exact():
+    import torch
+
+    from paper_2311_08050_amd import binding
+    lib = binding.Library()
+    ns = [1000, 2100, 3000]
+    (nb, tm), times = lib.autotune(ns, [0, 0, 0], prec="fp64", reps=1)
+    say(f"autotune fp64 {ns}: chose nb={nb} tm={tm}; ms {({f'{k[0]}/{k[1]}': round(v, 3) for k, v in times.items()})}")
+    assert (nb, tm) in binding.TUNE_CANDIDATES["fp64"]
+    assert all(v > 0 for v in times.values())
+    assert lib.tune_get("fp64", max(ns), len(ns)) == (nb, tm)
+    mats = [synth.random_spd(n, seed=400 + n) for n in ns]
+    refs = [O.logdet(q)[0] for q in mats]
+    for cnb, ctm in binding.TUNE_CANDIDATES["fp64"]:
+        lib.tune_set("fp64", max(ns), len(ns), cnb, ctm)
+        assert lib.tune_get("fp64", max(ns), len(ns)) == (cnb, ctm)
+        ld, info = lib.logdet([torch.tensor(q).cuda() for q in mats])
+        for i in range(len(ns)):
+            assert info[i] == 0 and abs(ld[i] - refs[i]) <= 1e-12 * abs(refs[i]), (cnb, ctm, i, ld[i], refs[i])
+    lib.tune_set("fp64", max(ns), len(ns), 0, 0)
+    assert lib.tune_get("fp64", max(ns), len(ns)) == (512, 128)
+    for prec in ("fp32", "bf16"):
+        (nb, tm), times = lib.autotune([2048, 2048], [129, 129], prec=prec, reps=1)
+        say(f"autotune {prec}: chose nb={nb} tm={tm}")
+        assert (nb, tm) in binding.TUNE_CANDIDATES[prec]
+
+
+@pytest.mark.parametrize("nb,tm", [(128, 64), (256, 128), (1024, 64)])
+def test_laplace_under_other_configurations(nb, tm):
+    from paper_2311_08050_amd import binding
+    lib = binding.Library()
+    models, thetas = uneven_case()
+    nmax = max(m["n"] for m in models)
+    # the Newton and final passes factor the latent block; the prior pass uses it too
+    lib.tune_set("fp64", nmax, len(models), nb, tm)
+    say(f"laplace with nb={nb} tm={tm}")
+    res, xs = lib.laplace_eval(dev_models(models), thetas)
+    for b, (m, th) in enumerate(zip(models, thetas)):
+        ref = O.laplace_eval(m, th)
+        r = res[b]
+        assert r["info"] == 0 and abs(r["iters"] - ref["iters"]) <= 1
+        for key in ("objective", "logdet_qprior", "logdet_sprior", "logdet_qstar", "logdet_s"):
+            assert rel(r[key], ref[key]) <= 1e-9, (nb, tm, b, key)
+        x = xs[b].cpu().numpy()
+        assert np.max(np.abs(x - ref["x"])) / max(1.0, np.max(np.abs(ref["x"]))) <= 1e-9
+
+
+def test_tune_argument_errors():
+    from paper_2311_08050_amd import binding
+    lib = binding.Library()
+    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, 384, 128) == -5
+    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, 512, 32) == -6
+    assert lib.lib.inla_tune_set(lib.h, 2, 1000, 4, 512, 64) == -6
+    assert lib.lib.inla_tune_set(lib.h, 0, 0, 4, 512, 64) == -3
+    import ctypes as C
+    n = (C.c_int32 * 1)(0)
+    kb = (C.c_int32 * 1)(0)
+    assert lib.lib.inla_autotune(lib.h, 1, n, kb, 0, 1, None, None, None, None) == -3
+    assert lib.lib.inla_autotune(lib.h, 0, n, kb, 0, 1, None, None, None, None) == -2
