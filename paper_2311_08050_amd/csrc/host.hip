@@ -482,10 +482,17 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
 // Mixed precision: refine the constrained Newton solve of every theta in `ids`
 // on the KKT system with FP64 residuals, using the low-precision factor.
 // Returns the thetas whose refinement did not reach ||dx|| <= tol_ir * max(1, ||x||).
+//
+// With eta > 0 the refinement is the inner solve of an inexact Newton step taken
+// in correction form: it also stops once the correction is below
+// min(eta, d1 / X) times d1, where d1 is the first correction (the Newton step
+// itself) and X the iterate's scale, which keeps Newton's quadratic reduction of
+// the step without solving each linear system to FP64 accuracy.
 static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, double tol_ir, std::vector<int> &failed,
-                  std::vector<int> &steps) {
+                  std::vector<int> &steps, double eta = 0.0) {
   PrecScope tag(b.ctx, prec);
   std::vector<int> act = ids;
+  std::vector<double> d1(b.plans.size(), 0.0);
   const double esz = prec != INLA_PREC_FP64 ? 4.0 : 8.0;
   for (int s = 1; s <= max_ir && !act.empty(); ++s) {
     ThetaDesc *d = upload_td(b, act);
@@ -511,7 +518,10 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
       std::vector<int> next;
       for (int i : act) {
         const double *dr = &b.hdres[DRES_COUNT * i];
-        if (!(dr[DRES_IR_DX] <= tol_ir * dr[DRES_IR_X])) next.push_back(i);
+        const double dx = dr[DRES_IR_DX], X = dr[DRES_IR_X];
+        if (s == 1) d1[i] = dx;
+        const bool inner = eta > 0.0 && s > 1 && dx <= std::min(eta, d1[i] / X) * d1[i];
+        if (!(dx <= tol_ir * X) && !inner) next.push_back(i);
       }
       act.swap(next);
     }
@@ -662,31 +672,41 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     if (!mixed) {
       if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
     } else {
-      // Inexact Newton far from the mode; refinement to FP64 accuracy once the
-      // previous step is below 1e-3 of the iterate's scale (a Gaussian
-      // likelihood's single Newton step is exact, so it is always refined).
-      // In BF16 mode the unrefined steps factor with BF16 trailing operands and
-      // the refined ones with FP32.
-      std::vector<int> ref, far, nconv;
-      for (int i : active)
-        (b.plans[i].t.lik == LIK_GAUSSIAN || prev_step[i] <= 1e-3 * prev_scale[i] ? ref : far).push_back(i);
-      if (prec == INLA_PREC_BF16) {
-        // Solved for the whole next iterate, a step with a BF16 factor would
-        // carry an error of order kappa u_bf16 |x| that never shrinks with the
-        // step, so these steps are taken in correction form: x + the solution
-        // of the KKT system with the FP64 residual at x (one refinement step
-        // from x), whose error is of order kappa u_bf16 times the step.  Such
-        // steps do not count as refined ones.
-        if (!far.empty()) {
-          std::vector<int> unconv;
-          if ((rc = run_pass(b, far, PASS_STEP, INLA_PREC_BF16))) return fail(rc);
-          if ((rc = refine(b, far, INLA_PREC_BF16, 1, 0.0, unconv, far_ir))) return fail(rc);
-        }
-        if (!ref.empty() && (rc = run_pass(b, ref, PASS_NEWTON, ref_prec))) return fail(rc);
-      } else if ((rc = run_pass(b, active, PASS_NEWTON, prec))) {
+      // Near the mode (previous step at most 1e-3 of the iterate's scale) a
+      // Newton step with the FP32 factor is taken in correction form: x + the
+      // solution of the KKT system whose right-hand side is the FP64 residual
+      // at x, refined until the correction falls below min(1e-3, step) times
+      // the step.  Solved for the whole next iterate instead, the step would
+      // carry an error of order kappa u |x| that never shrinks; in correction
+      // form the error is that relative tolerance times the step, so the
+      // iteration keeps Newton's quadratic convergence and the step counts as
+      // refined: its size bounds the distance to the exact Newton iterate.
+      // Far from the mode an FP32 step solves for the whole next iterate (its
+      // error is far below the step), while a step with BF16 trailing operands
+      // is taken in correction form with one refinement step (kappa u_bf16 |x|
+      // would not be below the step).  A Gaussian likelihood's single Newton
+      // step is exact, so it is solved once and refined to FP64 accuracy.
+      std::vector<int> gauss, near, far, nconv;
+      for (int i : active) {
+        if (b.plans[i].t.lik == LIK_GAUSSIAN) gauss.push_back(i);
+        else if (prev_step[i] <= 1e-3 * prev_scale[i]) near.push_back(i);
+        else far.push_back(i);
+      }
+      std::vector<int> unconv;
+      if (!far.empty() && prec == INLA_PREC_BF16) {
+        if ((rc = run_pass(b, far, PASS_STEP, prec))) return fail(rc);
+        if ((rc = refine(b, far, prec, 1, 0.0, unconv, far_ir))) return fail(rc);
+      } else if (!far.empty() && (rc = run_pass(b, far, PASS_NEWTON, prec))) {
         return fail(rc);
       }
-      if ((rc = refine(b, ref, ref_prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
+      if (!near.empty()) {
+        if ((rc = run_pass(b, near, PASS_STEP, ref_prec))) return fail(rc);
+        if ((rc = refine(b, near, ref_prec, max_ir, tol_ir, nconv, irsteps, 1e-3))) return fail(rc);
+      }
+      if (!gauss.empty()) {
+        if ((rc = run_pass(b, gauss, PASS_NEWTON, ref_prec))) return fail(rc);
+        if ((rc = refine(b, gauss, ref_prec, max_ir, tol_ir, nconv, irsteps))) return fail(rc);
+      }
       for (int i : nconv) { failed[i] = 1; redo.push_back(i); }
       std::vector<int> keep;
       for (int i : active) if (!failed[i]) keep.push_back(i);
@@ -712,6 +732,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       // a mixed-precision step only counts once it was refined to FP64 accuracy
       const bool conv = refined && (b.plans[i].t.lik == LIK_GAUSSIAN || dr[DRES_STEP] <= tol * dr[DRES_SCALE]);
       if (conv) done.push_back(i);
+      else if (it == max_iter && mixed && !warm) { failed[i] = 1; redo.push_back(i); }   // FP64 re-evaluation
       else if (it == max_iter) { res[i].info = INLA_INFO_NEWTON_MAXIT; done.push_back(i); }
       else next.push_back(i);
     }
