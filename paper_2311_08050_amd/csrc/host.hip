@@ -672,20 +672,20 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     if (!mixed) {
       if ((rc = run_pass(b, active, PASS_NEWTON, prec))) return fail(rc);
     } else {
-      // Near the mode (previous step at most 1e-3 of the iterate's scale) a
-      // Newton step with the FP32 factor is taken in correction form: x + the
-      // solution of the KKT system whose right-hand side is the FP64 residual
-      // at x, refined until the correction falls below min(1e-3, step) times
-      // the step.  Solved for the whole next iterate instead, the step would
-      // carry an error of order kappa u |x| that never shrinks; in correction
-      // form the error is that relative tolerance times the step, so the
-      // iteration keeps Newton's quadratic convergence and the step counts as
-      // refined: its size bounds the distance to the exact Newton iterate.
-      // Far from the mode an FP32 step solves for the whole next iterate (its
-      // error is far below the step), while a step with BF16 trailing operands
-      // is taken in correction form with one refinement step (kappa u_bf16 |x|
-      // would not be below the step).  A Gaussian likelihood's single Newton
-      // step is exact, so it is solved once and refined to FP64 accuracy.
+      // Every Newton step with a low-precision factor is taken in correction
+      // form: x + the solution of the KKT system whose right-hand side is the
+      // FP64 residual at x.  Solved for the whole next iterate instead, the
+      // step would carry an error of order kappa u |x| that never shrinks (and
+      // larger through the constraint block C Q^{-1} C^T, which the factor
+      // forms by cancellation); in correction form the error is of order
+      // kappa u times the step.  Far from the mode (previous step above 1e-3
+      // of the iterate's scale) one refinement step is taken, with BF16
+      // trailing operands in BF16 mode.  Near the mode the factor is FP32 and
+      // the step is refined until the correction falls below min(1e-3, step)
+      // times the step, which keeps Newton's quadratic convergence; such a
+      // step counts as refined: its size bounds the distance to the exact
+      // Newton iterate.  A Gaussian likelihood's single Newton step is exact,
+      // so it is solved once and refined to FP64 accuracy.
       std::vector<int> gauss, near, far, nconv;
       for (int i : active) {
         if (b.plans[i].t.lik == LIK_GAUSSIAN) gauss.push_back(i);
@@ -693,11 +693,9 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
         else far.push_back(i);
       }
       std::vector<int> unconv;
-      if (!far.empty() && prec == INLA_PREC_BF16) {
+      if (!far.empty()) {
         if ((rc = run_pass(b, far, PASS_STEP, prec))) return fail(rc);
         if ((rc = refine(b, far, prec, 1, 0.0, unconv, far_ir))) return fail(rc);
-      } else if (!far.empty() && (rc = run_pass(b, far, PASS_NEWTON, prec))) {
-        return fail(rc);
       }
       if (!near.empty()) {
         if ((rc = run_pass(b, near, PASS_STEP, ref_prec))) return fail(rc);

@@ -31,8 +31,14 @@ def solve_modes(lib, dmodel, thetas, prec="fp32", batch=64):
     return X, iters
 
 
-def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, lr=1e-3, seed=0, prec="fp32"):
-    """Solve the training points, fit the network, return (mlp, info dict)."""
+def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, lr=1e-3, seed=0, prec="fp32",
+          lr_final=0.01):
+    """Solve the training points, fit the network, return (mlp, info dict).
+
+    Adam with a cosine learning-rate decay from `lr` to `lr_final * lr`; the
+    training set is visited in a fresh random order every epoch (seeded)."""
+    import math
+
     import torch
 
     from .binding import Mlp
@@ -43,13 +49,20 @@ def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, 
     U = torch.tensor(((np.asarray(thetas) - centre) / scale).astype(np.float32), device="cuda")
     mlp = Mlp(lib, U.shape[1], hidden, dmodel.n, seed=seed)
     N = len(thetas)
+    rng = np.random.default_rng(seed)
+    per_epoch = max(1, N // batch)
+    total, k = epochs * per_epoch, 0
     losses = []
     t1 = time.perf_counter()
     for ep in range(epochs):
+        perm = torch.as_tensor(rng.permutation(N), device="cuda")
+        Us, Xs = U.index_select(0, perm), X.index_select(0, perm)
         tot = 0.0
         for s in range(0, N - batch + 1, batch):
-            tot += mlp.train_step(U[s:s + batch], X[s:s + batch], lr)
-        losses.append(tot / max(1, N // batch))
+            step_lr = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * k / total)))
+            tot += mlp.train_step(Us[s:s + batch], Xs[s:s + batch], step_lr)
+            k += 1
+        losses.append(tot / per_epoch)
     t_train = time.perf_counter() - t1
     return mlp, {"solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
                  "zero_start_iters_mean": float(np.mean(iters)), "n_train": N, "epochs": epochs}
