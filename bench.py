@@ -244,9 +244,9 @@ def main():
         for p in dict.fromkeys(v.split("+")[0] for v in variants):
             t0 = time.perf_counter()
             chosen, times = lib.autotune([n] * args.batch, [k + 1] * args.batch, prec=p, reps=2)
-            tuning[p] = {"nb": chosen[0], "tm": chosen[1], "tune_s": time.perf_counter() - t0,
-                         "candidate_ms": {f"nb{c[0]}_tm{c[1]}": round(v, 3) for c, v in times.items()}}
-            log(f"autotune {p}: nb={chosen[0]} tm={chosen[1]} {tuning[p]['candidate_ms']}")
+            tuning[p] = {"nb": chosen[0], "tm": chosen[1], "lookahead": chosen[2], "tune_s": time.perf_counter() - t0,
+                         "candidate_ms": {f"nb{c[0]}_tm{c[1]}_la{c[2]}": round(v, 3) for c, v in times.items()}}
+            log(f"autotune {p}: {chosen} {tuning[p]['candidate_ms']}")
     results, train_info, trained = {}, None, {}
     for v in variants:
         warm = None

@@ -286,31 +286,46 @@ int inla_profile_get(inla_handle *h, int32_t kclass, int32_t prec, inla_kstats *
  * least recently used dropped first) and releases them in inla_destroy or
  * when graphs are turned off.  Returns -1 for a null handle. */
 int inla_set_graphs(inla_handle *h, int32_t enable);
+/* Lookahead in the blocked Cholesky (allowed by default, used where the tuned
+ * configuration asks for it): after each panel, the
+ * trailing update of the next panel's columns runs first on the handle's
+ * stream, the rest of the trailing update on a second stream owned by the
+ * handle (created on first use, default priority), and the next panel is
+ * factored on the handle's stream meanwhile; events order the two streams and
+ * every call still returns with its work complete on the handle's stream.
+ * Results are identical with and without lookahead.  Returns -1 for a null
+ * handle. */
+int inla_set_lookahead(inla_handle *h, int32_t enable);
 /* Graphs captured and replayed so far by this handle (host outputs; either may be NULL). */
 int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
-/* Autotuner of the blocked Cholesky.  Times the factorisation of a synthetic
+/* Autotuner of the blocked Cholesky.  A configuration is int32_t[3] =
+ * {nb, tm, lookahead}: panel width nb in {128, 256, 512, 1024}, trailing tile
+ * tm in {64, 128} (128 only for INLA_PREC_BF16) and lookahead 0 or 1 (see
+ * inla_set_lookahead).  inla_autotune times the factorisation of a synthetic
  * symmetric positive definite batch shaped like B matrices of orders n[b]
- * with kb[b] border rows (host arrays; use kb = k + 1 for the Newton and final
- * passes of a model with k constraints) for every candidate (panel width nb in
- * {128, 256, 512, 1024}) x (trailing tile tm in {64, 128}; 128 only for
- * INLA_PREC_BF16), one untimed and `reps` timed runs each, and records the
- * fastest for (prec, padded largest order, batch size rounded up to a power
- * of two) in the handle's table, which every later factorisation of such a
- * batch uses.  Outputs (host, each may be NULL): the chosen nb and tm, the
- * mean time in ms of each candidate in the order above (ms, up to 8 values)
- * and the candidate count.  Uses the handle's workspace; the batch's matrices
- * are synthetic, so no caller data is touched.  Without an entry a batch
- * factorises with nb = 512 and tm = 128.  Returns -2 for B < 1, -3 / -4 for
- * a null or non-positive n / negative kb, INLA_ERR_UNSUPPORTED for an unknown
- * precision, -6 for reps < 1. */
+ * with kb[b] border rows (host arrays; kb = k + 1 for the Newton and final
+ * passes of a model with k constraints): every (nb, tm) without lookahead in
+ * the order (128,64), (128,128), (256,64), ..., (1024,128) (BF16: the four nb
+ * with tm = 128), then the fastest of them with lookahead (unless lookahead is
+ * turned off), one untimed and `reps` timed runs each.  It records the fastest
+ * for (prec, padded largest order, batch size rounded up to a power of two) in
+ * the handle's table, which every later factorisation of such a batch uses
+ * (the lookahead variant only when it is at least 5% faster).
+ * Outputs (host, each may be NULL): the chosen configuration, the mean time in
+ * ms of each candidate in the order above (at most INLA_TUNE_MAX_CAND values)
+ * and the candidate count.  Uses the handle's workspace; no caller data is
+ * touched.  Without a table entry a batch factorises with {512, 128, 0}.
+ * Returns -2 for B < 1, -3 / -4 for a null or non-positive n / null or
+ * negative kb, INLA_ERR_UNSUPPORTED for an unknown precision, -6 for reps < 1. */
+#define INLA_TUNE_MAX_CAND 9
 int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb, int32_t prec, int32_t reps,
-                  int32_t *nb, int32_t *tm, double *ms, int32_t *n_cand);
-/* Set (nb, tm) for (prec, largest order n_max, batch size B) directly, or
- * erase the entry with nb = 0.  nb must be one of the candidates above and tm
- * 64 or 128 (128 for INLA_PREC_BF16); returns -5 / -6 otherwise. */
-int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t nb, int32_t tm);
-/* The (nb, tm) a factorisation of such a batch uses (host outputs). */
-int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *nb, int32_t *tm);
+                  int32_t *config, double *ms, int32_t *n_cand);
+/* Set the configuration for (prec, largest order n_max, batch size B)
+ * directly, or erase the entry with config = NULL.  Returns -5 for an invalid
+ * configuration. */
+int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, const int32_t *config);
+/* The configuration a factorisation of such a batch uses (host output int32_t[3]). */
+int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *config);
 
 /* Library version string. */
 const char *inla_version(void);

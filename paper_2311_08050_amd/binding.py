@@ -34,11 +34,13 @@ EXPORTS = [
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
-    "inla_set_graphs", "inla_graph_stats", "inla_autotune", "inla_tune_set", "inla_tune_get",
+    "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats", "inla_autotune", "inla_tune_set", "inla_tune_get",
 ]
-# Autotuner candidates in the order inla_autotune reports their times.
+# Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
+# reports their times; the fastest is then timed with lookahead as well.
 TUNE_CANDIDATES = {p: [(nb, tm) for nb in (128, 256, 512, 1024) for tm in (64, 128) if p != "bf16" or tm == 128]
                    for p in PREC}
+TUNE_DEFAULT = (512, 128, 0)
 
 
 class Model(C.Structure):
@@ -98,10 +100,11 @@ def load_library(path: str = LIBPATH):
     lib.inla_mlp_train_step.argtypes = [P, i32, pf, pf, C.c_float, pd]
     lib.inla_mlp_predict_modes.argtypes = [P, i32, pd, i32, pd, pd, C.POINTER(P)]
     lib.inla_set_graphs.argtypes = [P, i32]
+    lib.inla_set_lookahead.argtypes = [P, i32]
     lib.inla_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
-    lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pi32, pd, pi32]
-    lib.inla_tune_set.argtypes = [P, i32, i32, i32, i32, i32]
-    lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32, pi32]
+    lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pd, pi32]
+    lib.inla_tune_set.argtypes = [P, i32, i32, i32, pi32]
+    lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32]
     lib.inla_version.restype = C.c_char_p
     for name in EXPORTS:
         if name != "inla_version":
@@ -232,6 +235,9 @@ class Library:
     def set_graphs(self, on: bool):
         self._check(self.lib.inla_set_graphs(self.h, 1 if on else 0), "inla_set_graphs")
 
+    def set_lookahead(self, on: bool):
+        self._check(self.lib.inla_set_lookahead(self.h, 1 if on else 0), "inla_set_lookahead")
+
     def graph_stats(self):
         cap, rep = C.c_int64(), C.c_int64()
         self._check(self.lib.inla_graph_stats(self.h, C.byref(cap), C.byref(rep)), "inla_graph_stats")
@@ -239,25 +245,31 @@ class Library:
 
     def autotune(self, ns, kbs, prec="fp64", reps=2):
         """Tune the factorisation of a batch of orders ``ns`` with border heights
-        ``kbs``; returns the chosen (nb, tm) and each candidate's mean time (ms)."""
+        ``kbs``; returns the chosen (nb, tm, lookahead) and each candidate's mean
+        time in ms, keyed by (nb, tm, lookahead)."""
         B = len(ns)
         n = (C.c_int32 * B)(*[int(v) for v in ns])
         kb = (C.c_int32 * B)(*[int(v) for v in kbs])
-        nb, tm, nc = C.c_int32(), C.c_int32(), C.c_int32()
-        ms = (C.c_double * 8)()
-        rc = self.lib.inla_autotune(self.h, B, n, kb, PREC[prec], reps, C.byref(nb), C.byref(tm), ms, C.byref(nc))
+        cfg, nc = (C.c_int32 * 3)(), C.c_int32()
+        ms = (C.c_double * 9)()
+        rc = self.lib.inla_autotune(self.h, B, n, kb, PREC[prec], reps, cfg, ms, C.byref(nc))
         self._check(rc, "inla_autotune")
-        cands = TUNE_CANDIDATES[prec]
-        assert nc.value == len(cands)
-        return (nb.value, tm.value), {c: ms[i] for i, c in enumerate(cands)}
+        base = TUNE_CANDIDATES[prec]
+        times = {(c[0], c[1], 0): ms[i] for i, c in enumerate(base)}
+        if nc.value > len(base):
+            fastest = min(times, key=times.get)
+            times[(fastest[0], fastest[1], 1)] = ms[len(base)]
+        return tuple(cfg[:]), times
 
-    def tune_set(self, prec, n_max, B, nb, tm):
-        self._check(self.lib.inla_tune_set(self.h, PREC[prec], n_max, B, nb, tm), "inla_tune_set")
+    def tune_set(self, prec, n_max, B, nb=None, tm=128, look=0):
+        """Set (nb, tm, lookahead) for such batches; nb=None erases the entry."""
+        cfg = None if nb is None else (C.c_int32 * 3)(nb, tm, look)
+        self._check(self.lib.inla_tune_set(self.h, PREC[prec], n_max, B, cfg), "inla_tune_set")
 
     def tune_get(self, prec, n_max, B):
-        nb, tm = C.c_int32(), C.c_int32()
-        self._check(self.lib.inla_tune_get(self.h, PREC[prec], n_max, B, C.byref(nb), C.byref(tm)), "inla_tune_get")
-        return nb.value, tm.value
+        cfg = (C.c_int32 * 3)()
+        self._check(self.lib.inla_tune_get(self.h, PREC[prec], n_max, B, cfg), "inla_tune_get")
+        return tuple(cfg[:])
 
     # ------------------------------------------------------------- profiling
     def profile(self, on: bool):

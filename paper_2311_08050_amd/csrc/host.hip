@@ -15,13 +15,31 @@ namespace inla {
 // ------------------------------------------------------------------ Ctx
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+int Ctx::side_ready() {
+  if (side) return INLA_OK;
+  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+    side = nullptr;
+    return INLA_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&ev_a, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_b, hipEventDisableTiming) != hipSuccess)
+    return INLA_ERR_HIP;
+  return INLA_OK;
+}
+
+// The ring is reused once every earlier reader has finished: work on the
+// caller's stream and on the side stream.
+static bool ring_wrap(Ctx &c) {
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
+  if (c.side && hipStreamSynchronize(c.side) != hipSuccess) return false;
+  c.ring_off = 0;
+  return true;
+}
+
 void *Ctx::upload(const void *src, size_t bytes) {
   bytes = align256(bytes);
   if (bytes > ring_size) return nullptr;
-  if (ring_off + bytes > ring_size) {
-    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
-    ring_off = 0;
-  }
+  if (ring_off + bytes > ring_size && !ring_wrap(*this)) return nullptr;
   std::memcpy(ring_host + ring_off, src, bytes);
   void *dst = ring + ring_off;
   if (hipMemcpyAsync(dst, ring_host + ring_off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return nullptr;
@@ -32,10 +50,7 @@ void *Ctx::upload(const void *src, size_t bytes) {
 int Ctx::upload_to(void *dst, const void *src, size_t bytes) {
   const size_t padded = align256(bytes);
   if (padded > ring_size) return INLA_ERR_NOMEM;
-  if (ring_off + padded > ring_size) {
-    if (hipStreamSynchronize(stream) != hipSuccess) return INLA_ERR_HIP;
-    ring_off = 0;
-  }
+  if (ring_off + padded > ring_size && !ring_wrap(*this)) return INLA_ERR_HIP;
   std::memcpy(ring_host + ring_off, src, bytes);
   if (hipMemcpyAsync(dst, ring_host + ring_off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return INLA_ERR_HIP;
   ring_off += padded;
@@ -177,6 +192,7 @@ void Ctx::launch(int cls, double flops, double bytes, const std::function<void()
 void Ctx::harvest() {
   if (pending.empty()) return;
   (void)hipStreamSynchronize(stream);
+  if (side) (void)hipStreamSynchronize(side);
   for (auto &p : pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -216,23 +232,18 @@ Ctx::~Ctx() {
     (void)hipFree(kv.second.dargs);
   }
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (ev_a) (void)hipEventDestroy(ev_a);
+  if (ev_b) (void)hipEventDestroy(ev_b);
   if (ws) (void)hipFree(ws);
   if (ring) (void)hipFree(ring);
   if (ring_host) (void)hipHostFree(ring_host);
 }
 
 // ------------------------------------------------------------------ planning
-// Panel width forced through the environment (INLA_NB = 128, 256, 512 or 1024);
-// 0 selects the tuned configuration.
-static int g_nb() {
-  static int nb = [] {
-    const char *s = std::getenv("INLA_NB");
-    const int v = s ? std::atoi(s) : 0;
-    return (v == 128 || v == 256 || v == 512 || v == 1024) ? v : 0;
-  }();
-  return nb;
-}
-
 // Per-theta workspace plan.
 struct Plan {
   ThetaDesc t{};
@@ -394,7 +405,7 @@ static int run_factor(Batch &b, const std::vector<int> &ids, int which, Mode mod
     HostFactor h = factor_of(p, which, b.dinfo + 4 * i + which, (void *)(b.bases[i] + lo), mode);
     if (h.d.nf > 0) fs.push_back(h);
   }
-  return factor_batch(b.ctx, fs, g_nb(), prec);
+  return factor_batch(b.ctx, fs, prec);
 }
 
 // Read back dres and info of every theta (one synchronisation).
@@ -884,6 +895,7 @@ int inla_destroy(inla_handle *h) {
 int inla_set_stream(inla_handle *h, void *stream) {
   if (!h) return -1;
   if (hipStreamSynchronize(h->ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  if (h->ctx.side && hipStreamSynchronize(h->ctx.side) != hipSuccess) return INLA_ERR_HIP;
   h->ctx.stream = (hipStream_t)stream;
   return INLA_OK;
 }
@@ -1059,6 +1071,12 @@ int inla_set_graphs(inla_handle *h, int32_t enable) {
   return INLA_OK;
 }
 
+int inla_set_lookahead(inla_handle *h, int32_t enable) {
+  if (!h) return -1;
+  h->ctx.lookahead = enable != 0;
+  return INLA_OK;
+}
+
 int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays) {
   if (!h) return -1;
   if (captured) *captured = h->ctx.graphs_captured;
@@ -1067,7 +1085,7 @@ int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays) {
 }
 
 int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb, int32_t prec, int32_t reps,
-                  int32_t *nb, int32_t *tm, double *ms, int32_t *n_cand) {
+                  int32_t *config, double *ms, int32_t *n_cand) {
   if (!h) return -1;
   if (B < 1) return -2;
   if (!n) return -3;
@@ -1078,38 +1096,37 @@ int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb
   }
   if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
   if (reps < 1) return -6;
-  return autotune(h->ctx, B, n, kb, prec, reps, nb, tm, ms, n_cand);
+  TuneCfg best;
+  const int rc = autotune(h->ctx, B, n, kb, prec, reps, &best, ms, n_cand);
+  if (rc) return rc;
+  if (config) { config[0] = best.nb; config[1] = best.tm; config[2] = best.look; }
+  return INLA_OK;
 }
 
-static bool tune_ok(int prec, int nb, int tm) {
-  const bool nbok = nb == 128 || nb == 256 || nb == 512 || nb == 1024;
-  return nbok && (tm == 128 || (tm == 64 && prec != INLA_PREC_BF16));
-}
-
-int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t nb, int32_t tm) {
+int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, const int32_t *config) {
   if (!h) return -1;
   if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
   if (n_max < 1) return -3;
   if (B < 1) return -4;
   const std::vector<int64_t> key = tune_key(prec, round_up(n_max, PADN), B);
-  if (nb == 0) {
+  if (!config) {
     h->ctx.tune.erase(key);
     return INLA_OK;
   }
-  if (nb != 128 && nb != 256 && nb != 512 && nb != 1024) return -5;
-  if (!tune_ok(prec, nb, tm)) return -6;
-  h->ctx.tune[key] = {nb, tm};
+  const TuneCfg c{config[0], config[1], config[2]};
+  if (!tune_valid(prec, c)) return -5;
+  h->ctx.tune[key] = c;
   return INLA_OK;
 }
 
-int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *nb, int32_t *tm) {
+int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_t *config) {
   if (!h) return -1;
   if (prec < 0 || prec >= INLA_PREC_COUNT) return INLA_ERR_UNSUPPORTED;
   if (n_max < 1) return -3;
   if (B < 1) return -4;
-  const std::pair<int, int> c = tuned_config(h->ctx, prec, round_up(n_max, PADN), B);
-  if (nb) *nb = c.first;
-  if (tm) *tm = c.second;
+  if (!config) return -5;
+  const TuneCfg c = tuned_config(h->ctx, prec, round_up(n_max, PADN), B);
+  config[0] = c.nb; config[1] = c.tm; config[2] = c.look;
   return INLA_OK;
 }
 

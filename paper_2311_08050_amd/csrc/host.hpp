@@ -22,6 +22,11 @@ struct HostFactor {
   int ks_real;   // real Schur columns starting at column nf
 };
 
+// Blocked-Cholesky configuration: panel width, trailing tile, lookahead.
+struct TuneCfg {
+  int nb = 512, tm = 128, look = 0;
+};
+
 struct Ctx {
   hipStream_t stream = nullptr;
   int device = 0;
@@ -56,8 +61,16 @@ struct Ctx {
   uint64_t graph_clock = 0;
   int64_t graphs_captured = 0, graphs_replayed = 0;
   int sticky = 0;   // first failure of a sequence() whose caller has no return path; reported by check()
+  // lookahead in the blocked Cholesky: a second stream of the handle (default
+  // priority) runs the bulk of each trailing update while the caller's stream
+  // factors the next panel (used where the tuned configuration asks for it and
+  // `lookahead` allows it)
+  bool lookahead = true;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  int side_ready();   // creates the side stream and its events on first use
   // autotuned (panel width, trailing tile) per (precision, padded order, batch bucket)
-  std::map<std::vector<int64_t>, std::pair<int, int>> tune;
+  std::map<std::vector<int64_t>, TuneCfg> tune;
 
   // Copy a small host array to device memory through the ring; returns the device
   // pointer (valid for work enqueued after this call on `stream`).
@@ -97,15 +110,17 @@ struct PrecScope {
 };
 
 // Library entry points implemented in other translation units.
-// nb, tm = 0: the tuned (or default) panel width and trailing tile for this batch.
-int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, int prec, int tm = 0);
+// cfg == nullptr: the tuned (or default) configuration for this batch.
+int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int prec, const TuneCfg *cfg = nullptr);
 // The configuration factor_batch uses for a batch of `B` factorisations whose
 // largest padded order is `nf_max`.
-std::pair<int, int> tuned_config(const Ctx &ctx, int prec, int nf_max, int B);
+TuneCfg tuned_config(const Ctx &ctx, int prec, int nf_max, int B);
 std::vector<int64_t> tune_key(int prec, int nf_max, int B);
+bool tune_valid(int prec, const TuneCfg &c);
+constexpr int TUNE_MAX_CAND = 9;
 // Time every candidate configuration on a synthetic batch and record the fastest.
-int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, int *nb_out, int *tm_out,
-             double *ms_out, int *n_cand);
+int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, TuneCfg *best_out, double *ms_out,
+             int *n_cand);
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 

@@ -78,6 +78,41 @@ def test_graph_replays_match_direct_launches(prec):
     assert g.graph_stats()["captured"] == cap, "a repeated call must only replay"
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_lookahead_matches_in_order_factorisation(prec):
+    """The trailing update split in two (next panel's columns first, the rest on
+    the side stream while the next panel is factored) updates every element with
+    the same tile and K range as the single update: identical bits."""
+    import torch
+
+    from paper_2311_08050_amd import binding
+    models, thetas = uneven_case()
+    dms = dev_models(models)
+    plain = binding.Library()
+    plain.set_lookahead(False)
+    ahead = binding.Library()
+    for nb in (128, 512):
+        plain.tune_set(prec, max(m["n"] for m in models), len(models), nb, 128, 0)
+        ahead.tune_set(prec, max(m["n"] for m in models), len(models), nb, 128, 1)
+        say(f"lookahead {prec} nb={nb}")
+        ref, xref = plain.laplace_eval(dms, thetas, prec=prec)
+        res, xs = ahead.laplace_eval(dms, thetas, prec=prec)
+        for b in range(len(models)):
+            for key in KEYS:
+                assert res[b][key] == ref[b][key], (prec, nb, b, key, res[b][key], ref[b][key])
+            assert torch.equal(xs[b], xref[b]), (prec, nb, b)
+    mats = [synth.random_spd(n, seed=500 + n) for n in (300, 1100, 2600)]
+    a = [torch.tensor(q).cuda() for q in mats]
+    c = [torch.tensor(q).cuda() for q in mats]
+    plain.tune_set(prec, 2600, 3, 256, 128, 0)
+    ahead.tune_set(prec, 2600, 3, 256, 128, 1)
+    l0, _ = plain.logdet(a, prec=prec)
+    l1, _ = ahead.logdet(c, prec=prec)
+    assert np.array_equal(l0, l1)
+    for x0, x1 in zip(a, c):
+        assert torch.equal(x0, x1)
+
+
 def test_graph_replays_marginal_var_and_logdet():
     import torch
 
@@ -109,25 +144,26 @@ def test_autotune_chooses_a_candidate_and_every_candidate_is_exact():
     from paper_2311_08050_amd import binding
     lib = binding.Library()
     ns = [1000, 2100, 3000]
-    (nb, tm), times = lib.autotune(ns, [0, 0, 0], prec="fp64", reps=1)
-    say(f"autotune fp64 {ns}: chose nb={nb} tm={tm}; ms {({f'{k[0]}/{k[1]}': round(v, 3) for k, v in times.items()})}")
-    assert (nb, tm) in binding.TUNE_CANDIDATES["fp64"]
+    cfg, times = lib.autotune(ns, [0, 0, 0], prec="fp64", reps=1)
+    say(f"autotune fp64 {ns}: chose {cfg}; ms {({str(k): round(v, 3) for k, v in times.items()})}")
+    assert cfg in times and len(times) == len(binding.TUNE_CANDIDATES["fp64"]) + 1
     assert all(v > 0 for v in times.values())
-    assert lib.tune_get("fp64", max(ns), len(ns)) == (nb, tm)
+    assert lib.tune_get("fp64", max(ns), len(ns)) == cfg
     mats = [synth.random_spd(n, seed=400 + n) for n in ns]
     refs = [O.logdet(q)[0] for q in mats]
     for cnb, ctm in binding.TUNE_CANDIDATES["fp64"]:
-        lib.tune_set("fp64", max(ns), len(ns), cnb, ctm)
-        assert lib.tune_get("fp64", max(ns), len(ns)) == (cnb, ctm)
-        ld, info = lib.logdet([torch.tensor(q).cuda() for q in mats])
-        for i in range(len(ns)):
-            assert info[i] == 0 and abs(ld[i] - refs[i]) <= 1e-12 * abs(refs[i]), (cnb, ctm, i, ld[i], refs[i])
-    lib.tune_set("fp64", max(ns), len(ns), 0, 0)
-    assert lib.tune_get("fp64", max(ns), len(ns)) == (512, 128)
+        for look in (0, 1):
+            lib.tune_set("fp64", max(ns), len(ns), cnb, ctm, look)
+            assert lib.tune_get("fp64", max(ns), len(ns)) == (cnb, ctm, look)
+            ld, info = lib.logdet([torch.tensor(q).cuda() for q in mats])
+            for i in range(len(ns)):
+                assert info[i] == 0 and abs(ld[i] - refs[i]) <= 1e-12 * abs(refs[i]), (cnb, ctm, look, i)
+    lib.tune_set("fp64", max(ns), len(ns))
+    assert lib.tune_get("fp64", max(ns), len(ns)) == binding.TUNE_DEFAULT
     for prec in ("fp32", "bf16"):
-        (nb, tm), times = lib.autotune([2048, 2048], [129, 129], prec=prec, reps=1)
-        say(f"autotune {prec}: chose nb={nb} tm={tm}")
-        assert (nb, tm) in binding.TUNE_CANDIDATES[prec]
+        cfg, times = lib.autotune([2048, 2048], [129, 129], prec=prec, reps=1)
+        say(f"autotune {prec}: chose {cfg}")
+        assert cfg in times and (cfg[0], cfg[1]) in binding.TUNE_CANDIDATES[prec]
 
 
 @pytest.mark.parametrize("nb,tm", [(128, 64), (256, 128), (1024, 64)])
@@ -137,7 +173,7 @@ def test_laplace_under_other_configurations(nb, tm):
     models, thetas = uneven_case()
     nmax = max(m["n"] for m in models)
     # the Newton and final passes factor the latent block; the prior pass uses it too
-    lib.tune_set("fp64", nmax, len(models), nb, tm)
+    lib.tune_set("fp64", nmax, len(models), nb, tm, 1)
     say(f"laplace with nb={nb} tm={tm}")
     res, xs = lib.laplace_eval(dev_models(models), thetas)
     for b, (m, th) in enumerate(zip(models, thetas)):
@@ -151,14 +187,19 @@ def test_laplace_under_other_configurations(nb, tm):
 
 
 def test_tune_argument_errors():
+    import ctypes as C
+
     from paper_2311_08050_amd import binding
     lib = binding.Library()
-    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, 384, 128) == -5
-    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, 512, 32) == -6
-    assert lib.lib.inla_tune_set(lib.h, 2, 1000, 4, 512, 64) == -6
-    assert lib.lib.inla_tune_set(lib.h, 0, 0, 4, 512, 64) == -3
-    import ctypes as C
+
+    def cfg(*v):
+        return (C.c_int32 * 3)(*v)
+    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, cfg(384, 128, 0)) == -5
+    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, cfg(512, 32, 0)) == -5
+    assert lib.lib.inla_tune_set(lib.h, 2, 1000, 4, cfg(512, 64, 0)) == -5
+    assert lib.lib.inla_tune_set(lib.h, 0, 1000, 4, cfg(512, 64, 2)) == -5
+    assert lib.lib.inla_tune_set(lib.h, 0, 0, 4, cfg(512, 64, 0)) == -3
     n = (C.c_int32 * 1)(0)
     kb = (C.c_int32 * 1)(0)
-    assert lib.lib.inla_autotune(lib.h, 1, n, kb, 0, 1, None, None, None, None) == -3
-    assert lib.lib.inla_autotune(lib.h, 0, n, kb, 0, 1, None, None, None, None) == -2
+    assert lib.lib.inla_autotune(lib.h, 1, n, kb, 0, 1, None, None, None) == -3
+    assert lib.lib.inla_autotune(lib.h, 0, n, kb, 0, 1, None, None, None) == -2
