@@ -144,16 +144,64 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
   if (tid == 0 && fail != 0 && *d.info == 0) *d.info = j + fail;
 }
 
-// Tile of one update launch for blockIdx.x: rows/columns of the C tile and the
-// K range [ks, ke).  TRSM launches enumerate row tiles of the block column;
-// PANEL and TRAIL launches enumerate the lower-triangular tiles of the updated
-// block (square part first, then the rectangle below).  Returns false when the
+// Tile bx of one update launch: rows/columns of the C tile and the K range
+// [ks, ke).  TRSM launches enumerate row tiles of the block column; the other
+// kinds enumerate the lower-triangular tiles of the updated block in the
+// grouped order of trap_grouped.  Returns false when the
 // workgroup has no tile, its tile reads identity border rows (or columns)
 // that are still zero over [ks, ke), or the row selection excludes it
 // (sel: 0 every tile, 1 tiles of the factored rows (row < nf), 2 tiles of the
 // border rows (row >= nf)).
+// XCD-aware workgroup order.  The hardware hands the workgroup with linear id
+// L to XCD L % 8, and each XCD has its own L2; remapped, XCD k walks the
+// contiguous range [k N/8, (k+1) N/8) of (theta, tile) pairs, so workgroups
+// that run side by side on one XCD work on neighbouring tiles of one theta and
+// share panel blocks in its L2.  The grid size N must be a multiple of 8.
+__device__ __forceinline__ void xcd_order(int &bx, int &by) {
+  const int N = gridDim.x * gridDim.y;
+  const int L = blockIdx.y * gridDim.x + blockIdx.x;
+  const int G = (L & 7) * (N >> 3) + (L >> 3);
+  by = G / gridDim.x;
+  bx = G - by * gridDim.x;
+}
+
+// Tile t of a lower trapezoid of nr tile rows and nc <= nr tile columns (tile
+// (I, J) present when J <= I), in groups of GR tile rows, column by column
+// within a group: consecutive tiles share their column block, and a group's GR
+// row blocks stay in L2 while its columns go by.  Returns false past the end.
+__device__ __forceinline__ bool trap_grouped(int t, int nr, int nc, int &I, int &J) {
+  constexpr int GR = 8;
+  auto before = [&](int r) {   // tiles in rows [0, r)
+    const int m = min(r, nc);
+    return m * (m + 1) / 2 + max(0, r - nc) * nc;
+  };
+  if (t >= before(nr)) return false;
+  int lo = 0, hi = (nr + GR - 1) / GR - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (before(mid * GR) <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  const int r0 = lo * GR, gh = min(GR, nr - r0);
+  int u = t - before(r0);
+  const int full = min(r0, nc);   // columns left of the group's diagonal: gh tiles each
+  if (u < full * gh) {
+    J = u / gh;
+    I = r0 + u % gh;
+    return true;
+  }
+  u -= full * gh;
+  J = r0;                         // column J >= r0 holds rows J .. r0 + gh - 1
+  while (u >= r0 + gh - J) {
+    u -= r0 + gh - J;
+    ++J;
+  }
+  I = J + u;
+  return true;
+}
+
 __device__ __forceinline__ bool update_tile(const FactorDesc &d, int kind, int p0, int nb, int j, int TM, int TN,
-                                            int sel, int &row0, int &col0, int &ks, int &ke) {
+                                            int sel, int bx, int &row0, int &col0, int &ks, int &ke) {
   if (j >= d.nf) return false;
   const int pend = min(p0 + nb, d.nf);
   int r0, c0, cend;
@@ -172,22 +220,10 @@ __device__ __forceinline__ bool update_tile(const FactorDesc &d, int kind, int p
   const int nr = (d.nrows - r0) / TM;
   int I, J;
   if (kind == KIND_TRSM) {
-    if ((int)blockIdx.x >= nr) return false;
-    I = blockIdx.x; J = 0;
-  } else {
-    const int nc = (cend - c0) / TN;
-    const int tri = nc * (nc + 1) / 2;
-    const int t = blockIdx.x;
-    if (t >= tri + (nr - nc) * nc) return false;
-    if (t < tri) {
-      int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while (i * (i + 1) / 2 > t) --i;
-      while ((i + 1) * (i + 2) / 2 <= t) ++i;
-      I = i; J = t - i * (i + 1) / 2;
-    } else {
-      const int u = t - tri;
-      I = nc + u / nc; J = u % nc;
-    }
+    if (bx >= nr) return false;
+    I = bx; J = 0;
+  } else if (!trap_grouped(bx, nr, (cend - c0) / TN, I, J)) {
+    return false;
   }
   row0 = r0 + I * TM;
   col0 = c0 + J * TN;
@@ -266,9 +302,11 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   __shared__ __attribute__((aligned(16))) T As[2][KCH][TM + PAD];
   __shared__ __attribute__((aligned(16))) T Bs[2][KCH][TN + PAD];
 
-  const FactorDesc d = descs[blockIdx.y];
+  int bx, by;
+  xcd_order(bx, by);
+  const FactorDesc d = descs[by];
   int row0, col0, ks, ke;
-  if (!update_tile(d, kind, p0, nb, j, TM, TN, SEL, row0, col0, ks, ke)) return;
+  if (!update_tile(d, kind, p0, nb, j, TM, TN, SEL, bx, row0, col0, ks, ke)) return;
 
   const int ld = d.ld;
   gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
@@ -392,9 +430,11 @@ __global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__
   __shared__ bf8 As[2][KG][TM];
   __shared__ bf8 Bs[2][KG][TN];
 
-  const FactorDesc d = descs[blockIdx.y];
+  int bx, by;
+  xcd_order(bx, by);
+  const FactorDesc d = descs[by];
   int row0, col0, ks, ke;
-  if (!update_tile(d, kind, p0, nb, p0, TM, TN, 1, row0, col0, ks, ke)) return;
+  if (!update_tile(d, kind, p0, nb, p0, TM, TN, 1, bx, row0, col0, ks, ke)) return;
   const int ld = d.ld;
   gcT *Ag = gptr((const float *)d.A) + (size_t)ks * ld + row0;
   gcT *Bg = gptr((const float *)d.A) + (size_t)ks * ld + col0;
@@ -601,6 +641,7 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
             }
           }
           if (gx == 0) continue;
+          gx = round_up(gx, 8);   // xcd_order needs a grid of a multiple of 8 workgroups
           ctx.launch(INLA_K_PANEL, fl, by, [&] {
             hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, pd,
                                kind, p0, nb, j);
@@ -638,6 +679,7 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
       by_q += elq > 0 ? 2.0 * esz * elq + esz * (nrq + ncq) * kr : 0.0;
     }
     if (gx == 0) return;
+    gx = round_up(gx, 8);   // xcd_order needs a grid of a multiple of 8 workgroups
     if (split) {
       // BF16 operands for the factored rows only: the border rows carry the
       // constraint rows and the right-hand side, whose Schur block (C Q^{-1}
