@@ -38,6 +38,12 @@ struct FactorDesc {
   int ncols;       // nf <= ncols <= nrows, multiple of PADN
   int id_row0;     // first row of an identity border block (INT_MAX if none)
   int pad_;
+  // BF16 copies of the current panel for the BF16 trailing update, two slots
+  // (panel parity): slot s holds entry (k-group g, row r) = the eight panel
+  // values of row r at k = p0 + 8g .. p0 + 8g + 7 as 16 bytes at
+  // pbf[s * pbf_slot + g * nf + r]; rows [p0 + nb, nf) are written
+  void *pbf;
+  int64_t pbf_slot;  // entries per slot
 };
 
 // Likelihood / prior kinds (values match the C header).

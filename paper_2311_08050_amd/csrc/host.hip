@@ -146,6 +146,24 @@ void Ctx::drop_graphs() {
   graph_cache.clear();
 }
 
+char *Ctx::pbf_reserve(size_t bytes) {
+  if (bytes <= pbf_size) return pbf;
+  if (pbf) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
+    if (side && hipStreamSynchronize(side) != hipSuccess) return nullptr;
+    (void)hipFree(pbf);
+    pbf = nullptr;
+    pbf_size = 0;
+  }
+  if (hipMalloc(&pbf, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    pbf = nullptr;
+    return nullptr;
+  }
+  pbf_size = bytes;
+  return pbf;
+}
+
 bool Ctx::reserve(size_t bytes) {
   if (bytes <= ws_size) return true;
   if (ws) {
@@ -239,6 +257,7 @@ Ctx::~Ctx() {
   if (ev_a) (void)hipEventDestroy(ev_a);
   if (ev_b) (void)hipEventDestroy(ev_b);
   if (ws) (void)hipFree(ws);
+  if (pbf) (void)hipFree(pbf);
   if (ring) (void)hipFree(ring);
   if (ring_host) (void)hipHostFree(ring_host);
 }

@@ -69,6 +69,10 @@ struct Ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   int side_ready();   // creates the side stream and its events on first use
+  // scratch of the BF16 panel copies (grow-only, reallocated after a stream sync)
+  char *pbf = nullptr;
+  size_t pbf_size = 0;
+  char *pbf_reserve(size_t bytes);
   // autotuned (panel width, trailing tile) per (precision, padded order, batch bucket)
   std::map<std::vector<int64_t>, TuneCfg> tune;
 

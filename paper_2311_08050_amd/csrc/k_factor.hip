@@ -287,7 +287,9 @@ template <typename T, int TM, int TN, int SEL>
 __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
                                                              int p0, int nb, int j) {
   constexpr bool F64 = sizeof(T) == 8;
-  constexpr int KCH = F64 ? 16 : 32;            // K chunk staged per LDS buffer
+  // K chunk staged per LDS buffer: 16 deep in both precisions, which keeps a
+  // 128 x 128 FP32 tile's buffers at 34 KB (up to four workgroups per CU)
+  constexpr int KCH = 16;
   constexpr int VEC = 16 / sizeof(T);           // elements per 16-byte global load
   constexpr int WM = 2, WN = 2;                 // 2 x 2 waves
   constexpr int WTM = TM / WM, WTN = TN / WN;   // wave tile
@@ -398,35 +400,47 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
 }
 
 // --------------------------------------------------------------------------
-// Trailing update with BF16 operands: FP32 storage, the panel values rounded to
-// BF16 (round to nearest even) on their way into LDS, v_mfma_f32_16x16x32_bf16
-// with FP32 accumulation, FP32 read-modify-write of C.  That instruction takes
-// in lane l the row (l%16) of A and the column (l%16) of B^T at the eight k
-// values 8(l/16) .. 8(l/16)+7, and returns D rows 4(l/16)+v of column (l%16)
-// (the FP32 layout, so the epilogue is shared).
+// Trailing update with BF16 operands (factored rows only): FP32 storage, the
+// panel rounded once to BF16 (round to nearest even) into a packed copy,
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, FP32 read-modify-write of
+// C.  That instruction takes in lane l the row (l%16) of A and the column
+// (l%16) of B^T at the eight k values 8(l/16) .. 8(l/16)+7, and returns D rows
+// 4(l/16)+v of column (l%16) (the FP32 layout, so the epilogue is shared).
 //
-// Staging: a K chunk of 64 is 8 groups of 8 k values.  Thread (row quad q,
-// group g) loads four consecutive rows at the group's 8 k values with 16-byte
-// loads (a half-wave covers 512 contiguous bytes per k), transposes them in
-// registers and writes each row's eight BF16 values as one 16-byte LDS entry.
-// LDS holds entry [g][row] at slot row ^ ((row >> 4) & 3): the four rows a
-// lane writes per instruction and the sixteen rows a quarter-wave reads then
-// fall into distinct 16-byte slots of a 256-byte bank window.
+// The packed copy holds, per group of eight k values, one 16-byte entry per
+// row, which is exactly an MFMA operand: a K chunk of 32 is 4 groups x 128
+// rows of entries, loaded with 16-byte loads (a wave covers 1 KB contiguous)
+// and stored unchanged into LDS.  LDS holds entry [g][row] at slot
+// row ^ ((row >> 4) & 3), so that the sixteen rows a quarter-wave reads fall
+// into distinct 16-byte slots of a 256-byte bank window.
 // --------------------------------------------------------------------------
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef __attribute__((address_space(1))) const bf8 gcbf8;
 
 __device__ __forceinline__ int bf_slot(int r) { return r ^ ((r >> 4) & 3); }
+
+// Packed BF16 copy of the panel [p0, pend) for rows [pend, nf): one thread per
+// (row, group of eight k), slot (p0 / nb) & 1.
+__global__ __launch_bounds__(256) void panel_bf16_kernel(const FactorDesc *__restrict__ descs, int p0, int nb) {
+  const FactorDesc d = descs[blockIdx.z];
+  const int pend = min(p0 + nb, d.nf);
+  const int r = pend + blockIdx.x * 256 + threadIdx.x, gk = blockIdx.y;
+  if (r >= d.nf || p0 + 8 * gk >= pend) return;
+  const __attribute__((address_space(1))) float *src = gptr((const float *)d.A) + (size_t)(p0 + 8 * gk) * d.ld + r;
+  bf8 v;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = (__bf16)src[(size_t)i * d.ld];
+  bf8 *dst = (bf8 *)d.pbf + (size_t)((p0 / nb) & 1) * d.pbf_slot + (size_t)gk * d.nf + r;
+  *gptr(dst) = v;
+}
 
 template <int TM, int TN>
 __global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__restrict__ descs, int kind, int p0,
                                                             int nb) {
-  constexpr int KCH = 64, KG = KCH / 8;
+  constexpr int KCH = 32, KG = KCH / 8;
   constexpr int WM = 2, WN = 2, WTM = TM / WM, WTN = TN / WN, BM = WTM / 16, BN = WTN / 16;
-  constexpr int QA = TM / 4, QB = TN / 4;              // row quads per K group
-  static_assert(QA * KG == 256 && QB * KG == 256, "one row quad of A and of B per thread");
+  constexpr int EA = KG * TM / 256, EB = KG * TN / 256;   // entries per thread per chunk
   typedef __attribute__((address_space(1))) float gT;
-  typedef __attribute__((address_space(1))) const float gcT;
-  typedef __attribute__((address_space(1))) const f4 gcf4;
   __shared__ bf8 As[2][KG][TM];
   __shared__ bf8 Bs[2][KG][TN];
 
@@ -436,15 +450,14 @@ __global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__
   int row0, col0, ks, ke;
   if (!update_tile(d, kind, p0, nb, p0, TM, TN, 1, bx, row0, col0, ks, ke)) return;
   const int ld = d.ld;
-  gcT *Ag = gptr((const float *)d.A) + (size_t)ks * ld + row0;
-  gcT *Bg = gptr((const float *)d.A) + (size_t)ks * ld + col0;
+  // the packed panel: entry (group g, row r) at P[g * nf + r]; k = ks + 8 g
+  gcbf8 *P = gptr((const bf8 *)d.pbf + (size_t)((p0 / nb) & 1) * d.pbf_slot);
   gT *Cg = gptr((float *)d.A) + (size_t)col0 * ld + row0;
-  const int K = ke - ks;
+  const int K = ke - ks, nf = d.nf;
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = w / WN, wn = w % WN;
   const int g = lane >> 4, li = lane & 15;
-  const int qa = tid % QA, ga = tid / QA, qb = tid % QB, gb = tid / QB;
 
   f4 acc[BM][BN];
 #pragma unroll
@@ -452,25 +465,30 @@ __global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__
 #pragma unroll
     for (int b = 0; b < BN; ++b) acc[a][b] = f4{0, 0, 0, 0};
 
-  f4 ra[8], rb[8];
+  bf8 ra[EA], rb[EB];
   auto gload = [&](int kc) {
+    const int g0 = kc / 8;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      ra[i] = *reinterpret_cast<gcf4 *>(Ag + (size_t)(kc + 8 * ga + i) * ld + 4 * qa);
-      rb[i] = *reinterpret_cast<gcf4 *>(Bg + (size_t)(kc + 8 * gb + i) * ld + 4 * qb);
+    for (int i = 0; i < EA; ++i) {
+      const int e = i * 256 + tid, eg = e / TM, er = e % TM;
+      ra[i] = P[(size_t)(g0 + eg) * nf + row0 + er];
+    }
+#pragma unroll
+    for (int i = 0; i < EB; ++i) {
+      const int e = i * 256 + tid, eg = e / TN, er = e % TN;
+      rb[i] = P[(size_t)(g0 + eg) * nf + col0 + er];
     }
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      bf8 va, vb;
+    for (int i = 0; i < EA; ++i) {
+      const int e = i * 256 + tid;
+      As[buf][e / TM][bf_slot(e % TM)] = ra[i];
+    }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        va[i] = (__bf16)ra[i][rr];
-        vb[i] = (__bf16)rb[i][rr];
-      }
-      As[buf][ga][bf_slot(4 * qa + rr)] = va;
-      Bs[buf][gb][bf_slot(4 * qb + rr)] = vb;
+    for (int i = 0; i < EB; ++i) {
+      const int e = i * 256 + tid;
+      Bs[buf][e / TN][bf_slot(e % TN)] = rb[i];
     }
   };
 
@@ -587,6 +605,20 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return fs[a].d.nf > fs[b].d.nf; });
   std::vector<FactorDesc> hd(B);
   for (int i = 0; i < B; ++i) hd[i] = fs[order[i]].d;
+  const bool split = std::is_same<T, float>::value && bf16_trail;
+  if (split) {
+    // two slots of the packed BF16 panel copy per theta (16-byte entries)
+    size_t entries = 0;
+    for (int i = 0; i < B; ++i) entries += 2 * (size_t)(nb / 8) * hd[i].nf;
+    char *base = ctx.pbf_reserve(16 * entries);
+    if (!base) return INLA_ERR_NOMEM;
+    size_t off = 0;
+    for (int i = 0; i < B; ++i) {
+      hd[i].pbf = base + 16 * off;
+      hd[i].pbf_slot = (int64_t)(nb / 8) * hd[i].nf;
+      off += 2 * (size_t)hd[i].pbf_slot;
+    }
+  }
   FactorDesc *dd = (FactorDesc *)ctx.upload(hd.data(), sizeof(FactorDesc) * B);
   if (!dd) return INLA_ERR_NOMEM;
   const int nf_max = hd[0].nf;
@@ -603,10 +635,8 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
     key0.insert(key0.end(), {h.d.nf, h.d.nrows, h.d.ncols, h.d.id_row0, h.n_real, h.kb_real, h.ks_real});
   }
   // the panel [p0, p0 + nb): potf2_inv, TRSM and in-panel update of every
-  // 64-wide block, enqueued on ctx.stream
-  auto panel = [&](int p0) -> int {
-    std::vector<int64_t> key = key0;
-    key.push_back(p0);
+  // 64-wide block (one graph replay), enqueued on ctx.stream
+  auto panel_seq = [&](int p0, const std::vector<int64_t> &key) -> int {
     return ctx.sequence(INLA_K_PANEL, key, hd.data(), sizeof(FactorDesc) * B, [&](const void *dv) {
       const FactorDesc *pd = (const FactorDesc *)dv;
       for (int j = p0; j < p0 + nb && j < nf_max; j += NBI) {
@@ -650,12 +680,35 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
       }
     });
   };
+  // the packed BF16 copy of panel p0 for the BF16 trailing update, on ctx.stream
+  auto panel_copy = [&](int p0) {
+    const int act = active(p0);
+    int rows = 0;
+    double by = 0;
+    for (int i = 0; i < act; ++i) {
+      const HostFactor &h = fs[order[i]];
+      const int pend = std::min(p0 + nb, h.d.nf);
+      rows = std::max(rows, h.d.nf - pend);
+      by += 6.0 * std::max(0, h.n_real - pend) * (double)std::max(0, std::min(pend, h.n_real) - p0);
+    }
+    if (rows <= 0) return;
+    ctx.launch(INLA_K_PANEL, 0.0, by, [&] {
+      hipLaunchKernelGGL(panel_bf16_kernel, dim3((rows + 255) / 256, nb / 8, act), dim3(256), 0, ctx.stream, dd, p0,
+                         nb);
+    });
+  };
+  auto panel = [&](int p0) -> int {
+    std::vector<int64_t> key = key0;
+    key.push_back(p0);
+    const int rc = panel_seq(p0, key);
+    if (!rc && split) panel_copy(p0);
+    return rc;
+  };
   // the trailing update of kind TRAIL (everything right of the panel), TRAIL_A
   // (the next panel's columns) or TRAIL_B (the columns after the next panel),
   // enqueued on ctx.stream
   auto trail = [&](int p0, int kind) {
     const int act = active(p0);
-    const bool split = std::is_same<T, float>::value && bf16_trail;
     const int TT = split ? 128 : tm;   // the BF16 split path has 128 x 128 tiles only
     int gx = 0;
     double fl = 0, by = 0, fl_q = 0, by_q = 0;   // all tiles; tiles of the factored rows only
