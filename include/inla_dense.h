@@ -243,6 +243,76 @@ int inla_mlp_train_step(inla_mlp *m, int32_t B, const float *x, const double *ta
 int inla_mlp_predict_modes(inla_mlp *m, int32_t B, const double *theta, int32_t ldtheta, const double *centre,
                            const double *scale, double *const *x);
 
+/* --------------------------------------------- hyperparameter mode and CCD */
+/* Stage 1 of the method (section "Stage 1", appendix "Marginal posteriors of the
+ * hyperparameters"): theta* = argmin -log pi~(theta | y) with
+ * log pi~(theta | y) = log pi~(y | theta) (inla_laplace_eval's objective, Eq. (41))
+ * + log pi(theta), by BFGS (Nocedal and Wright's inverse-Hessian update, scaled
+ * by s^T y / y^T y at the first update, steepest descent restart on a
+ * non-descent direction), with central-difference gradients.  Every gradient
+ * (2t points) and every round of the backtracking line search (Armijo,
+ * c1 = 1e-4, step lengths 1, 1/2, ..., 1/2^11 in rounds of four) is one batched
+ * inla_laplace_eval call, warm-started from the mode at the current point.  The
+ * step is first scaled so that its largest component is at most max_step. */
+typedef double (*inla_log_prior_fn)(const double *theta, int32_t t, void *user);  /* log pi(theta), host */
+typedef struct inla_theta_opts {
+  int32_t max_iter;   /* BFGS iterations, <= 0: 100                                        */
+  int32_t reserved;
+  double h;           /* central-difference step in theta, <= 0: 1e-3                      */
+  double gtol;        /* stop when ||gradient||_inf <= gtol, <= 0: 1e-3                    */
+  double ftol;        /* stop when the decrease of -log pi~ <= ftol max(1, |value|), <= 0: 1e-12 */
+  double max_step;    /* largest component of a step before the line search, <= 0: 1      */
+  inla_opts eval;     /* options of every Laplace evaluation (start is managed here)       */
+} inla_theta_opts;
+#define INLA_THETA_OK 0            /* converged (gradient or decrease test)                  */
+#define INLA_THETA_MAXIT 1         /* max_iter reached                                       */
+#define INLA_THETA_LINESEARCH 2    /* no step length of the line search decreased enough    */
+#define INLA_THETA_EVAL_FAILED 3   /* an evaluation at the iterate failed (info != 0)        */
+#define INLA_THETA_NOT_PD (-2000)  /* inla_ccd_points: the negative Hessian is not positive definite */
+#define INLA_CCD_MAX_T 12
+/* model: one model (its device arrays), t = number of theta components of its
+ * prior kind plus one; theta0 (host [t]); log_prior may be NULL (flat).  Host
+ * outputs: theta_star [t], f_star = log pi~(theta* | y) (may be NULL), grad =
+ * gradient of log pi~ at theta* (may be NULL), iterations, evaluations, info
+ * (INLA_THETA_*).  Returns -i for an invalid i-th argument (-3: t does not
+ * match the prior kind), else the status of the Laplace evaluations. */
+int inla_theta_mode(inla_handle *h, const inla_model *model, int32_t t, const double *theta0,
+                    const inla_theta_opts *opts, inla_log_prior_fn log_prior, void *user, double *theta_star,
+                    double *f_star, double *grad, int32_t *iters, int32_t *evals, int32_t *info);
+/* Negative Hessian of log pi~(theta | y) at theta (host [t]) by central
+ * differences with step `step` (<= 0: 5e-3): diagonal (f(+h) - 2 f(0) + f(-h)) / h^2,
+ * off-diagonal four-point stencil, 1 + 2 t^2 evaluations, the last 2 t^2 in
+ * one batch (the paper's bound is 2 (t^2 + t)).  Writes neg_hess (host t x t,
+ * row-major) and log_post = log pi~(theta | y) (may be NULL); info (may be
+ * NULL) is INLA_THETA_EVAL_FAILED if an evaluation failed. */
+int inla_theta_hessian(inla_handle *h, const inla_model *model, int32_t t, const double *theta, double step,
+                       const inla_opts *opts, inla_log_prior_fn log_prior, void *user, double *neg_hess,
+                       double *log_post, int32_t *info);
+/* Central composite design (section "Hyperparameter exploration": 45 points
+ * at t = 6) in the standardised z scale: the centre, the 2t axial points
+ * +-f0 sqrt(t) e_i, and the factorial points f0 (+-1, ..., +-1): all 2^t for
+ * t <= 4, for t >= 5 the half fraction whose last coordinate is the product of
+ * the others (1 + 2t + 2^(t-1) points: 27 at t = 5, 45 at t = 6); none at
+ * t = 1.  Every point but the centre lies on the sphere |z| = f0 sqrt(t), f0 > 1.
+ * delta: design weights relative to the density's value at each point, chosen
+ * so that the rule is exact for the mass, mean and covariance of a standard
+ * Gaussian: 1 - 1/f0^2 at the centre, exp(f0^2 t / 2) / (f0^2 (n - 1)) elsewhere.
+ * With z and delta NULL only *n_points is written; otherwise *n_points is the
+ * capacity on input (-3 and the needed count when too small), z is host
+ * [n x t] row-major and delta host [n].  Host only, no handle. */
+int inla_ccd_design(int32_t t, double f0, int32_t *n_points, double *z, double *delta);
+/* The design mapped to theta: theta_k = theta* + V Lambda^{1/2} z_k with the
+ * eigen-decomposition Sigma = neg_hess^{-1} = V Lambda V^T (the z-parameterisation
+ * of the appendix on asymmetric Gaussian interpolation).  neg_hess host t x t
+ * row-major (symmetrised); returns INLA_THETA_NOT_PD if it is not positive
+ * definite.  *n_points: capacity in, count out; theta_k host [n x t], delta host [n]. */
+int inla_ccd_points(int32_t t, const double *theta_star, const double *neg_hess, double f0, int32_t *n_points,
+                    double *theta_k, double *delta);
+/* Integration weights of the explored points: w_k proportional to
+ * delta_k exp(log_post_k), normalised to sum 1 (host arrays of n_points; a
+ * non-finite log_post_k gets weight 0). */
+int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_post, double *weights);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */
 enum {

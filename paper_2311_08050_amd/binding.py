@@ -34,7 +34,8 @@ EXPORTS = [
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
-    "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats", "inla_autotune", "inla_tune_set", "inla_tune_get",
+    "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats",
+    "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
 ]
 # Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
 # reports their times; the fastest is then timed with lookahead as well.
@@ -67,6 +68,15 @@ class Result(C.Structure):
 
     def asdict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ThetaOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("reserved", C.c_int32), ("h", C.c_double), ("gtol", C.c_double),
+                ("ftol", C.c_double), ("max_step", C.c_double), ("eval", Opts)]
+
+
+LOG_PRIOR_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_int32, C.c_void_p)
+THETA_STATUS = {0: "ok", 1: "max_iter", 2: "line_search", 3: "eval_failed"}
 
 
 class KStats(C.Structure):
@@ -105,6 +115,13 @@ def load_library(path: str = LIBPATH):
     lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pd, pi32]
     lib.inla_tune_set.argtypes = [P, i32, i32, i32, pi32]
     lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32]
+    lib.inla_theta_mode.argtypes = [P, C.POINTER(Model), i32, pd, C.POINTER(ThetaOpts), LOG_PRIOR_FN, P, pd, pd, pd,
+                                    pi32, pi32, pi32]
+    lib.inla_theta_hessian.argtypes = [P, C.POINTER(Model), i32, pd, C.c_double, C.POINTER(Opts), LOG_PRIOR_FN, P, pd,
+                                       pd, pi32]
+    lib.inla_ccd_design.argtypes = [i32, C.c_double, pi32, pd, pd]
+    lib.inla_ccd_points.argtypes = [i32, pd, pd, C.c_double, pi32, pd, pd]
+    lib.inla_ccd_weights.argtypes = [i32, pd, pd, pd]
     lib.inla_version.restype = C.c_char_p
     for name in EXPORTS:
         if name != "inla_version":
@@ -230,6 +247,71 @@ class Library:
                                         theta.shape[1], xptrs, vptrs, info)
         self._check(rc, "inla_marginal_var")
         return var, np.array(info[:], dtype=np.int32)
+
+    # ------------------------------------------------------------- theta mode, Hessian, CCD
+    @staticmethod
+    def _prior(log_prior):
+        if log_prior is None:
+            return LOG_PRIOR_FN()
+        return LOG_PRIOR_FN(lambda th, t, user: float(log_prior(np.ctypeslib.as_array(th, shape=(t,)).copy())))
+
+    def theta_mode(self, dmodel, theta0, log_prior=None, max_iter=0, h=0.0, gtol=0.0, ftol=0.0, max_step=0.0,
+                   prec="fp64"):
+        """BFGS mode of log pi~(theta | y); returns a dict (theta, log_post, grad,
+        iters, evals, info)."""
+        th0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        t = len(th0)
+        o = ThetaOpts(max_iter=max_iter, reserved=0, h=h, gtol=gtol, ftol=ftol, max_step=max_step,
+                      eval=Opts(prec=PREC[prec], max_iter=0, tol=0.0, start=0, reserved=0))
+        cb = self._prior(log_prior)
+        out, grad = np.zeros(t), np.zeros(t)
+        fs = C.c_double()
+        it, ev, info = C.c_int32(), C.c_int32(), C.c_int32()
+        pd = C.POINTER(C.c_double)
+        rc = self.lib.inla_theta_mode(self.h, C.byref(dmodel.struct), t, th0.ctypes.data_as(pd), C.byref(o), cb, None,
+                                      out.ctypes.data_as(pd), C.byref(fs), grad.ctypes.data_as(pd), C.byref(it),
+                                      C.byref(ev), C.byref(info))
+        self._check(rc, "inla_theta_mode")
+        return {"theta": out, "log_post": fs.value, "grad": grad, "iters": it.value, "evals": ev.value,
+                "info": info.value}
+
+    def theta_hessian(self, dmodel, theta, step=0.0, log_prior=None, prec="fp64"):
+        """(negative Hessian t x t, log pi~ at theta, info)."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        t = len(th)
+        H = np.zeros((t, t))
+        lp = C.c_double()
+        info = C.c_int32()
+        o = Opts(prec=PREC[prec], max_iter=0, tol=0.0, start=0, reserved=0)
+        pd = C.POINTER(C.c_double)
+        rc = self.lib.inla_theta_hessian(self.h, C.byref(dmodel.struct), t, th.ctypes.data_as(pd), step, C.byref(o),
+                                         self._prior(log_prior), None, H.ctypes.data_as(pd), C.byref(lp),
+                                         C.byref(info))
+        self._check(rc, "inla_theta_hessian")
+        return H, lp.value, info.value
+
+    def ccd_points(self, theta_star, neg_hess, f0=1.1):
+        """(theta_k [n x t], delta [n]) of the CCD exploration around theta*."""
+        th = np.ascontiguousarray(theta_star, dtype=np.float64)
+        t = len(th)
+        H = np.ascontiguousarray(neg_hess, dtype=np.float64)
+        n = C.c_int32(0)
+        self._check(self.lib.inla_ccd_design(t, f0, C.byref(n), None, None), "inla_ccd_design")
+        pts, delta = np.zeros((n.value, t)), np.zeros(n.value)
+        pd = C.POINTER(C.c_double)
+        rc = self.lib.inla_ccd_points(t, th.ctypes.data_as(pd), H.ctypes.data_as(pd), f0, C.byref(n),
+                                      pts.ctypes.data_as(pd), delta.ctypes.data_as(pd))
+        self._check(rc, "inla_ccd_points")
+        return pts, delta
+
+    def ccd_weights(self, delta, log_post):
+        d = np.ascontiguousarray(delta, dtype=np.float64)
+        lp = np.ascontiguousarray(log_post, dtype=np.float64)
+        w = np.zeros(len(d))
+        pd = C.POINTER(C.c_double)
+        self._check(self.lib.inla_ccd_weights(len(d), d.ctypes.data_as(pd), lp.ctypes.data_as(pd),
+                                              w.ctypes.data_as(pd)), "inla_ccd_weights")
+        return w
 
     # ------------------------------------------------------------- graphs and tuning
     def set_graphs(self, on: bool):
