@@ -243,6 +243,28 @@ int inla_mlp_train_step(inla_mlp *m, int32_t B, const float *x, const double *ta
 int inla_mlp_predict_modes(inla_mlp *m, int32_t B, const double *theta, int32_t ldtheta, const double *centre,
                            const double *scale, double *const *x);
 
+/* ------------------------------------------- variational-Bayes mean correction */
+/* Correction of the posterior mean by variational Bayes (appendix "Variational
+ * Bayes approximation strategy", algorithm "Correction of Posterior Mean using
+ * Variational Bayes"): x | y, theta ~ N(mu + lambda, Q*^{-1}) with Q* and the
+ * marginal variances s_i^2 of the Laplace approximation fixed; each iteration
+ * solves (Q_prior + diag I'') lambda = -(I' + Q_prior mu) (the minimiser of the
+ * second-order expansion of E[-log pi(y | eta)] + KLD, with the paper's sign of
+ * c taken so that lambda minimises), kriged so that C mu stays e, and sets
+ * mu <- mu + lambda, until ||lambda||_inf <= tol max(1, ||mu||_inf).  I' and I''
+ * are the expectations of -d log pi / d eta and -d^2 log pi / d eta^2 over
+ * eta_i ~ N(eta_i(mu), s_i^2) by n_gh-point Gauss-Hermite quadrature (<= 0: 20,
+ * at most 64; rule by Golub-Welsch on the host).  A Gaussian likelihood's
+ * correction is zero.  var[b]: device [n] marginal variances at the Laplace
+ * mode (e.g. from inla_marginal_var); x[b]: device [n], the Laplace mode on
+ * input, the corrected mean on output (left unchanged where info != 0).  opts:
+ * max_iter (<= 0: 50) and tol (<= 0: 1e-11) are used; prec must be FP64.
+ * iters, info: host [B] (INLA_INFO_* codes).  Returns -i for an invalid i-th
+ * argument, INLA_ERR_UNSUPPORTED for another precision. */
+int inla_vb_mean(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                 const double *const *var, double *const *x, int32_t n_gh, const inla_opts *opts, int32_t *iters,
+                 int32_t *info);
+
 /* --------------------------------------------- hyperparameter mode and CCD */
 /* Stage 1 of the method (section "Stage 1", appendix "Marginal posteriors of the
  * hyperparameters"): theta* = argmin -log pi~(theta | y) with

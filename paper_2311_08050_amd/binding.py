@@ -35,7 +35,7 @@ EXPORTS = [
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
     "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats",
-    "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
+    "inla_vb_mean", "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
 ]
 # Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
 # reports their times; the fastest is then timed with lookahead as well.
@@ -115,6 +115,8 @@ def load_library(path: str = LIBPATH):
     lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pd, pi32]
     lib.inla_tune_set.argtypes = [P, i32, i32, i32, pi32]
     lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32]
+    lib.inla_vb_mean.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), i32, C.POINTER(Opts),
+                                 pi32, pi32]
     lib.inla_theta_mode.argtypes = [P, C.POINTER(Model), i32, pd, C.POINTER(ThetaOpts), LOG_PRIOR_FN, P, pd, pd, pd,
                                     pi32, pi32, pi32]
     lib.inla_theta_hessian.argtypes = [P, C.POINTER(Model), i32, pd, C.c_double, C.POINTER(Opts), LOG_PRIOR_FN, P, pd,
@@ -352,6 +354,20 @@ class Library:
         cfg = (C.c_int32 * 3)()
         self._check(self.lib.inla_tune_get(self.h, PREC[prec], n_max, B, cfg), "inla_tune_get")
         return tuple(cfg[:])
+
+    def vb_mean(self, dmodels, theta, var, x_mode, n_gh=0, max_iter=0, tol=0.0):
+        """Variational-Bayes corrected means (device tensors, new) from the Laplace
+        modes and marginal variances; returns (means, iterations, info)."""
+        B, theta, models, _, _ = self._common(dmodels, theta, None)
+        xs = [t.clone() for t in x_mode]
+        xp = (C.c_void_p * B)(*[t.data_ptr() for t in xs])
+        vp = (C.c_void_p * B)(*[t.data_ptr() for t in var])
+        it, info = (C.c_int32 * B)(), (C.c_int32 * B)()
+        o = Opts(prec=0, max_iter=max_iter, tol=tol, start=0, reserved=0)
+        rc = self.lib.inla_vb_mean(self.h, B, models, theta.ctypes.data_as(C.POINTER(C.c_double)), theta.shape[1],
+                                   vp, xp, n_gh, C.byref(o), it, info)
+        self._check(rc, "inla_vb_mean")
+        return xs, np.array(it[:], dtype=np.int32), np.array(info[:], dtype=np.int32)
 
     # ------------------------------------------------------------- profiling
     def profile(self, on: bool):

@@ -75,6 +75,12 @@ struct ThetaDesc {
   void *linv;      // inverses of the big factor's 64 x 64 diagonal blocks (factor storage type)
   double *u;       // forward-solve output / refinement correction [n_pad]
   double *out;     // caller's output vector (mode or variances), device
+  // variational-Bayes mean correction: with vb_var set, the likelihood terms
+  // are expectations over eta ~ N(eta(x), vb_var[i]) by ngh-point Gauss-Hermite
+  // quadrature (gh: nodes, then weights divided by sqrt(pi))
+  const double *vb_var;
+  const double *gh;
+  int ngh;
 };
 
 // Per-theta device result slots.

@@ -258,6 +258,7 @@ Ctx::~Ctx() {
   if (ev_b) (void)hipEventDestroy(ev_b);
   if (ws) (void)hipFree(ws);
   if (pbf) (void)hipFree(pbf);
+  if (gh) (void)hipFree(gh);
   if (ring) (void)hipFree(ring);
   if (ring_host) (void)hipHostFree(ring_host);
 }
@@ -872,6 +873,59 @@ static int var_chunk(Ctx &ctx, int B, const inla_model *models, const double *th
   return ctx.check();
 }
 
+// Variational-Bayes correction of the posterior mean for one chunk: from the
+// Laplace mode in x, repeated constrained Newton-form passes whose likelihood
+// terms are Gauss-Hermite expectations over the fixed marginal variances.
+static int vb_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
+                    const double *const *var, double *const *x, int ngh, int max_iter, double tol, int32_t *iters,
+                    int32_t *info) {
+  Batch b(ctx);
+  int rc = setup(b, B, models, theta, ldtheta, MODE_LAPLACE);
+  if (rc) { teardown(b); return rc; }
+  auto fail = [&](int r) { teardown(b); return r; };
+  std::vector<int> all;
+  for (int i = 0; i < B; ++i) {
+    iters[i] = 0;
+    info[i] = 0;
+    ThetaDesc &t = b.plans[i].t;
+    t.vb_var = var[i];
+    t.gh = ctx.gh;
+    t.ngh = ngh;
+    if (hipMemcpyAsync(t.x, x[i], sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    if (t.n_pad > t.n && hipMemsetAsync(t.x + t.n, 0, sizeof(double) * (t.n_pad - t.n), ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    all.push_back(i);
+  }
+  if ((rc = prior_build(b, all))) return fail(rc);
+  std::vector<int> active = all;
+  for (int it = 1; it <= max_iter && !active.empty(); ++it) {
+    if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+    if ((rc = run_pass(b, active, PASS_NEWTON, INLA_PREC_FP64))) return fail(rc);
+    if ((rc = readback(b))) return fail(rc);
+    std::vector<int> next;
+    for (int i : active) {
+      const int *inf = &b.hinfo[4 * i];
+      const double *dr = &b.hdres[DRES_COUNT * i];
+      iters[i] = it;
+      if (inf[F_PRIOR]) info[i] = inf[F_PRIOR];
+      else if (dr[DRES_NONFINITE] != 0.0) info[i] = INLA_INFO_NONFINITE;
+      else if (inf[F_BIG]) info[i] = inf[F_BIG];
+      else if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) info[i] = INLA_INFO_CONSTRAINT_RANK;
+      else if (dr[DRES_STEP] <= tol * dr[DRES_SCALE]) continue;
+      else if (it == max_iter) info[i] = INLA_INFO_NEWTON_MAXIT;
+      else next.push_back(i);
+    }
+    active.swap(next);
+  }
+  for (int i = 0; i < B; ++i)
+    if (info[i] == 0 &&
+        hipMemcpyAsync(x[i], b.plans[i].t.x, sizeof(double) * b.plans[i].t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess)
+      return fail(INLA_ERR_HIP);
+  if (hipStreamSynchronize(ctx.stream) != hipSuccess) return fail(INLA_ERR_HIP);
+  ctx.harvest();
+  teardown(b);
+  return ctx.check();
+}
+
 }  // namespace inla
 
 // ====================================================================== C-ABI
@@ -1146,6 +1200,41 @@ int inla_tune_get(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, int32_
   if (!config) return -5;
   const TuneCfg c = tuned_config(h->ctx, prec, round_up(n_max, PADN), B);
   config[0] = c.nb; config[1] = c.tm; config[2] = c.look;
+  return INLA_OK;
+}
+
+int inla_vb_mean(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                 const double *const *var, double *const *x, int32_t n_gh, const inla_opts *opts, int32_t *iters,
+                 int32_t *info) {
+  int rc = validate_common(h, B, models, theta, ldtheta, nullptr, false);
+  if (rc) return rc;
+  if (B == 0) return INLA_OK;
+  if (!var) return -6;
+  if (!x) return -7;
+  for (int i = 0; i < B; ++i) {
+    if (!var[i]) return -6;
+    if (!x[i]) return -7;
+  }
+  if (n_gh <= 0) n_gh = 20;
+  if (n_gh > 64) return -8;
+  if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
+  if (!iters) return -10;
+  if (!info) return -11;
+  Ctx &ctx = h->ctx;
+  if (!ctx.gh && hipMalloc(&ctx.gh, sizeof(double) * 128) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx.gh = nullptr;
+    return INLA_ERR_NOMEM;
+  }
+  const std::vector<double> rule = gauss_hermite(n_gh);
+  if ((rc = ctx.upload_to(ctx.gh, rule.data(), sizeof(double) * rule.size()))) return rc;
+  const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 50;
+  const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-11;
+  for (auto c : chunks(ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
+    rc = vb_chunk(ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
+                  var + c.first, x + c.first, n_gh, max_iter, tol, iters + c.first, info + c.first);
+    if (rc) return rc;
+  }
   return INLA_OK;
 }
 

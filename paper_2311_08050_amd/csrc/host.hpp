@@ -69,6 +69,8 @@ struct Ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   int side_ready();   // creates the side stream and its events on first use
+  // Gauss-Hermite rule of the variational-Bayes correction (device, 2 x 64 doubles)
+  double *gh = nullptr;
   // scratch of the BF16 panel copies (grow-only, reallocated after a stream sync)
   char *pbf = nullptr;
   size_t pbf_size = 0;
@@ -127,5 +129,10 @@ int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, T
              int *n_cand);
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Small dense symmetric eigen-decomposition (host) and the Gauss-Hermite rule
+// built on it (nodes, then weights / sqrt(pi)).
+void sym_eigen(int t, std::vector<double> A, std::vector<double> &w, std::vector<double> &V);
+std::vector<double> gauss_hermite(int d);
 
 }  // namespace inla

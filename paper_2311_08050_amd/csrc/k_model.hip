@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void prior_assemble_kernel(const ThetaDesc *__
   }
 }
 
-__device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, double &g, double &W, double &ll) {
+__device__ __forceinline__ void lik_point_at(const ThetaDesc &t, int i, double x, double &g, double &W, double &ll) {
   const double y = t.y[i];
   if (t.lik == LIK_GAUSSIAN) {
     const double s2 = t.lpar;
@@ -107,6 +107,25 @@ __device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, d
     W = mu;
     ll = y * (log(E) + eta) - mu - lgamma(y + 1.0);
   }
+}
+
+// g = d log pi(y_i | eta) / d eta and W = -d^2 log pi / d eta^2 at eta(x); in a
+// variational-Bayes pass their expectations over eta ~ N(eta(x), vb_var[i])
+// (appendix "Variational Bayes approximation strategy": I' = -E g, I'' = E W),
+// by Gauss-Hermite quadrature: E h = sum_j w_j / sqrt(pi) h(eta + sqrt(2 var) r_j).
+__device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, double &g, double &W, double &ll) {
+  lik_point_at(t, i, x, g, W, ll);
+  if (!t.vb_var) return;
+  const double sd = sqrt(2.0 * t.vb_var[i]);
+  double eg = 0.0, ew = 0.0;
+  for (int j = 0; j < t.ngh; ++j) {
+    double gj, wj, lj;
+    lik_point_at(t, i, x + sd * t.gh[j], gj, wj, lj);
+    eg += t.gh[t.ngh + j] * gj;
+    ew += t.gh[t.ngh + j] * wj;
+  }
+  g = eg;
+  W = ew;
 }
 
 // The bordered posterior precision of one Newton step (algorithm "Gaussian

@@ -118,9 +118,15 @@ int gradient(Evaluator &ev, const std::vector<double> &th, double h, std::vector
   return INLA_OK;
 }
 
+int n_prior_params(int prior) { return prior == INLA_PRIOR_DENSE ? 0 : (prior == INLA_PRIOR_EXPCOV ? 2 : 3); }
+
+}  // namespace
+
+namespace inla {
+
 // Symmetric eigen-decomposition of a small matrix (cyclic Jacobi rotations):
 // A (t x t, row-major) = V diag(w) V^T, V's columns the eigenvectors.
-void jacobi_eigen(int t, std::vector<double> A, std::vector<double> &w, std::vector<double> &V) {
+void sym_eigen(int t, std::vector<double> A, std::vector<double> &w, std::vector<double> &V) {
   V.assign((size_t)t * t, 0.0);
   for (int i = 0; i < t; ++i) V[(size_t)i * t + i] = 1.0;
   for (int sweep = 0; sweep < 100; ++sweep) {
@@ -160,9 +166,26 @@ void jacobi_eigen(int t, std::vector<double> A, std::vector<double> &w, std::vec
   for (int i = 0; i < t; ++i) w[i] = A[(size_t)i * t + i];
 }
 
-int n_prior_params(int prior) { return prior == INLA_PRIOR_DENSE ? 0 : (prior == INLA_PRIOR_EXPCOV ? 2 : 3); }
+// Gauss-Hermite rule of d points for the weight e^{-z^2} (Golub-Welsch: the
+// nodes are the eigenvalues of the symmetric tridiagonal Jacobi matrix with
+// off-diagonal sqrt(k / 2), the weights sqrt(pi) times the squared first
+// components of its normalised eigenvectors).  Returns d nodes, then the d
+// weights divided by sqrt(pi) (they sum to 1).
+std::vector<double> gauss_hermite(int d) {
+  std::vector<double> J((size_t)d * d, 0.0), w, V;
+  for (int k = 1; k < d; ++k) J[(size_t)(k - 1) * d + k] = J[(size_t)k * d + k - 1] = std::sqrt(0.5 * k);
+  sym_eigen(d, J, w, V);
+  std::vector<double> out(2 * (size_t)d);
+  for (int j = 0; j < d; ++j) {
+    out[j] = w[j];
+    out[d + j] = V[j] * V[j];   // first row of V
+  }
+  return out;
+}
 
-}  // namespace
+}  // namespace inla
+
+using inla::sym_eigen;
 
 extern "C" {
 
@@ -396,7 +419,7 @@ int inla_ccd_points(int32_t t, const double *theta_star, const double *neg_hess,
   for (int i = 0; i < t; ++i)   // symmetrise
     for (int j = i + 1; j < t; ++j)
       H[(size_t)i * t + j] = H[(size_t)j * t + i] = 0.5 * (H[(size_t)i * t + j] + H[(size_t)j * t + i]);
-  jacobi_eigen(t, H, w, V);
+  sym_eigen(t, H, w, V);
   for (double v : w)
     if (!(v > 0.0)) return INLA_THETA_NOT_PD;
   int np = *n_points;
