@@ -181,6 +181,54 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
     }
 
 
+def run_extras(lib, binding, synth, dms, thetas, xs):
+    """Separately timed figures (not part of `value`): marginal variances and the
+    variational-Bayes mean correction of the headline batch (FP64, from the modes
+    the last variant left in xs), and Stage 1 plus the CCD exploration on the
+    n = 3000 space-time configuration."""
+    import numpy as np
+    import torch
+
+    out = {}
+    B = len(dms)
+    torch.cuda.synchronize()
+    lib.marginal_var(dms[:1], thetas[:1], xs[:1])           # warm-up (workspace, graphs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    var, info = lib.marginal_var(dms, thetas, xs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert np.all(info == 0), info
+    out["marginal_var"] = {"value": B / dt, "unit": "var-evals/s", "batch": B, "s": dt, "precision": "fp64"}
+    log(f"marginal variances: {B / dt:.2f} var-evals/s")
+    t0 = time.perf_counter()
+    mus, its, vinfo = lib.vb_mean(dms, thetas, var, xs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert np.all(vinfo == 0), vinfo
+    out["vb_mean"] = {"value": B / dt, "unit": "VB corrections/s", "batch": B, "s": dt,
+                      "iterations_mean": float(np.mean(its)), "precision": "fp64"}
+    log(f"VB mean correction: {B / dt:.2f} corrections/s, {np.mean(its):.2f} iterations")
+    m3, _ = synth.kron3000()
+    d3 = binding.DeviceModel(m3)
+    th0 = synth.kron_theta0(30)
+    prior = lambda th: -0.5 * float(np.sum((np.asarray(th) - th0) ** 2))   # noqa: E731
+    t0 = time.perf_counter()
+    g = lib.theta_mode(d3, th0 + np.array([0.2, 0.2, -0.2, 0.05]), log_prior=prior)
+    t1 = time.perf_counter()
+    H, _, hinfo = lib.theta_hessian(d3, g["theta"], log_prior=prior)
+    pts, delta = lib.ccd_points(g["theta"], H)
+    res, _ = lib.laplace_eval([d3] * len(pts), pts)
+    lib.ccd_weights(delta, [q["objective"] + prior(p) for q, p in zip(res, pts)])
+    t2 = time.perf_counter()
+    out["stage1_n3000"] = {"workload": "Poisson space-time n=3000 (100 regions x 30 times), k=129, t=4, "
+                                       "N(theta0, I) log prior", "mode_s": t1 - t0, "bfgs_iterations": g["iters"],
+                           "evaluations": g["evals"], "theta_evals_per_s": g["evals"] / (t1 - t0),
+                           "hessian_and_ccd_s": t2 - t1, "ccd_points": len(pts), "info": [g["info"], hinfo]}
+    log(f"stage 1 at n=3000: {t1 - t0:.2f} s ({g['iters']} iterations), Hessian + CCD {t2 - t1:.2f} s")
+    return out
+
+
 def main():
     import faulthandler
     faulthandler.enable()   # a crash in native code prints the Python stack that led to it
@@ -196,6 +244,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="factor with the default panel width and tile instead of tuning them first")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no hipGraph replays)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the separately timed marginal-variance, VB-correction and Stage-1 figures")
     ap.add_argument("--rocprof-window", metavar="CSV",
                     help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
     ap.add_argument("--bench-json", metavar="FILE", help="the JSON line printed by the profiled bench run")
@@ -304,6 +354,8 @@ def main():
         out["warm_start_training"] = dict(train_info, **MLP_TRAIN)
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = hv["value"] / results["fp64"]["value"]
+    if not args.no_extras:
+        out["extras"] = run_extras(lib, binding, synth, dms, thetas, xs)
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_info
 
