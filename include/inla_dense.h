@@ -109,6 +109,18 @@ typedef struct inla_model {
   const double *e;      /* device [k] constraint right-hand side, or NULL for zeros */
   const double *coords; /* device [n_s*2] points (x, y) row-major (EXPCOV, KRON)    */
   const double *Qprior; /* device, DENSE only: column-major n x n, lower triangle   */
+  /* Design matrix A (eta = offset + A x, the LGM of the Introduction).  m = 0:
+   * A = I and y, E have n entries.  m >= 1: A is m x n in CSR form (device
+   * arrays A_rowptr [m + 1], A_col [nnz], A_val [nnz], column indices in
+   * [0, n), A_rowptr[0] = 0, A_rowptr[m] = nnz) and y, E have m entries.
+   * Then Q* = Q_prior + A^T W A, whose pattern the library derives on the host
+   * once per call; such models are evaluated in FP64 (INLA_PREC_FP64 only)
+   * and the variational-Bayes correction is not available for them. */
+  int32_t m;
+  int32_t nnz;
+  const int32_t *A_rowptr;
+  const int32_t *A_col;
+  const double *A_val;
 } inla_model;
 
 /* Newton options (appendix "Gaussian approximation strategy", algorithm

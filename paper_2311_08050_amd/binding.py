@@ -50,6 +50,7 @@ class Model(C.Structure):
         ("n_s", C.c_int32), ("n_t", C.c_int32), ("ldq", C.c_int32), ("reserved", C.c_int32),
         ("y", C.c_void_p), ("E", C.c_void_p), ("C", C.c_void_p), ("e", C.c_void_p),
         ("coords", C.c_void_p), ("Qprior", C.c_void_p),
+        ("m", C.c_int32), ("nnz", C.c_int32), ("A_rowptr", C.c_void_p), ("A_col", C.c_void_p), ("A_val", C.c_void_p),
     ]
 
 
@@ -158,12 +159,27 @@ class DeviceModel:
         Q = model.get("Qprior")
         # column-major n x n: the transpose of a C-order array is its column-major view
         self.Q = dev(np.asarray(Q).T) if Q is not None else None
+        # a general design matrix travels in CSR form (built from the dense array)
+        A = model.get("A")
+        self.m, self.nnz = 0, 0
+        self.A_rowptr = self.A_col = self.A_val = None
+        if A is not None:
+            A = np.asarray(A, dtype=np.float64)
+            rows, cols = np.nonzero(A)
+            self.m, self.nnz = int(A.shape[0]), int(len(rows))
+            rowptr = np.zeros(self.m + 1, dtype=np.int32)
+            np.add.at(rowptr, rows + 1, 1)
+            rowptr = np.cumsum(rowptr).astype(np.int32)
+            self.A_rowptr = torch.as_tensor(rowptr).to(device)
+            self.A_col = torch.as_tensor(cols.astype(np.int32)).to(device)
+            self.A_val = dev(A[rows, cols])
         self.struct = Model(
             n=self.n, k=self.k, lik=LIK[model["lik"]], prior=PRIOR[model["prior"]],
             n_s=int(model.get("n_s") or self.n), n_t=int(model.get("n_t") or 1),
             ldq=self.n if Q is not None else 0, reserved=0,
             y=_ptr(self.y), E=_ptr(self.E), C=_ptr(self.C), e=_ptr(self.e),
             coords=_ptr(self.coords), Qprior=_ptr(self.Q),
+            m=self.m, nnz=self.nnz, A_rowptr=_ptr(self.A_rowptr), A_col=_ptr(self.A_col), A_val=_ptr(self.A_val),
         )
 
 

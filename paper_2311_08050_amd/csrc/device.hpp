@@ -81,6 +81,19 @@ struct ThetaDesc {
   const double *vb_var;
   const double *gh;
   int ngh;
+  // general design matrix (m > 0; m == 0 means A = I): the caller's CSR, its
+  // CSC and the lower pattern of A^T A (column c: entries patp[c] .. patp[c+1],
+  // entry e in row patr[e] with terms patt[e] .. patt[e+1] of coefficient
+  // tcoef[q] = A_{i r} A_{i c} for observation tobs[q]); per-observation
+  // workspace: A x, the likelihood terms g, W and log pi(y_i | eta_i)
+  int m;
+  const int *A_rowptr, *A_col;
+  const double *A_val;
+  const int *cscp, *csci;
+  const double *cscv;
+  const int *patp, *patr, *patt, *tobs;
+  const double *tcoef;
+  double *obs_ax, *obs_g, *obs_W, *obs_ll;
 };
 
 // Per-theta device result slots.

@@ -267,7 +267,7 @@ Ctx::~Ctx() {
 // Per-theta workspace plan.
 struct Plan {
   ThetaDesc t{};
-  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, off_linv_small = 0, bytes = 0;
+  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, off_linv_small = 0, off_obs = 0, bytes = 0;
   int ns_real = 0;
   bool needs_prior_build = false;
 };
@@ -279,6 +279,7 @@ static int n_prior_params(int prior) { return prior == PRIOR_DENSE ? 0 : (prior 
 // Validate one model; returns 0 or a negative argument index code.
 static int check_model(const inla_model &m) {
   if (m.n < 1 || m.k < 0 || m.k >= m.n) return -1;
+  if (m.m < 0 || (m.m > 0 && (m.nnz < 0 || !m.A_rowptr || (m.nnz > 0 && (!m.A_col || !m.A_val))))) return -1;
   if (m.lik != LIK_GAUSSIAN && m.lik != LIK_POISSON) return -1;
   if (!m.y) return -1;
   if (m.k > 0 && !m.C) return -1;
@@ -338,6 +339,10 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
   // build, whose order is at most n_pad) and kriging factor
   p.off_linv = off; off += align256(sizeof(double) * (size_t)t.n_pad * NBI);
   p.off_linv_small = off; off += align256(sizeof(double) * (size_t)std::max(t.k_pad, NBI) * NBI);
+  // general design matrix: A x, g, W and log-likelihood per observation
+  t.m = m.m;
+  t.A_rowptr = m.A_rowptr; t.A_col = m.A_col; t.A_val = m.A_val;
+  p.off_obs = off; off += align256(sizeof(double) * 4 * (size_t)m.m);
   p.bytes = off;
   return p;
 }
@@ -360,6 +365,10 @@ static void bind(Plan &p, char *base) {
   t.part = v; v += 2 * t.ldw;
   t.dres = v;
   t.linv = (void *)(base + p.off_linv);
+  if (t.m > 0) {
+    double *o = (double *)(base + p.off_obs);
+    t.obs_ax = o; t.obs_g = o + t.m; t.obs_W = o + 2 * (size_t)t.m; t.obs_ll = o + 3 * (size_t)t.m;
+  }
 }
 
 // State shared by the passes of one call.
@@ -373,6 +382,7 @@ struct Batch {
   std::vector<double> hdres;
   double *pin = nullptr;       // pinned staging for results
   std::vector<ThetaDesc> last_td;   // host copy of the last uploaded descriptor array
+  char *design = nullptr;           // device: CSC and A^T A patterns of the general design matrices
   explicit Batch(Ctx &c) : ctx(c) {}
 };
 
@@ -491,7 +501,7 @@ static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) 
     tbytes += esz * 0.5 * t.n * (t.n + 1.0);
   }
   launch_assemble(b.ctx, d, B, max_over(b, ids, &ThetaDesc::Ncw), pass != PASS_PRIOR, pass == PASS_FINAL, BORDER_CB,
-                  abytes, prec);
+                  abytes, prec, max_over(b, ids, &ThetaDesc::m));
   int rc;
   if ((rc = run_factor(b, ids, F_BIG, MODE_LAPLACE, prec))) return rc;
   launch_kriging_build(b.ctx, d, B, max_over(b, ids, &ThetaDesc::k_pad), prec);
@@ -561,6 +571,8 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
   return b.ctx.check();
 }
 
+static int setup_design(Batch &b, const inla_model *models, int B);
+
 // Allocate and bind the workspace of a batch; zero the per-theta scratch.
 static int setup(Batch &b, int B, const inla_model *models, const double *theta, int ldtheta, Mode mode) {
   b.plans.resize(B);
@@ -589,12 +601,150 @@ static int setup(Batch &b, int B, const inla_model *models, const double *theta,
   }
   if (hipHostMalloc(&b.pin, sizeof(double) * DRES_COUNT * B + sizeof(int) * 4 * B + 64) != hipSuccess)
     return INLA_ERR_NOMEM;
-  return 0;
+  return setup_design(b, models, B);
 }
 
 static void teardown(Batch &b) {
   if (b.pin) (void)hipHostFree(b.pin);
   b.pin = nullptr;
+  if (b.design) {
+    (void)hipStreamSynchronize(b.ctx.stream);
+    (void)hipFree(b.design);
+    b.design = nullptr;
+  }
+}
+
+// Host-side structures of a general design matrix A (m x n, CSR): its CSC and
+// the lower pattern of A^T A, each entry (r, c) with the observations i that
+// contribute A_{i r} A_{i c} to (A^T W A)_{r c}.
+struct DesignHost {
+  std::vector<int> cscp, csci, patp, patr, patt, tobs;
+  std::vector<double> cscv, tcoef;
+};
+
+static int build_design(const inla_model &m, hipStream_t s, DesignHost &dh) {
+  const int M = m.m, n = m.n;
+  std::vector<int> rp(M + 1), ci;
+  std::vector<double> v;
+  if (hipMemcpyAsync(rp.data(), m.A_rowptr, sizeof(int) * (M + 1), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return INLA_ERR_HIP;
+  const int nnz = rp[M];
+  if (rp[0] != 0 || nnz != m.nnz) return -3;
+  for (int i = 0; i < M; ++i)
+    if (rp[i + 1] < rp[i]) return -3;
+  ci.resize(nnz);
+  v.resize(nnz);
+  if (nnz > 0 && (hipMemcpyAsync(ci.data(), m.A_col, sizeof(int) * nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipMemcpyAsync(v.data(), m.A_val, sizeof(double) * nnz, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                  hipStreamSynchronize(s) != hipSuccess))
+    return INLA_ERR_HIP;
+  for (int c : ci)
+    if (c < 0 || c >= n) return -3;
+  // CSC
+  dh.cscp.assign(n + 1, 0);
+  for (int c : ci) dh.cscp[c + 1]++;
+  for (int c = 0; c < n; ++c) dh.cscp[c + 1] += dh.cscp[c];
+  dh.csci.resize(nnz);
+  dh.cscv.resize(nnz);
+  std::vector<int> fill(dh.cscp.begin(), dh.cscp.end() - 1);
+  for (int i = 0; i < M; ++i)
+    for (int p = rp[i]; p < rp[i + 1]; ++p) {
+      const int q = fill[ci[p]]++;
+      dh.csci[q] = i;
+      dh.cscv[q] = v[p];
+    }
+  // lower pattern of A^T A: per column c, rows r >= c in increasing order
+  std::vector<std::map<int, std::vector<std::pair<int, double>>>> cols(n);
+  for (int i = 0; i < M; ++i)
+    for (int a = rp[i]; a < rp[i + 1]; ++a)
+      for (int b = rp[i]; b < rp[i + 1]; ++b) {
+        const int r = ci[a], c = ci[b];
+        if (r < c) continue;
+        if (r == c && a != b) continue;   // a repeated column index: its diagonal term comes from (a, a)
+        cols[c][r].push_back({i, v[a] * v[b]});
+      }
+  dh.patp.assign(n + 1, 0);
+  dh.patt.assign(1, 0);
+  for (int c = 0; c < n; ++c) {
+    for (auto &kv : cols[c]) {
+      dh.patr.push_back(kv.first);
+      for (auto &tr : kv.second) {
+        dh.tobs.push_back(tr.first);
+        dh.tcoef.push_back(tr.second);
+      }
+      dh.patt.push_back((int)dh.tobs.size());
+    }
+    dh.patp[c + 1] = (int)dh.patr.size();
+  }
+  return INLA_OK;
+}
+
+// Upload the design structures of every model with a general A (one copy per
+// distinct A) and bind them into the descriptors.
+static int setup_design(Batch &b, const inla_model *models, int B) {
+  std::map<const int32_t *, int> seen;
+  std::vector<DesignHost> hs;
+  std::vector<int> which(B, -1);
+  for (int i = 0; i < B; ++i) {
+    if (models[i].m == 0) continue;
+    auto it = seen.find(models[i].A_rowptr);
+    if (it == seen.end()) {
+      DesignHost dh;
+      const int rc = build_design(models[i], b.ctx.stream, dh);
+      if (rc) return rc;
+      it = seen.emplace(models[i].A_rowptr, (int)hs.size()).first;
+      hs.push_back(std::move(dh));
+    }
+    which[i] = it->second;
+  }
+  if (hs.empty()) return INLA_OK;
+  // one allocation: per design [cscp csci patp patr patt tobs | cscv tcoef]
+  std::vector<size_t> off(hs.size());
+  size_t total = 0;
+  auto a8 = [](size_t v) { return (v + 255) & ~size_t(255); };
+  for (size_t d = 0; d < hs.size(); ++d) {
+    const DesignHost &h = hs[d];
+    off[d] = total;
+    total += a8(4 * (h.cscp.size() + h.csci.size() + h.patp.size() + h.patr.size() + h.patt.size() + h.tobs.size())) +
+             a8(8 * (h.cscv.size() + h.tcoef.size())) + 256;
+  }
+  if (hipMalloc(&b.design, total) != hipSuccess) {
+    (void)hipGetLastError();
+    b.design = nullptr;
+    return INLA_ERR_NOMEM;
+  }
+  std::vector<char> host(total, 0);
+  struct Ptrs { const int *cscp, *csci, *patp, *patr, *patt, *tobs; const double *cscv, *tcoef; };
+  std::vector<Ptrs> ptrs(hs.size());
+  for (size_t d = 0; d < hs.size(); ++d) {
+    const DesignHost &h = hs[d];
+    size_t o = off[d];
+    auto put_i = [&](const std::vector<int> &vec) {
+      std::memcpy(host.data() + o, vec.data(), 4 * vec.size());
+      const int *p = (const int *)(b.design + o);
+      o += 4 * vec.size();
+      return p;
+    };
+    Ptrs &P = ptrs[d];
+    P.cscp = put_i(h.cscp); P.csci = put_i(h.csci); P.patp = put_i(h.patp);
+    P.patr = put_i(h.patr); P.patt = put_i(h.patt); P.tobs = put_i(h.tobs);
+    o = off[d] + a8(4 * (h.cscp.size() + h.csci.size() + h.patp.size() + h.patr.size() + h.patt.size() + h.tobs.size()));
+    std::memcpy(host.data() + o, h.cscv.data(), 8 * h.cscv.size());
+    P.cscv = (const double *)(b.design + o);
+    o += 8 * h.cscv.size();
+    std::memcpy(host.data() + o, h.tcoef.data(), 8 * h.tcoef.size());
+    P.tcoef = (const double *)(b.design + o);
+  }
+  if (hipMemcpy(b.design, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return INLA_ERR_HIP;
+  for (int i = 0; i < B; ++i) {
+    if (which[i] < 0) continue;
+    const Ptrs &P = ptrs[which[i]];
+    ThetaDesc &t = b.plans[i].t;
+    t.cscp = P.cscp; t.csci = P.csci; t.cscv = P.cscv;
+    t.patp = P.patp; t.patr = P.patr; t.patt = P.patt; t.tobs = P.tobs; t.tcoef = P.tcoef;
+  }
+  return INLA_OK;
 }
 
 // Memory budget for one chunk of thetas: 85% of the device's free memory.
@@ -855,7 +1005,8 @@ static int var_chunk(Ctx &ctx, int B, const inla_model *models, const double *th
   if ((rc = prior_build(b, all))) return fail(rc);
   ThetaDesc *d = upload_td(b, all);
   if (!d) return fail(INLA_ERR_NOMEM);
-  launch_assemble(ctx, d, B, max_over(b, all, &ThetaDesc::Ncw), 1, 0, BORDER_CI, 0.0, INLA_PREC_FP64);
+  launch_assemble(ctx, d, B, max_over(b, all, &ThetaDesc::Ncw), 1, 0, BORDER_CI, 0.0, INLA_PREC_FP64,
+                  max_over(b, all, &ThetaDesc::m));
   if ((rc = run_factor(b, all, F_BIG, MODE_VAR))) return fail(rc);
   launch_var_small_build(ctx, d, B, max_over(b, all, &ThetaDesc::k_pad));
   if ((rc = run_factor(b, all, F_SMALL, MODE_VAR))) return fail(rc);
@@ -1072,6 +1223,9 @@ static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, con
   if (!x) return -6;
   for (int i = 0; i < B; ++i) if (!x[i]) return -6;
   if (opts && (opts->prec < 0 || opts->prec >= INLA_PREC_COUNT)) return INLA_ERR_UNSUPPORTED;
+  if (opts && opts->prec != INLA_PREC_FP64)
+    for (int i = 0; i < B; ++i)
+      if (models[i].m > 0) return INLA_ERR_UNSUPPORTED;   // general design matrices are evaluated in FP64
   for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
     rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
                     x + c.first, opts, res + c.first, laplace);
@@ -1218,6 +1372,8 @@ int inla_vb_mean(inla_handle *h, int32_t B, const inla_model *models, const doub
   if (n_gh <= 0) n_gh = 20;
   if (n_gh > 64) return -8;
   if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
+  for (int i = 0; i < B; ++i)
+    if (models[i].m > 0) return INLA_ERR_UNSUPPORTED;   // written for A = I
   if (!iters) return -10;
   if (!info) return -11;
   Ctx &ctx = h->ctx;

@@ -128,6 +128,22 @@ __device__ __forceinline__ void lik_point(const ThetaDesc &t, int i, double x, d
   W = ew;
 }
 
+// Per observation of a model with a general design matrix: (A x)_i by the CSR
+// row, then the likelihood terms at eta_i = offset + (A x)_i.
+__global__ __launch_bounds__(256) void obs_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (t.m == 0 || i >= t.m) return;
+  double ax = 0.0;
+  for (int p = t.A_rowptr[i]; p < t.A_rowptr[i + 1]; ++p) ax += t.A_val[p] * t.x[t.A_col[p]];
+  double g, W, ll;
+  lik_point_at(t, i, ax, g, W, ll);
+  t.obs_ax[i] = ax;
+  t.obs_g[i] = g;
+  t.obs_W[i] = W;
+  t.obs_ll[i] = ll;
+}
+
 // The bordered posterior precision of one Newton step (algorithm "Gaussian
 // Approximation": Q* = Q_prior + Q_l(x0), b = grad + Q_l x0; A = I so Q_l is the
 // diagonal W), written in the factorisation's storage type T:
@@ -152,12 +168,22 @@ __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restri
     for (int r = c + threadIdx.x; r < N; r += 256) col[r] = (T)0;
     return;
   }
-  double g = 0.0, W = 0.0, ll = 0.0, xc = 0.0;
+  double g = 0.0, W = 0.0, ll = 0.0, xc = 0.0, bc = 0.0;
   if (c < n) {
     xc = t.x[c];
-    if (with_lik) lik_point(t, c, xc, g, W, ll);
+    if (with_lik && t.m == 0) lik_point(t, c, xc, g, W, ll);
   }
-  const double bc = with_lik ? g + W * xc : 0.0;
+  if (with_lik && t.m == 0) {
+    bc = g + W * xc;
+  } else if (with_lik && c < n) {
+    // b_c = (A^T (g + W A x))_c over the CSC column, fixed-order block sum
+    double s = 0.0;
+    for (int p = t.cscp[c] + threadIdx.x; p < t.cscp[c + 1]; p += 256) {
+      const int i = t.csci[p];
+      s += t.cscv[p] * (t.obs_g[i] + t.obs_W[i] * t.obs_ax[i]);
+    }
+    bc = block_sum256(s, sh);
+  }
   const double *q = t.Qp + (size_t)c * t.ldqp;
   const int kc_pad = round_up_dev(k, PADN);
   double xq = 0.0;
@@ -178,6 +204,20 @@ __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restri
   if (want_xqx) {
     xq = block_sum256(xq, sh);
     if (threadIdx.x == 0) t.part[t.ldw + c] = xq * xc;
+  }
+  if (with_lik && t.m > 0 && c < n) {
+    // + (A^T W A)_{r c} for the lower pattern entries of column c (distinct rows)
+    __syncthreads();
+    double bad = 0.0;
+    for (int e = t.patp[c] + threadIdx.x; e < t.patp[c + 1]; e += 256) {
+      double v = 0.0;
+      for (int q = t.patt[e]; q < t.patt[e + 1]; ++q) v += t.tcoef[q] * t.obs_W[t.tobs[q]];
+      if (!isfinite(v)) bad = 1.0;
+      const int r = t.patr[e];
+      col[r] = (T)((double)col[r] + v);
+    }
+    bad = block_sum256(bad, sh);
+    if (threadIdx.x == 0 && bad > 0.0) t.dres[DRES_NONFINITE] = 1.0;
   }
   if (threadIdx.x == 0) {
     t.part[c] = ll;
@@ -309,8 +349,12 @@ void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, do
   });
 }
 void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
-                     double bytes, int prec) {
+                     double bytes, int prec, int m_max) {
   if (B <= 0 || N_max <= 0) return;
+  if (with_lik && m_max > 0)
+    ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(obs_kernel, dim3((m_max + 255) / 256, B), dim3(256), 0, ctx.stream, dtd);
+    });
   ctx.launch(INLA_K_ASSEMBLE, 0.0, bytes, [&] {
     if (prec != INLA_PREC_FP64)
       hipLaunchKernelGGL(assemble_kernel<float>, dim3(N_max, B), dim3(256), 0, ctx.stream, dtd, with_lik, want_xqx,

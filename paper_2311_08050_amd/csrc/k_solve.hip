@@ -386,6 +386,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const ThetaDesc *__restrict
     ll += t.part[i];
     xq += t.part[t.ldw + i];
   }
+  for (int i = threadIdx.x; i < t.m; i += 256) ll += t.obs_ll[i];   // general design matrix
   ld = block_sum256(ld, sh);
   ll = block_sum256(ll, sh);
   xq = block_sum256(xq, sh);

@@ -13,8 +13,10 @@ __device__ __forceinline__ int round_up_dev(int v, int m) { return (v + m - 1) /
 // assembly (k_model.hip)
 void launch_expcov_bordered(Ctx &ctx, const ThetaDesc *dtd, int B, int Np_max);
 void launch_prior_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes);
+// with_lik and m_max > 0: the per-observation terms of general design
+// matrices are computed first
 void launch_assemble(Ctx &ctx, const ThetaDesc *dtd, int B, int N_max, int with_lik, int want_xqx, int border,
-                     double bytes, int prec);
+                     double bytes, int prec, int m_max = 0);
 void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int prec);
 void launch_objective_terms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes);
 void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes);

@@ -132,6 +132,39 @@ def dense_poisson(n, k, seed):
     }
 
 
+def crossed_effects(n_a, n_b, n_obs, seed, lik="gaussian", sigma2=1.0, sum_to_zero=False):
+    """Crossed random effects (the LGM example of the paper's Introduction):
+    eta_k = alpha_{i_k} + gamma_{j_k} with i_k, j_k drawn with replacement from
+    n_a and n_b levels, alpha, gamma ~ N(0, 1) (dense prior precision I), A the
+    n_obs x (n_a + n_b) design matrix with two ones per row.  Gaussian:
+    y = eta + eps, eps ~ N(0, sigma2); Poisson: y ~ Poisson(E e^{beta0 + eta})
+    with beta0 = 0 and E ~ U(5, 50).  With sum_to_zero the gamma levels sum to 0."""
+    rng = np.random.default_rng(seed)
+    n = n_a + n_b
+    i = rng.integers(0, n_a, size=n_obs)
+    j = rng.integers(0, n_b, size=n_obs)
+    A = np.zeros((n_obs, n))
+    A[np.arange(n_obs), i] = 1.0
+    A[np.arange(n_obs), n_a + j] = 1.0
+    x = rng.normal(0.0, 1.0 if lik == "gaussian" else 0.3, size=n)
+    C = e = None
+    if sum_to_zero:
+        C = np.zeros((1, n))
+        C[0, n_a:] = 1.0
+        e = np.zeros(1)
+        x[n_a:] -= x[n_a:].mean()
+    E = None
+    if lik == "gaussian":
+        y = A @ x + rng.normal(0.0, math.sqrt(sigma2), size=n_obs)
+    else:
+        E = rng.uniform(5.0, 50.0, size=n_obs)
+        y = rng.poisson(E * np.exp(A @ x)).astype(np.float64)
+    return {
+        "n": n, "lik": lik, "prior": "dense", "y": y, "E": E, "A": A,
+        "C": C, "e": e, "coords": None, "n_s": n, "n_t": 1, "Qprior": np.eye(n), "x_true": x,
+    }
+
+
 def fd_batch(theta0, h, dims):
     """theta0 followed by theta0 +/- h e_j for each j in ``dims`` (the points of a
     central finite-difference gradient)."""

@@ -41,12 +41,30 @@ def test_binding_export_list_matches_header():
     assert sorted(binding.EXPORTS) == declared_functions()
 
 
-def test_struct_layouts():
+def test_struct_layouts(tmp_path):
+    """Every struct the binding passes has the size and field offsets the C
+    compiler gives the header's declaration."""
+    import subprocess
+
     from paper_2311_08050_amd import binding
-    assert ctypes.sizeof(binding.Model) == 8 * 4 + 6 * 8
-    assert ctypes.sizeof(binding.Opts) == 24
-    assert ctypes.sizeof(binding.Result) == 9 * 8 + 4 * 4
-    assert ctypes.sizeof(binding.KStats) == 32
+    pairs = [("inla_model", binding.Model), ("inla_opts", binding.Opts), ("inla_result", binding.Result),
+             ("inla_kstats", binding.KStats), ("inla_theta_opts", binding.ThetaOpts)]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    want = []
+    for _, cls in pairs:
+        want.append(ctypes.sizeof(cls))
+        want += [getattr(cls, fname).offset for fname, _ in cls._fields_]
+    assert got == want
 
 
 def test_version_string(libpath):

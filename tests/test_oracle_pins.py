@@ -241,3 +241,27 @@ def test_theta_layout_padded_rows():
     g = synth.expcov_gaussian(10, seed=3)
     th = np.array([0.2, math.log(0.3), math.log(0.4)])
     assert O.laplace_eval(g, th)["objective"] == O.laplace_eval(g, np.append(th, 7.0))["objective"]
+
+
+@pytest.mark.parametrize("sum_to_zero", [False, True])
+def test_crossed_effects_gaussian_closed_form(sum_to_zero):
+    """The Introduction's crossed random effects with a Gaussian likelihood:
+    the mode is the posterior mean (A^T A / s2 + Q_prior)^{-1} A^T y / s2 (kriged
+    onto C x = 0) and the objective equals the marginal likelihood
+    log N(y; 0, A Sigma_c A^T + s2 I), Sigma_c the (constrained) prior covariance."""
+    m = synth.crossed_effects(7, 5, 30, seed=12, sum_to_zero=sum_to_zero)
+    s2 = 0.7
+    th = np.array([math.log(s2)])
+    r = O.laplace_eval(m, th)
+    A, y = m["A"], m["y"]
+    Sigma = np.linalg.inv(m["Qprior"])
+    if sum_to_zero:
+        C = m["C"]
+        Sigma = Sigma - Sigma @ C.T @ np.linalg.solve(C @ Sigma @ C.T, C @ Sigma)
+    K = A @ Sigma @ A.T + s2 * np.eye(len(y))
+    mean = Sigma @ A.T @ np.linalg.solve(K, y)
+    sign, ld = np.linalg.slogdet(K)
+    ml = -0.5 * (len(y) * math.log(2 * math.pi) + ld + y @ np.linalg.solve(K, y))
+    assert r["info"] == 0
+    assert np.max(np.abs(r["x"] - mean)) <= 1e-12 * max(1.0, np.max(np.abs(mean)))
+    assert abs(r["objective"] - ml) <= 1e-10 * abs(ml)
