@@ -36,8 +36,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "θ-evals/sec + TFLOP/s vs MFMA peak at n=8192, FP64 vs mixed+warm-start"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks
-TRAIL_KERNEL = {"fp64": "gemm_update_kernel<double,128,128,0>", "fp32": "gemm_update_kernel<float,128,128,0>",
-                "bf16": "trail_bf16_kernel<128,128>"}
+TYPE_NAME = {"fp64": "double", "fp32": "float"}
+
+
+def trail_kernel_name(precision, tile):
+    """Symbol of the trailing-update kernel of a precision at the tuned tile."""
+    if precision == "bf16":
+        return "trail_bf16_kernel<128,128>"
+    return f"trail_update_kernel<{TYPE_NAME[precision]},{tile},{tile}>"
 MLP_TRAIN = {"n_train": 2048, "epochs": 400, "hidden": 256, "lr": 2e-3, "lr_final": 0.01, "seed": 91}
 
 
@@ -112,6 +118,9 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
 
     prec = variant.split("+")[0]
 
+    def tname(p):   # the trailing kernel at the tile the handle uses for this batch
+        return trail_kernel_name(p, lib.tune_get(p, dms[0].n, len(dms))[1])
+
     def step():
         if warm is None:
             return lib.laplace_eval(dms, thetas, x=xs, prec=prec)
@@ -156,7 +165,7 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
         "zero_start_fallbacks": int(sum((r["fallback"] >> 1) & 1 for r in res)),
         "roofline": {
             "bound": "mfma",
-            "kernel": f"{TRAIL_KERNEL[key]} ({key.upper()} MFMA trailing update of the blocked Cholesky)",
+            "kernel": f"{tname(key)} ({key.upper()} MFMA trailing update of the blocked Cholesky)",
             "achieved": achieved,
             "peak": peak,
             "unit": "TFLOP/s",
@@ -169,7 +178,7 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
             "alg_bytes_per_launch": trail["bytes"] / max(1, trail["launches"]),
         },
         "trail_kernels": {
-            p: {"kernel": TRAIL_KERNEL[p], "launches": sb["trail"]["launches"],
+            p: {"kernel": tname(p), "launches": sb["trail"]["launches"],
                 "avg_launch_ms": sb["trail"]["time_ms"] / sb["trail"]["launches"],
                 "achieved_tflops": sb["trail"]["flops"] / (sb["trail"]["time_ms"] * 1e-3) / 1e12,
                 "frac_of_peak": sb["trail"]["flops"] / (sb["trail"]["time_ms"] * 1e-3) / 1e12 / PEAK_TFLOPS[p]}
@@ -325,7 +334,7 @@ def main():
         pv = results[v]["roofline"]["precision"]
         results[v]["roofline"]["traffic"] = traffic_from_profile(
             os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"),
-            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64_traffic.md"))
+            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64.md"))
     out = {
         "metric": METRIC,
         "value": hv["value"],

@@ -282,10 +282,12 @@ __device__ __forceinline__ void subtract_tile(__attribute__((address_space(1))) 
 // bank conflicts.
 // --------------------------------------------------------------------------
 // SEL (row selection of update_tile) is a template parameter so that the
-// border-row launch beside a BF16 trailing update is a kernel of its own.
+// border-row launch beside a BF16 trailing update is a kernel of its own; the
+// trailing update of every row is trail_update_kernel (below), so that each
+// launch class has its own kernel symbol.
 template <typename T, int TM, int TN, int SEL>
-__global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
-                                                             int p0, int nb, int j) {
+__device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ descs, int kind, int p0, int nb,
+                                                 int j) {
   constexpr bool F64 = sizeof(T) == 8;
   // K chunk staged per LDS buffer: 16 deep in both precisions, which keeps a
   // 128 x 128 FP32 tile's buffers at 34 KB (up to four workgroups per CU)
@@ -397,6 +399,21 @@ __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *_
   } else {
     subtract_tile<T, BM, BN>(Cg, ld, acc, rl, cl, diag_tile, row0, col0);
   }
+}
+
+// Panel TRSM and in-panel updates (SEL 0), border rows beside a BF16 trailing
+// update (SEL 2).
+template <typename T, int TM, int TN, int SEL>
+__global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
+                                                             int p0, int nb, int j) {
+  gemm_update_body<T, TM, TN, SEL>(descs, kind, p0, nb, j);
+}
+
+// The trailing update of the blocked Cholesky (kinds TRAIL, TRAIL_A, TRAIL_B).
+template <typename T, int TM, int TN>
+__global__ __launch_bounds__(256, 2) void trail_update_kernel(const FactorDesc *__restrict__ descs, int kind, int p0,
+                                                              int nb) {
+  gemm_update_body<T, TM, TN, 0>(descs, kind, p0, nb, p0);
 }
 
 // --------------------------------------------------------------------------
@@ -748,13 +765,13 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
       });
     } else if (TT == 64) {
       ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-        hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
-                           nb, p0);
+        hipLaunchKernelGGL((trail_update_kernel<T, 64, 64>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
+                           nb);
       });
     } else {
       ctx.launch(INLA_K_TRAIL, fl, by, [&] {
-        hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind,
-                           p0, nb, p0);
+        hipLaunchKernelGGL((trail_update_kernel<T, 128, 128>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind, p0,
+                           nb);
       });
     }
   };
@@ -825,6 +842,7 @@ int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int prec, const Tu
 }
 
 constexpr double LOOKAHEAD_MARGIN = 0.05;
+constexpr double DEFAULT_MARGIN = 0.03;
 
 // Candidate (panel width, trailing tile) pairs without lookahead; the BF16 path
 // has one tile size.  The fastest is then timed once more with lookahead.
@@ -890,11 +908,17 @@ int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, T
     return tot / std::max(1, reps);
   };
   const size_t nbase = cand.size();
+  int dflt = -1;
+  double dflt_ms = 0;
   for (size_t c = 0; c < nbase && !rc; ++c) {
     const double avg = time_cfg(cand[c]);
     if (ms_out) ms_out[c] = avg;
     if (!rc && (best < 0 || avg < best_ms)) { best = (int)c; best_ms = avg; }
+    if (cand[c].nb == TuneCfg{}.nb && cand[c].tm == TuneCfg{}.tm) { dflt = (int)c; dflt_ms = avg; }
   }
+  // the default configuration stays unless another is clearly faster, so that
+  // timing noise between near-equal candidates does not change the choice
+  if (!rc && dflt >= 0 && best_ms > (1.0 - DEFAULT_MARGIN) * dflt_ms) { best = dflt; best_ms = dflt_ms; }
   if (!rc && ctx.lookahead) {
     TuneCfg la = cand[best];
     la.look = 1;
