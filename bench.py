@@ -51,11 +51,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel_source, summary_md):
+def traffic_from_profile(kernel_source, summary_md, kernel_instance):
     """HBM bytes per launch of the trailing-update kernel from the committed
-    counter summary (its `kernel_source_sha256:` and `traffic_bytes_per_launch:`
-    lines), or None if the summary is missing or was taken on a different
-    kernel source."""
+    counter summary (its `kernel_instance:`, `kernel_source_sha256:` and
+    `traffic_bytes_per_launch:` lines), or None if the summary is missing, was
+    taken on a different kernel source or on another instance (tile size) than
+    the one this run timed."""
     import hashlib
     try:
         with open(summary_md) as f:
@@ -70,7 +71,7 @@ def traffic_from_profile(kernel_source, summary_md):
         if ":" in ln:
             key, val = ln.split(":", 1)
             fields[key.strip()] = val.strip()
-    if fields.get("kernel_source_sha256") != digest:
+    if fields.get("kernel_source_sha256") != digest or fields.get("kernel_instance") != kernel_instance:
         return None
     try:
         return float(fields["traffic_bytes_per_launch"])
@@ -334,7 +335,8 @@ def main():
         pv = results[v]["roofline"]["precision"]
         results[v]["roofline"]["traffic"] = traffic_from_profile(
             os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"),
-            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64.md"))
+            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64.md"),
+            results[v]["roofline"]["kernel"].split(" ")[0])
     out = {
         "metric": METRIC,
         "value": hv["value"],
