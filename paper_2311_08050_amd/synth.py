@@ -165,6 +165,49 @@ def crossed_effects(n_a, n_b, n_obs, seed, lik="gaussian", sigma2=1.0, sum_to_ze
     }
 
 
+def region_graph(coords):
+    """Neighbouring-region pairs of points: the edges of their Delaunay
+    triangulation (a connected planar graph, like the adjacency of a map)."""
+    from scipy.spatial import Delaunay
+    tri = Delaunay(np.asarray(coords, dtype=np.float64))
+    e = set()
+    for a, b, c in tri.simplices:
+        for i, j in ((a, b), (b, c), (a, c)):
+            e.add((min(int(i), int(j)), max(int(i), int(j))))
+    return np.array(sorted(e), dtype=np.int64)
+
+
+def rw1_besag(n_s, n_t, seed, lik="poisson", beta0=0.0, sigma2=0.25):
+    """Space x time interaction with an intrinsic prior (Type IV: first-order
+    random walk in time kron a Besag model on a random region graph), latent
+    index t*n_s + s, no explicit constraints (the prior's null space identifies
+    the field).  Poisson: E ~ U(5, 50), y ~ Poisson(E exp(beta0 + x_true));
+    Gaussian: y = x_true + eps, eps ~ N(0, sigma2).  x_true is a smooth field
+    with region and time means removed."""
+    rng = np.random.default_rng(seed)
+    coords = points(rng, n_s)
+    edges = region_graph(coords)
+    x = double_centre(smooth_field(rng, coords, n_t)).reshape(-1)
+    n = n_s * n_t
+    E = None
+    if lik == "poisson":
+        E = rng.uniform(5.0, 50.0, size=n)
+        y = rng.poisson(E * np.exp(beta0 + x)).astype(np.float64)
+    else:
+        y = x + rng.normal(0.0, math.sqrt(sigma2), size=n)
+    return {
+        "n": n, "lik": lik, "prior": "rw1_besag", "y": y, "E": E, "A": None, "C": None, "e": None,
+        "coords": coords, "edges": edges, "n_s": n_s, "n_t": n_t, "x_true": x,
+    }
+
+
+def rw1_besag_theta0(n_t, lik="poisson"):
+    """(log tau0, lik0): tau0 = (n_t^2 - 1) / (6 n_t 0.25) as for the Kronecker
+    prior; lik0 = beta0 = 0 (Poisson) or log 0.25 (Gaussian)."""
+    tau0 = (n_t * n_t - 1.0) / (6.0 * n_t * 0.25)
+    return np.array([math.log(tau0), 0.0 if lik == "poisson" else math.log(0.25)])
+
+
 def fd_batch(theta0, h, dims):
     """theta0 followed by theta0 +/- h e_j for each j in ``dims`` (the points of a
     central finite-difference gradient)."""
