@@ -60,15 +60,20 @@ extern "C" {
 #define INLA_INFO_NEWTON_MAXIT (-1)     /* no convergence within max_iter; last iterate returned */
 #define INLA_INFO_CONSTRAINT_RANK (-2)  /* C Q^{-1} C^T not positive definite: C lacks full row rank */
 #define INLA_INFO_NONFINITE (-3)        /* NaN/Inf in theta, a start vector or an iterate */
+#define INLA_INFO_EIG_MAXIT (-4)        /* inla_pinv: Jacobi sweeps did not converge; result from the
+                                           last sweep */
 
 /* ----------------------------------------------------------------- enums */
 enum { INLA_LIK_GAUSSIAN = 0, INLA_LIK_POISSON = 1 };
 enum {
   INLA_PRIOR_DENSE = 0,           /* Q_prior supplied by the caller (model.Qprior)       */
   INLA_PRIOR_EXPCOV = 1,          /* Q_prior = tau Sigma(rho)^{-1}, Sigma_ij = exp(-d_ij/rho) */
-  INLA_PRIOR_KRON_RW1_EXPCOV = 2  /* Q_prior = tau (R_t kron Sigma_s(rho)^{-1} + delta I),
+  INLA_PRIOR_KRON_RW1_EXPCOV = 2, /* Q_prior = tau (R_t kron Sigma_s(rho)^{-1} + delta I),
                                      R_t the unscaled first-order random walk on n_t
                                      steps, latent index t*n_s + s */
+  INLA_PRIOR_PINV = 3             /* inla_woodbury_eval only: model.Qprior holds the
+                                     Moore-Penrose inverse Q_prior^+ (full symmetric
+                                     storage, model.ldq) of an intrinsic prior */
 };
 /* Precision of the Newton and final-pass factorisations (extension to the
  * paper's FP64 method).
@@ -346,6 +351,58 @@ int inla_ccd_points(int32_t t, const double *theta_star, const double *neg_hess,
  * delta_k exp(log_post_k), normalised to sum 1 (host arrays of n_points; a
  * non-finite log_post_k gets weight 0). */
 int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_post, double *weights);
+
+/* ------------------------------------- Moore-Penrose route (intrinsic priors) */
+/* Section "Bypassing constraints complexity in disease mapping models using
+ * dense matrices": a rank-deficient (intrinsic) prior precision is handled
+ * through its Moore-Penrose inverse, whose null space identifies the field in
+ * place of explicit constraints, and the posterior covariance follows the
+ * Woodbury form of Eq. (woodeqn).
+ *
+ * inla_pinv: Q^+ of B symmetric matrices by a cyclic two-sided Jacobi
+ * eigen-decomposition Q = V diag(lambda) V^T (round-robin rotation order, sweeps
+ * until the off-diagonal Frobenius norm is at most 4 eps ||A||_F, or below
+ * 1e-14 ||A||_F and shrinking by less than 10% per sweep; at most 40 sweeps),
+ * Q^+ = V diag(f) V^T with f_k = 1 / lambda_k where |lambda_k| > rtol *
+ * max|lambda| and 0 otherwise.
+ *   n        host [B] orders, 1 <= n[b] <= 4096
+ *   Q        host array of B device pointers: column-major, lower triangle read
+ *   ldq      host [B] leading dimensions (>= n[b])
+ *   Qpinv    host array of B device pointers: output, full symmetric n x n
+ *            (both triangles written), column-major, leading dimension ldp[b]
+ *   rtol     relative rank threshold; <= 0: 1e-9
+ *   rank     host [B] output: number of eigenvalues kept
+ *   sweeps   host [B] output: Jacobi sweeps taken
+ *   info     host [B] output: 0, INLA_INFO_EIG_MAXIT or INLA_INFO_NONFINITE
+ * Uses the handle's workspace (2 n^2 + O(n) doubles per matrix) and
+ * synchronises the handle's stream once per sweep.  Returns -i for an invalid
+ * i-th argument (a bad n[b] as -3), INLA_ERR_NOMEM or INLA_ERR_HIP. */
+int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *Q, const int32_t *ldq,
+              double *const *Qpinv, const int32_t *ldp, double rtol, int32_t *rank, int32_t *sweeps, int32_t *info);
+
+/* inla_woodbury_eval: log pi~(y | theta) with an intrinsic prior, A = I.  Each
+ * model has prior INLA_PRIOR_PINV, k = 0 and m = 0; model.Qprior is the device
+ * pseudo-inverse Q_prior(theta_b)^+ (full symmetric, ld model.ldq; the caller
+ * scales it with theta), and theta row b holds the likelihood parameter only:
+ * (lik), lik = log sigma^2 (Gaussian) or beta0 (Poisson).  Newton in covariance
+ * form: b = g + W x, x_new = Sigma* b with Sigma* = Q^+ - Q^+ S M^{-1} S Q^+,
+ * S = diag(sqrt(W)), M = I + S Q^+ S factored by the blocked Cholesky (FP64);
+ * the stopping rule is that of inla_laplace_eval (Gaussian: one step).  The
+ * objective is the Laplace approximation on range(Q_prior):
+ *   objective = loglik - 1/2 x*^T Q_prior x* - 1/2 log|M|,
+ * which equals 1/2 log pdet(Q_prior) + 1/2 log pdet(Sigma*) - 1/2 x*^T Q_prior x*
+ * + loglik (pdet: product of the non-zero eigenvalues), and the kriging
+ * objective with constraints spanning null(Q_prior).  M comes from the last
+ * Newton step.
+ *   x     host array of B device pointers [n]: start (opts->start = 1) and the mode
+ *   opts  as for inla_laplace_eval; prec must be INLA_PREC_FP64
+ *   res   host [B]: objective, xqx = x*^T Q_prior x*, loglik, logdet_qstar =
+ *         log|M| (= log pdet(Q*) - log pdet(Q_prior) on range(Q_prior)), step,
+ *         iters, info; the prior and constraint log-det fields are 0.
+ * Returns -i for an invalid i-th argument (a model that is not of this form as
+ * -3), INLA_ERR_UNSUPPORTED for another precision, INLA_ERR_NOMEM, INLA_ERR_HIP. */
+int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                       double *const *x, const inla_opts *opts, inla_result *res);
 
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libinla_dense.so")
 
 LIK = {"gaussian": 0, "poisson": 1}
-PRIOR = {"dense": 0, "expcov": 1, "kron": 2}
+PRIOR = {"dense": 0, "expcov": 1, "kron": 2, "pinv": 3, "rw1_besag": 3, "intrinsic": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 N_PRIOR_PARAMS = {"dense": 0, "expcov": 2, "kron": 3}
 
@@ -23,6 +23,7 @@ INFO_OK = 0
 INFO_NEWTON_MAXIT = -1
 INFO_CONSTRAINT_RANK = -2
 INFO_NONFINITE = -3
+INFO_EIG_MAXIT = -4
 
 K_TRAIL, K_PANEL, K_POTF2, K_ASSEMBLE, K_SOLVE, K_BORDER = 0, 1, 2, 3, 4, 5
 K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "assemble", K_SOLVE: "solve",
@@ -36,6 +37,7 @@ EXPORTS = [
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
     "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats",
     "inla_vb_mean", "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
+    "inla_pinv", "inla_woodbury_eval",
 ]
 # Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
 # reports their times; the fastest is then timed with lookahead as well.
@@ -95,8 +97,9 @@ def load_library(path: str = LIBPATH):
     lib.inla_destroy.argtypes = [P]
     lib.inla_set_stream.argtypes = [P, P]
     lib.inla_logdet.argtypes = [P, i32, pi32, C.POINTER(P), pi32, i32, pd, pi32]
-    for f in (lib.inla_constrained_mode, lib.inla_laplace_eval):
+    for f in (lib.inla_constrained_mode, lib.inla_laplace_eval, lib.inla_woodbury_eval):
         f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
+    lib.inla_pinv.argtypes = [P, i32, pi32, C.POINTER(P), pi32, C.POINTER(P), pi32, C.c_double, pi32, pi32, pi32]
     lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
     lib.inla_profile.argtypes = [P, i32]
     lib.inla_profile_get.argtypes = [P, i32, i32, C.POINTER(KStats)]
@@ -255,6 +258,44 @@ class Library:
 
     def constrained_mode(self, dmodels, theta, x=None, start=0, max_iter=0, tol=0.0, prec="fp64"):
         return self._run(self.lib.inla_constrained_mode, dmodels, theta, x, start, max_iter, tol, prec)
+
+    def pinv(self, mats, rtol=0.0):
+        """Moore-Penrose inverses of symmetric float64 device tensors (inla_pinv;
+        C order equals column-major for symmetric input).  Returns (list of
+        device tensors Q^+, ranks, Jacobi sweeps, info codes)."""
+        B = len(mats)
+        n = (C.c_int32 * B)(*[int(m.shape[0]) for m in mats])
+        ld = (C.c_int32 * B)(*[int(m.shape[0]) for m in mats])
+        out = [self.torch.empty_like(m) for m in mats]
+        qp = (C.c_void_p * B)(*[m.data_ptr() for m in mats])
+        pp = (C.c_void_p * B)(*[o.data_ptr() for o in out])
+        rank, sweeps, info = (C.c_int32 * B)(), (C.c_int32 * B)(), (C.c_int32 * B)()
+        rc = self.lib.inla_pinv(self.h, B, n, qp, ld, pp, ld, float(rtol), rank, sweeps, info)
+        self._check(rc, "inla_pinv")
+        return out, np.array(rank[:]), np.array(sweeps[:]), np.array(info[:], dtype=np.int32)
+
+    def woodbury_eval(self, dmodels, lik_params, qpinv, x=None, start=0, max_iter=0, tol=0.0):
+        """Laplace evaluation through the pseudo-inverse route (inla_woodbury_eval):
+        dmodels are DeviceModels of intrinsic-prior models, lik_params the per-theta
+        likelihood parameter (log sigma^2 or beta0), qpinv the device tensors
+        Q_prior(theta_b)^+.  Returns (results, modes)."""
+        B = len(dmodels)
+        th = np.ascontiguousarray(np.asarray(lik_params, dtype=np.float64).reshape(B, 1))
+        structs = []
+        for dm, P in zip(dmodels, qpinv):
+            s = Model.from_buffer_copy(dm.struct)
+            s.prior, s.k, s.C, s.e, s.Qprior, s.ldq = 3, 0, None, None, P.data_ptr(), int(P.shape[0])
+            structs.append(s)
+        models = (Model * B)(*structs)
+        if x is None:
+            x = [self.torch.zeros(m.n, dtype=self.torch.float64, device="cuda") for m in dmodels]
+        ptrs = (C.c_void_p * B)(*[t.data_ptr() for t in x])
+        opts = Opts(prec=0, max_iter=max_iter, tol=tol, start=start, reserved=0)
+        res = (Result * B)()
+        rc = self.lib.inla_woodbury_eval(self.h, B, models, th.ctypes.data_as(C.POINTER(C.c_double)), 1, ptrs,
+                                         C.byref(opts), res)
+        self._check(rc, "inla_woodbury_eval")
+        return [r.asdict() for r in res], x
 
     def marginal_var(self, dmodels, theta, x_modes):
         B, theta, models, x_modes, xptrs = self._common(dmodels, theta, x_modes)

@@ -1088,6 +1088,7 @@ struct inla_handle {
 
 namespace inla {
 hipStream_t handle_stream(inla_handle *h) { return h->ctx.stream; }
+Ctx *handle_ctx(inla_handle *h) { return &h->ctx; }
 }  // namespace inla
 
 extern "C" {

@@ -1,0 +1,738 @@
+// The Moore-Penrose route for intrinsic (rank-deficient) priors, section
+// "Bypassing constraints complexity in disease mapping models using dense
+// matrices": the pseudo-inverse Q^+ of the prior precision by a cyclic two-sided
+// Jacobi eigen-decomposition (one per evaluation where the prior changes), and
+// the Laplace evaluation with the posterior covariance in the Woodbury form of
+// Eq. (woodeqn), A = I.
+//
+// Jacobi: the pairs of a round follow the round-robin (circle) schedule, so the
+// n/2 rotations of a round are disjoint and one launch applies all of them: the
+// workgroup of pair (p, q) owns columns p and q of A and of V, mixes the two
+// columns with its own rotation and then every row pair with that pair's
+// rotation.  The rotation angles of the next round are read from a small side
+// array that each owner fills with its new diagonal entry and the entry its
+// column holds in the row of its next partner, so every workgroup computes
+// bit-identical angles without reading columns another workgroup is writing.
+//
+// Woodbury Newton: with W the likelihood curvature (Q_l = diag(W)) and
+// S = diag(sqrt(W)), the symmetric form of Eq. (woodeqn) is
+//     Sigma* = Q^+ - Q^+ S M^{-1} S Q^+,   M = I + S Q^+ S  (eigenvalues >= 1),
+// so each step factors M with the blocked Cholesky instead of solving the
+// non-symmetric system I + Q_l Q^+.  The new iterate is
+//     x_new = Sigma* b = Q^+ (b - S M^{-1} S Q^+ b),   b = g + W x,
+// the forward substitution L^{-1} r (r = S Q^+ b) comes out of the
+// factorisation as its border row, and x_new^T Q_prior x_new = z^T x_new with
+// z = b - S M^{-1} r, because Q^+ Q_prior Q^+ = Q^+.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "device.hpp"
+#include "host.hpp"
+#include "model.hpp"
+
+struct inla_handle;
+
+namespace inla {
+
+Ctx *handle_ctx(inla_handle *h);
+
+// ------------------------------------------------------------------ Jacobi
+constexpr int JAC_MAX_N = 4096;      // two columns of the working matrix fit the 64 KiB of LDS
+constexpr int JAC_MAX_SWEEPS = 40;
+constexpr double JAC_RTOL_DEFAULT = 1e-9;
+
+struct JacDesc {
+  const double *Q;   // input, lower triangle read (ld ldq)
+  double *A, *V;     // ne x ne working matrix and eigenvectors (ld ne)
+  double *side;      // 2 slots x 2 x ne: [slot][0][k] = a_kk, [slot][1][k] = a_{partner(k), k}
+  double *f;         // [ne] 1/lambda_k or 0
+  double *norms;     // [4] off-diagonal sum of squares, sum of squares, max|lambda|, rank
+  double *P;         // output Q^+ (ld ldp), full symmetric
+  int n, ne, ldq, ldp;
+};
+
+// Round-robin schedule of ne (even) players, round r in [0, ne - 2]: slot 0
+// holds player 0, the other players rotate through slots 1 .. ne - 1; slots s
+// and ne - 1 - s play each other.
+__host__ __device__ __forceinline__ int rr_pos(int slot, int r, int ne) {
+  return slot == 0 ? 0 : 1 + (slot - 1 + r) % (ne - 1);
+}
+__host__ __device__ __forceinline__ int rr_slot(int k, int r, int ne) {
+  return k == 0 ? 0 : 1 + (k - 1 - r + (ne - 1)) % (ne - 1);
+}
+__host__ __device__ __forceinline__ int rr_partner(int k, int r, int ne) {
+  return rr_pos(ne - 1 - rr_slot(k, r, ne), r, ne);
+}
+
+// The rotation J = [c s; -s c] (rows and columns p, q) with (J^T A J)_pq = 0
+// (the symmetric Schur decomposition of the 2 x 2 block).
+__device__ __forceinline__ void jac_rot(double app, double aqq, double apq, double &c, double &s) {
+  if (apq == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  const double tau = (aqq - app) / (2.0 * apq);
+  const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+// A = Q (symmetric from its lower triangle, zero padded to ne), V = I, and the
+// side array of round 0.  Grid (ne / 256 row blocks, ne columns, B).
+__global__ __launch_bounds__(256) void jacobi_init_kernel(const JacDesc *__restrict__ jd) {
+  const JacDesc J = jd[blockIdx.z];
+  const int c = blockIdx.y, i = blockIdx.x * 256 + threadIdx.x;
+  if (c >= J.ne || i >= J.ne) return;
+  double a = 0.0;
+  if (i < J.n && c < J.n) a = i >= c ? J.Q[(size_t)c * J.ldq + i] : J.Q[(size_t)i * J.ldq + c];
+  J.A[(size_t)c * J.ne + i] = a;
+  J.V[(size_t)c * J.ne + i] = i == c ? 1.0 : 0.0;
+  if (i == c) J.side[c] = a;
+  if (i == rr_partner(c, 0, J.ne)) J.side[J.ne + c] = a;
+}
+
+// One round: A <- J^T A J and V <- V J for the ne / 2 disjoint rotations of
+// round r (global round counter; each matrix uses r mod (ne - 1) and the side
+// slot r mod 2).  Workgroup j owns the columns of pair j.  Grid (ne_max / 2, B),
+// dynamic LDS 2 * ne_max doubles.
+__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc *__restrict__ jd, int r) {
+  const JacDesc J = jd[blockIdx.y];
+  const int ne = J.ne, j = blockIdx.x;
+  if (j >= ne / 2) return;
+  const int rb = r % (ne - 1);
+  const double *sd_in = J.side + (size_t)(r & 1) * 2 * ne;
+  double *sd_out = J.side + (size_t)((r + 1) & 1) * 2 * ne;
+  const int p = rr_pos(j, rb, ne), q = rr_pos(ne - 1 - j, rb, ne);
+  double cj, sj;
+  jac_rot(sd_in[p], sd_in[q], sd_in[ne + p], cj, sj);
+  extern __shared__ double lds[];
+  double *cp = lds, *cq = lds + ne;
+  auto *Ap = gptr(J.A + (size_t)p * ne), *Aq = gptr(J.A + (size_t)q * ne);
+  for (int i = threadIdx.x; i < ne; i += 256) {
+    cp[i] = Ap[i];
+    cq[i] = Aq[i];
+  }
+  auto *Vp = gptr(J.V + (size_t)p * ne), *Vq = gptr(J.V + (size_t)q * ne);
+  for (int i = threadIdx.x; i < ne; i += 256) {
+    const double a = Vp[i], b = Vq[i];
+    Vp[i] = cj * a - sj * b;
+    Vq[i] = sj * a + cj * b;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ne / 2; i += 256) {
+    const int P = rr_pos(i, rb, ne), Qr = rr_pos(ne - 1 - i, rb, ne);
+    double ci = cj, si = sj;
+    if (i != j) jac_rot(sd_in[P], sd_in[Qr], sd_in[ne + P], ci, si);
+    // columns: (A J) on rows P and Qr of the two owned columns
+    const double aPp = cp[P], aPq = cq[P], aQp = cp[Qr], aQq = cq[Qr];
+    const double bPp = cj * aPp - sj * aPq, bPq = sj * aPp + cj * aPq;
+    const double bQp = cj * aQp - sj * aQq, bQq = sj * aQp + cj * aQq;
+    // rows: J^T (A J) mixes rows P and Qr
+    double nPp = ci * bPp - si * bQp, nQp = si * bPp + ci * bQp;
+    double nPq = ci * bPq - si * bQq, nQq = si * bPq + ci * bQq;
+    if (i == j) {   // the annihilated entry of this pair's own 2 x 2 block
+      nQp = 0.0;
+      nPq = 0.0;
+    }
+    cp[P] = nPp;
+    cp[Qr] = nQp;
+    cq[P] = nPq;
+    cq[Qr] = nQq;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ne; i += 256) {
+    Ap[i] = cp[i];
+    Aq[i] = cq[i];
+  }
+  if (threadIdx.x == 0) {
+    const int r1 = (r + 1) % (ne - 1);
+    sd_out[p] = cp[p];
+    sd_out[q] = cq[q];
+    sd_out[ne + p] = cp[rr_partner(p, r1, ne)];
+    sd_out[ne + q] = cq[rr_partner(q, r1, ne)];
+  }
+}
+
+// Sums of squares of the off-diagonal and of all entries.  One workgroup per
+// matrix (grid B).
+__global__ __launch_bounds__(256) void jacobi_norms_kernel(const JacDesc *__restrict__ jd) {
+  const JacDesc J = jd[blockIdx.x];
+  __shared__ double sh[4];
+  double off = 0.0, fro = 0.0;
+  const auto *A = gptr((const double *)J.A);
+  for (int c = 0; c < J.ne; ++c) {
+    for (int i = threadIdx.x; i < J.ne; i += 256) {
+      const double a = A[(size_t)c * J.ne + i];
+      fro += a * a;
+      if (i != c) off += a * a;
+    }
+  }
+  off = block_sum256(off, sh);
+  fro = block_sum256(fro, sh);
+  if (threadIdx.x == 0) {
+    J.norms[0] = off;
+    J.norms[1] = fro;
+  }
+}
+
+// f_k = 1 / lambda_k for |lambda_k| > rtol * max|lambda|, else 0; the rank.
+// One workgroup per matrix (grid B).
+__global__ __launch_bounds__(256) void pinv_spectrum_kernel(const JacDesc *__restrict__ jd, double rtol) {
+  const JacDesc J = jd[blockIdx.x];
+  __shared__ double sh[4];
+  double mx = 0.0;
+  for (int k = threadIdx.x; k < J.ne; k += 256) mx = fmax(mx, fabs(J.A[(size_t)k * J.ne + k]));
+  mx = block_max256(mx, sh);
+  const double cut = rtol * mx;
+  double cnt = 0.0;
+  for (int k = threadIdx.x; k < J.ne; k += 256) {
+    const double l = J.A[(size_t)k * J.ne + k];
+    const bool keep = fabs(l) > cut;
+    J.f[k] = keep ? 1.0 / l : 0.0;
+    cnt += keep ? 1.0 : 0.0;
+  }
+  cnt = block_sum256(cnt, sh);
+  if (threadIdx.x == 0) {
+    J.norms[2] = mx;
+    J.norms[3] = cnt;
+  }
+}
+
+// Q^+ = V diag(f) V^T, one 64 x 64 output tile per workgroup (4 x 4 per
+// thread, K staged through LDS in chunks of 16).  Grid (n / 64, n / 64, B).
+__global__ __launch_bounds__(256) void pinv_form_kernel(const JacDesc *__restrict__ jd) {
+  const JacDesc J = jd[blockIdx.z];
+  const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+  if (i0 >= J.n || j0 >= J.n) return;
+  __shared__ double Vi[16][65], Vj[16][65];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const auto *V = gptr((const double *)J.V);
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int k0 = 0; k0 < J.ne; k0 += 16) {
+    for (int e = tid; e < 1024; e += 256) {
+      const int r = e & 63, kk = e >> 6, k = k0 + kk;
+      double vi = 0.0, vj = 0.0;
+      if (k < J.ne) {
+        const double fk = J.f[k];
+        if (i0 + r < J.ne) vi = V[(size_t)k * J.ne + i0 + r] * fk;
+        if (j0 + r < J.ne) vj = V[(size_t)k * J.ne + j0 + r];
+      }
+      Vi[kk][r] = vi;
+      Vj[kk][r] = vj;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Vi[kk][tx + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Vj[kk][ty + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int jj = j0 + ty + 16 * v;
+    if (jj >= J.n) continue;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int ii = i0 + tx + 16 * u;
+      if (ii < J.n) J.P[(size_t)jj * J.ldp + ii] = acc[u][v];
+    }
+  }
+}
+
+static size_t a256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Batched pseudo-inverse; see inla_pinv in the header.
+static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, const int *ldq, double *const *P,
+                      const int *ldp, double rtol, int *rank, int *sweeps, int *info) {
+  if (rtol <= 0) rtol = JAC_RTOL_DEFAULT;
+  std::vector<JacDesc> hd(B);
+  std::vector<size_t> off(B);
+  size_t total = 0;
+  int ne_max = 0;
+  for (int b = 0; b < B; ++b) {
+    const int ne = n[b] + (n[b] & 1);
+    off[b] = total;
+    total += 2 * a256(sizeof(double) * (size_t)ne * ne) + a256(sizeof(double) * 5 * ne) + a256(sizeof(double) * 4);
+    ne_max = std::max(ne_max, ne);
+  }
+  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  for (int b = 0; b < B; ++b) {
+    const int ne = n[b] + (n[b] & 1);
+    char *base = ctx.ws + off[b];
+    JacDesc &J = hd[b];
+    J.Q = Q[b]; J.ldq = ldq[b]; J.P = P[b]; J.ldp = ldp[b]; J.n = n[b]; J.ne = ne;
+    J.A = (double *)base;
+    base += a256(sizeof(double) * (size_t)ne * ne);
+    J.V = (double *)base;
+    base += a256(sizeof(double) * (size_t)ne * ne);
+    J.side = (double *)base;
+    J.f = J.side + 4 * ne;
+    base += a256(sizeof(double) * 5 * ne);
+    J.norms = (double *)base;
+  }
+  const JacDesc *dall = (const JacDesc *)ctx.upload(hd.data(), sizeof(JacDesc) * B);
+  if (!dall) return INLA_ERR_NOMEM;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 16.0 * ne_max * ne_max * B, [&] {
+    hipLaunchKernelGGL(jacobi_init_kernel, dim3((ne_max + 255) / 256, ne_max, B), dim3(256), 0, ctx.stream, dall);
+  });
+  std::vector<int> act(B);
+  for (int b = 0; b < B; ++b) { act[b] = b; sweeps[b] = 0; info[b] = INLA_INFO_OK; }
+  std::vector<double> prev(B, std::numeric_limits<double>::infinity());
+  std::vector<double> hn(4 * (size_t)B);
+  int r = 0;   // global round counter (keeps every matrix's schedule and side slot in step)
+  for (int sw = 0; sw < JAC_MAX_SWEEPS && !act.empty(); ++sw) {
+    std::vector<JacDesc> ha;
+    int ne_act = 0;
+    for (int b : act) { ha.push_back(hd[b]); ne_act = std::max(ne_act, hd[b].ne); }
+    const JacDesc *da = (const JacDesc *)ctx.upload(ha.data(), sizeof(JacDesc) * ha.size());
+    if (!da) return INLA_ERR_NOMEM;
+    const int nb = (int)ha.size();
+    const size_t lds = sizeof(double) * 2 * ne_act;
+    for (int k = 0; k < ne_act - 1; ++k, ++r) {
+      const int rr = r;
+      ctx.launch(INLA_K_SOLVE, 6.0 * ne_act * ne_act * nb, 32.0 * ne_act * ne_act * nb, [&] {
+        hipLaunchKernelGGL(jacobi_round_kernel, dim3(ne_act / 2, nb), dim3(256), lds, ctx.stream, da, rr);
+      });
+    }
+    ctx.launch(INLA_K_SOLVE, 0.0, 8.0 * ne_act * ne_act * nb, [&] {
+      hipLaunchKernelGGL(jacobi_norms_kernel, dim3(nb), dim3(256), 0, ctx.stream, da);
+    });
+    for (int q = 0; q < nb; ++q)
+      if (hipMemcpyAsync(hn.data() + 4 * q, ha[q].norms, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx.stream) !=
+          hipSuccess)
+        return INLA_ERR_HIP;
+    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    std::vector<int> keep;
+    for (int q = 0; q < nb; ++q) {
+      const int b = act[q];
+      sweeps[b] = sw + 1;
+      const double off_ = std::sqrt(hn[4 * q]), fro = std::sqrt(hn[4 * q + 1]);
+      if (!std::isfinite(off_) || !std::isfinite(fro)) { info[b] = INLA_INFO_NONFINITE; continue; }
+      const double eps = std::numeric_limits<double>::epsilon();
+      // converged: the off-diagonal part at the rounding level.  Clustered
+      // spectra pass through plateaus well above it (halving per sweep), so a
+      // sweep that no longer shrinks it ends the iteration only once it is
+      // already below 1e-14 of the matrix.
+      const bool done = off_ <= 4.0 * eps * fro || (off_ <= 1e-14 * fro && off_ >= 0.9 * prev[b]);
+      prev[b] = off_;
+      if (!done) keep.push_back(b);
+    }
+    // a matrix that keeps rotating resumes at round r, whose side slot its last
+    // round wrote
+    act.swap(keep);
+  }
+  for (int b : act) info[b] = INLA_INFO_EIG_MAXIT;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(pinv_spectrum_kernel, dim3(B), dim3(256), 0, ctx.stream, dall, rtol);
+  });
+  int n_max = 0;
+  for (int b = 0; b < B; ++b) n_max = std::max(n_max, n[b]);
+  const int tiles = (n_max + 63) / 64;
+  double fl = 0;
+  for (int b = 0; b < B; ++b) fl += 2.0 * n[b] * (double)n[b] * hd[b].ne;
+  ctx.launch(INLA_K_ASSEMBLE, fl, 0.0, [&] {
+    hipLaunchKernelGGL(pinv_form_kernel, dim3(tiles, tiles, B), dim3(256), 0, ctx.stream, dall);
+  });
+  for (int b = 0; b < B; ++b)
+    if (hipMemcpyAsync(hn.data() + 4 * b, hd[b].norms, sizeof(double) * 4, hipMemcpyDeviceToHost, ctx.stream) !=
+        hipSuccess)
+      return INLA_ERR_HIP;
+  if (hipStreamSynchronize(ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  for (int b = 0; b < B; ++b) rank[b] = (int)std::llround(hn[4 * b + 3]);
+  return ctx.check();
+}
+
+// ------------------------------------------------------------------ Woodbury Newton
+constexpr int WB_CH = 32;   // column chunks of the Q^+ products
+enum { WR_STEP = 0, WR_SCALE = 1, WR_ZTX = 2, WR_LOGDET = 3, WR_LOGLIK = 4, WR_NONFINITE = 5, WR_COUNT = 8 };
+enum { WV_X = 0, WV_B = 1, WV_U = 2, WV_T = 3, WV_W = 4 };
+
+struct WbDesc {
+  const double *Pq;    // Q^+ (caller's), full symmetric, column-major, ld ldq
+  const double *y, *E;
+  double *xext;        // caller's start / output vector [n]
+  double *M;           // factor storage: ldm = n_pad + PADN rows (row n_pad: border), n_pad columns
+  double *linv;
+  double *x, *b, *sw, *u, *s, *t, *w;   // [n_pad]
+  double *part;        // [WB_CH][n_pad]
+  double *res;         // [WR_COUNT]
+  int *info;
+  double lpar;         // Gaussian: sigma^2; Poisson: beta0
+  int n, n_pad, ldq, ldm, lik, pad_;
+};
+
+__device__ __forceinline__ double *wb_vec(const WbDesc &D, int v) {
+  return v == WV_X ? D.x : v == WV_B ? D.b : v == WV_U ? D.u : v == WV_T ? D.t : D.w;
+}
+
+// x <- caller's vector (start = 1) or 0, padding zero.  Grid (n_pad / 256, B).
+__global__ __launch_bounds__(256) void wb_start_kernel(const WbDesc *__restrict__ wd, int start) {
+  const WbDesc D = wd[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= D.n_pad) return;
+  D.x[i] = (start && i < D.n) ? D.xext[i] : 0.0;
+}
+
+// b = g + W x and sw = sqrt(W) at the current iterate (Q_l = diag(W), the
+// negative second derivative of log pi(y | eta)); clears the factor status.
+__global__ __launch_bounds__(256) void wb_lik_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *D.info = 0;
+  if (i >= D.n_pad) return;
+  double bi = 0.0, si = 0.0;
+  if (i < D.n) {
+    const double xi = D.x[i];
+    double g, W;
+    if (D.lik == LIK_POISSON) {
+      const double mu = (D.E ? D.E[i] : 1.0) * exp(D.lpar + xi);
+      g = D.y[i] - mu;
+      W = mu;
+    } else {
+      W = 1.0 / D.lpar;
+      g = (D.y[i] - xi) * W;
+    }
+    bi = g + W * xi;
+    si = sqrt(W);
+  }
+  D.b[i] = bi;
+  D.sw[i] = si;
+}
+
+// Partial products of Q^+ v over WB_CH column chunks (v = src, or sw * src).
+// Grid (n_pad / 256, WB_CH, B); the row reads of each column are coalesced.
+__global__ __launch_bounds__(256) void wb_symv_part_kernel(const WbDesc *__restrict__ wd, int src, int scaled) {
+  const WbDesc D = wd[blockIdx.z];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x * 256 >= D.n_pad) return;
+  const int cs = (D.n + WB_CH - 1) / WB_CH;
+  const int j0 = blockIdx.y * cs, j1 = min(D.n, j0 + cs);
+  const double *v = wb_vec(D, src);
+  double acc = 0.0;
+  if (i < D.n) {
+    const auto *col = gptr(D.Pq) + i;
+#pragma unroll 8
+    for (int j = j0; j < j1; ++j) acc = fma(col[(size_t)j * D.ldq], scaled ? D.sw[j] * v[j] : v[j], acc);
+  }
+  if (i < D.n_pad) D.part[(size_t)blockIdx.y * D.n_pad + i] = acc;
+}
+
+// dst = sum of the partials in chunk order; with `border` also the border row
+// of M: r = sw * dst.  Grid (n_pad / 256, B).
+__global__ __launch_bounds__(256) void wb_symv_reduce_kernel(const WbDesc *__restrict__ wd, int dst, int border) {
+  const WbDesc D = wd[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= D.n_pad) return;
+  double s = 0.0;
+  for (int c = 0; c < WB_CH; ++c) s += D.part[(size_t)c * D.n_pad + i];
+  wb_vec(D, dst)[i] = s;
+  if (border) D.M[(size_t)i * D.ldm + D.n_pad] = D.sw[i] * s;
+}
+
+// M = I + diag(sw) Q^+ diag(sw), lower triangle, identity on the padding, zero
+// border rows below row n_pad (row n_pad is written by the reduction).  Grid
+// (ldm / 256, n_pad, B).
+__global__ __launch_bounds__(256) void wb_assemble_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.z];
+  const int j = blockIdx.y;
+  if (j >= D.n_pad) return;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= D.ldm || i < j || i == D.n_pad) return;
+  double v = 0.0;
+  if (i < D.n_pad) {
+    v = i == j ? 1.0 : 0.0;
+    if (i < D.n && j < D.n) v += D.sw[i] * D.Pq[(size_t)j * D.ldq + i] * D.sw[j];
+  }
+  D.M[(size_t)j * D.ldm + i] = v;
+}
+
+// s = L^{-1} r from the factored border row.  Grid (n_pad / 256, B).
+__global__ __launch_bounds__(256) void wb_border_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= D.n_pad) return;
+  D.s[i] = D.M[(size_t)i * D.ldm + D.n_pad];
+}
+
+// x_new = u - w, the step, max(1, |x_new|_inf), z^T x_new with
+// z = b - sw * t, and log|M| = 2 sum log L_ii.  One workgroup per theta.
+__global__ __launch_bounds__(256) void wb_update_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.x];
+  __shared__ double sh[4];
+  double step = 0.0, xmax = 0.0, ztx = 0.0, ld = 0.0, bad = 0.0;
+  for (int i = threadIdx.x; i < D.n; i += 256) {
+    const double xn = D.u[i] - D.w[i];
+    const double zi = D.b[i] - D.sw[i] * D.t[i];
+    step = fmax(step, fabs(xn - D.x[i]));
+    xmax = fmax(xmax, fabs(xn));
+    ztx += zi * xn;
+    ld += log(D.M[(size_t)i * D.ldm + i]);
+    if (!isfinite(xn)) bad = 1.0;
+    D.x[i] = xn;
+  }
+  step = block_max256(step, sh);
+  xmax = block_max256(xmax, sh);
+  ztx = block_sum256(ztx, sh);
+  ld = block_sum256(ld, sh);
+  bad = block_max256(bad, sh);
+  if (threadIdx.x == 0) {
+    D.res[WR_STEP] = step;
+    D.res[WR_SCALE] = fmax(1.0, xmax);
+    D.res[WR_ZTX] = ztx;
+    D.res[WR_LOGDET] = 2.0 * ld;
+    D.res[WR_NONFINITE] = bad;
+  }
+}
+
+// sum_i log pi(y_i | eta_i) at the mode (normalising constants included) and
+// the caller's copy of the mode.  One workgroup per theta.
+__global__ __launch_bounds__(256) void wb_final_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.x];
+  __shared__ double sh[4];
+  double ll = 0.0;
+  for (int i = threadIdx.x; i < D.n; i += 256) {
+    const double xi = D.x[i], yi = D.y[i];
+    if (D.lik == LIK_POISSON) {
+      const double Ei = D.E ? D.E[i] : 1.0;
+      const double eta = D.lpar + xi;
+      ll += yi * (log(Ei) + eta) - Ei * exp(eta) - lgamma(yi + 1.0);
+    } else {
+      const double r = yi - xi;
+      ll += -0.5 * log(2.0 * M_PI * D.lpar) - r * r / (2.0 * D.lpar);
+    }
+    D.xext[i] = xi;
+  }
+  ll = block_sum256(ll, sh);
+  if (threadIdx.x == 0) D.res[WR_LOGLIK] = ll;
+}
+
+static int wb_validate(int B, const inla_model *models, const double *theta, int ldtheta, double *const *x,
+                       const inla_opts *opts, inla_result *res) {
+  if (B < 0) return -2;
+  if (B == 0) return INLA_OK;
+  if (!models) return -3;
+  if (!theta || ldtheta < 1) return -4;
+  if (!x) return -6;
+  if (!res) return -8;
+  if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
+  for (int b = 0; b < B; ++b) {
+    const inla_model &m = models[b];
+    if (m.prior != INLA_PRIOR_PINV || m.n < 1 || m.k != 0 || m.m != 0 || !m.Qprior || m.ldq < m.n || !m.y ||
+        (m.lik != INLA_LIK_GAUSSIAN && m.lik != INLA_LIK_POISSON))
+      return -3;
+    if (!x[b]) return -6;
+  }
+  return INLA_OK;
+}
+
+static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
+                         double *const *x, const inla_opts *opts, inla_result *res) {
+  const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 50;
+  const double tol = opts && opts->tol > 0 ? opts->tol : 1e-11;
+  const int start = opts ? opts->start : 0;
+  std::vector<WbDesc> hd(B);
+  std::vector<size_t> off(B);
+  size_t total = a256(sizeof(double) * WR_COUNT * B) + a256(sizeof(int) * B);
+  int np_max = 0, ldm_max = 0;
+  for (int b = 0; b < B; ++b) {
+    const int np = round_up(models[b].n, PADN), ldm = np + PADN;
+    off[b] = total;
+    total += a256(sizeof(double) * (size_t)ldm * np) + a256(sizeof(double) * (size_t)np * NBI) +
+             a256(sizeof(double) * (size_t)(7 + WB_CH) * np);
+    np_max = std::max(np_max, np);
+    ldm_max = std::max(ldm_max, ldm);
+  }
+  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  double *dres = (double *)ctx.ws;
+  int *dinfo = (int *)(ctx.ws + a256(sizeof(double) * WR_COUNT * B));
+  for (int b = 0; b < B; ++b) {
+    const inla_model &m = models[b];
+    WbDesc &D = hd[b];
+    D = WbDesc{};
+    D.Pq = m.Qprior; D.ldq = m.ldq; D.y = m.y; D.E = m.E; D.xext = x[b];
+    D.n = m.n; D.n_pad = round_up(m.n, PADN); D.ldm = D.n_pad + PADN; D.lik = m.lik;
+    const double lp = theta[(size_t)b * ldtheta];
+    D.lpar = m.lik == INLA_LIK_GAUSSIAN ? std::exp(lp) : lp;
+    char *base = ctx.ws + off[b];
+    D.M = (double *)base;
+    base += a256(sizeof(double) * (size_t)D.ldm * D.n_pad);
+    D.linv = (double *)base;
+    base += a256(sizeof(double) * (size_t)D.n_pad * NBI);
+    double *v = (double *)base;
+    D.x = v; D.b = v + D.n_pad; D.sw = v + 2 * D.n_pad; D.u = v + 3 * D.n_pad; D.s = v + 4 * D.n_pad;
+    D.t = v + 5 * D.n_pad; D.w = v + 6 * D.n_pad; D.part = v + 7 * D.n_pad;
+    D.res = dres + WR_COUNT * b;
+    D.info = dinfo + b;
+    res[b] = inla_result{};
+    if (!std::isfinite(lp)) res[b].info = INLA_INFO_NONFINITE;
+  }
+  std::vector<int> act;
+  for (int b = 0; b < B; ++b) if (res[b].info == INLA_INFO_OK) act.push_back(b);
+  {
+    const WbDesc *dall = (const WbDesc *)ctx.upload(hd.data(), sizeof(WbDesc) * B);
+    if (!dall) return INLA_ERR_NOMEM;
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_start_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dall, start);
+    });
+  }
+  std::vector<double> hres((size_t)WR_COUNT * B);
+  std::vector<int> hinfo(B);
+  std::vector<int> done;
+  for (int it = 1; it <= max_iter && !act.empty(); ++it) {
+    std::vector<WbDesc> ha;
+    std::vector<HostFactor> fs;
+    std::vector<ThetaDesc> td;
+    int np = 0, ldm = 0;
+    double qbytes = 0;
+    for (int b : act) {
+      const WbDesc &D = hd[b];
+      ha.push_back(D);
+      np = std::max(np, D.n_pad);
+      ldm = std::max(ldm, D.ldm);
+      qbytes += 8.0 * D.n * D.n;
+      HostFactor h{};
+      h.d.A = D.M; h.d.linv = D.linv; h.d.info = D.info; h.d.ld = D.ldm; h.d.nf = D.n_pad;
+      h.d.nrows = D.ldm; h.d.ncols = D.n_pad; h.d.id_row0 = std::numeric_limits<int>::max();
+      h.n_real = D.n; h.kb_real = 1; h.ks_real = 0;
+      fs.push_back(h);
+      ThetaDesc t{};
+      t.W = D.M; t.ldw = D.ldm; t.linv = D.linv; t.n_pad = D.n_pad; t.n = D.n; t.r = D.s; t.u = D.t;
+      td.push_back(t);
+    }
+    const int na = (int)ha.size();
+    const WbDesc *da = (const WbDesc *)ctx.upload(ha.data(), sizeof(WbDesc) * na);
+    if (!da) return INLA_ERR_NOMEM;
+    const dim3 gv((np + 255) / 256, na);
+    ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_lik_kernel, gv, dim3(256), 0, ctx.stream, da);
+    });
+    ctx.launch(INLA_K_SOLVE, 2.0 * qbytes / 8.0, qbytes, [&] {
+      hipLaunchKernelGGL(wb_symv_part_kernel, dim3((np + 255) / 256, WB_CH, na), dim3(256), 0, ctx.stream, da, WV_B, 0);
+    });
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_symv_reduce_kernel, gv, dim3(256), 0, ctx.stream, da, WV_U, 1);
+    });
+    ctx.launch(INLA_K_ASSEMBLE, 0.0, qbytes, [&] {
+      hipLaunchKernelGGL(wb_assemble_kernel, dim3((ldm + 255) / 256, np, na), dim3(256), 0, ctx.stream, da);
+    });
+    int rc = factor_batch(ctx, fs, INLA_PREC_FP64);
+    if (rc) return rc;
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_border_kernel, gv, dim3(256), 0, ctx.stream, da);
+    });
+    launch_trsv_bwd(ctx, td, np, V_R, V_U, 0.0, INLA_PREC_FP64);
+    ctx.launch(INLA_K_SOLVE, 2.0 * qbytes / 8.0, qbytes, [&] {
+      hipLaunchKernelGGL(wb_symv_part_kernel, dim3((np + 255) / 256, WB_CH, na), dim3(256), 0, ctx.stream, da, WV_T, 1);
+    });
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_symv_reduce_kernel, gv, dim3(256), 0, ctx.stream, da, WV_W, 0);
+    });
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_update_kernel, dim3(na), dim3(256), 0, ctx.stream, da);
+    });
+    if (hipMemcpyAsync(hres.data(), dres, sizeof(double) * WR_COUNT * B, hipMemcpyDeviceToHost, ctx.stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * B, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess)
+      return INLA_ERR_HIP;
+    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    if ((rc = ctx.check())) return rc;
+    std::vector<int> keep;
+    for (int b : act) {
+      const double *R = hres.data() + WR_COUNT * b;
+      inla_result &o = res[b];
+      o.iters = it;
+      o.step = R[WR_STEP];
+      if (hinfo[b] > 0) { o.info = hinfo[b]; continue; }
+      if (R[WR_NONFINITE] != 0.0 || !std::isfinite(R[WR_STEP])) { o.info = INLA_INFO_NONFINITE; continue; }
+      if (models[b].lik == INLA_LIK_GAUSSIAN || R[WR_STEP] <= tol * R[WR_SCALE]) {
+        done.push_back(b);
+        continue;
+      }
+      if (it == max_iter) {
+        o.info = INLA_INFO_NEWTON_MAXIT;
+        done.push_back(b);
+        continue;
+      }
+      keep.push_back(b);
+    }
+    act.swap(keep);
+  }
+  if (!done.empty()) {
+    std::vector<WbDesc> ha;
+    for (int b : done) ha.push_back(hd[b]);
+    const WbDesc *da = (const WbDesc *)ctx.upload(ha.data(), sizeof(WbDesc) * ha.size());
+    if (!da) return INLA_ERR_NOMEM;
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(wb_final_kernel, dim3((unsigned)ha.size()), dim3(256), 0, ctx.stream, da);
+    });
+    if (hipMemcpyAsync(hres.data(), dres, sizeof(double) * WR_COUNT * B, hipMemcpyDeviceToHost, ctx.stream) !=
+        hipSuccess)
+      return INLA_ERR_HIP;
+    if (hipStreamSynchronize(ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    for (int b : done) {
+      const double *R = hres.data() + WR_COUNT * b;
+      inla_result &o = res[b];
+      o.xqx = R[WR_ZTX];
+      o.loglik = R[WR_LOGLIK];
+      o.logdet_qstar = R[WR_LOGDET];
+      o.objective = o.loglik - 0.5 * o.xqx - 0.5 * o.logdet_qstar;
+    }
+  }
+  return ctx.check();
+}
+
+}  // namespace inla
+
+extern "C" {
+
+int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *Q, const int32_t *ldq,
+              double *const *Qpinv, const int32_t *ldp, double rtol, int32_t *rank, int32_t *sweeps, int32_t *info) {
+  using namespace inla;
+  if (!h) return -1;
+  if (B < 0) return -2;
+  if (B == 0) return INLA_OK;
+  if (!n) return -3;
+  if (!Q) return -4;
+  if (!ldq) return -5;
+  if (!Qpinv) return -6;
+  if (!ldp) return -7;
+  if (!rank) return -9;
+  if (!sweeps) return -10;
+  if (!info) return -11;
+  for (int b = 0; b < B; ++b) {
+    if (n[b] < 1 || n[b] > JAC_MAX_N) return -3;
+    if (!Q[b]) return -4;
+    if (ldq[b] < n[b]) return -5;
+    if (!Qpinv[b]) return -6;
+    if (ldp[b] < n[b]) return -7;
+  }
+  if (!(rtol < 1.0)) return -8;
+  return pinv_batch(*handle_ctx(h), B, n, Q, ldq, Qpinv, ldp, rtol, rank, sweeps, info);
+}
+
+int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                       double *const *x, const inla_opts *opts, inla_result *res) {
+  using namespace inla;
+  if (!h) return -1;
+  int rc = wb_validate(B, models, theta, ldtheta, x, opts, res);
+  if (rc || B == 0) return rc;
+  return woodbury_eval(*handle_ctx(h), B, models, theta, ldtheta, x, opts, res);
+}
+
+}  // extern "C"

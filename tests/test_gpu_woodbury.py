@@ -1,0 +1,174 @@
+"""GPU parity of the Moore-Penrose route (inla_pinv, inla_woodbury_eval) against
+the CPU reference (``oracle/woodbury_oracle.py``) on the same seeded intrinsic
+RW1 x Besag models, and against the GPU kriging route on the equivalent proper
+prior with sum-to-zero constraints.
+
+Tolerances: both pseudo-inverses are backward stable, so they differ by about
+n eps ||Q^+|| times the spread of the spectrum near the rank cut; on these
+models CPU computations of Q^+ by two different algorithms differ by <= 4e-13
+of max|Q^+| (n <= 3000), and the modes and objectives they lead to by <= 3e-13
+and <= 4e-15 relative.  The bounds below (1e-11 on Q^+, 1e-9 on modes and
+objectives, as for the kriging route) leave two orders of margin."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import inla_oracle as O
+from oracle import woodbury_oracle as WB
+from paper_2311_08050_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-woodbury] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def null_rows(n_s, n_t):
+    return synth.sum_to_zero_rows(n_s, n_t)
+
+
+@pytest.mark.parametrize("shapes", [[(5, 3)], [(13, 7), (4, 3)], [(40, 12)]])
+def test_pinv_matches_reference(lib, shapes):
+    mats, refs = [], []
+    for i, (ns, nt) in enumerate(shapes):
+        m = synth.rw1_besag(ns, nt, seed=40 + i)
+        Q = WB.prior_precision(m, np.array([0.3 * i, 0.0]))
+        mats.append(Q)
+        refs.append(WB.pseudo_inverse(Q))
+    say(f"pinv n = {[q.shape[0] for q in mats]}")
+    out, rank, sweeps, info = lib.pinv([dev(q) for q in mats])
+    say(f"ranks {rank.tolist()}, sweeps {sweeps.tolist()}, info {info.tolist()}")
+    for P, (Pr, rr, _), r, s, inf in zip(out, refs, rank, sweeps, info):
+        Pg = P.cpu().numpy()
+        assert inf == 0 and r == rr and 1 <= s <= 40
+        assert np.max(np.abs(Pg - Pr)) <= 1e-11 * np.max(np.abs(Pr))
+        assert np.array_equal(Pg, Pg.T) or np.max(np.abs(Pg - Pg.T)) <= 1e-14 * np.max(np.abs(Pr))
+
+
+def test_pinv_small_and_full_rank(lib):
+    """n = 1, n = 2 and an odd full-rank SPD matrix: Q^+ = Q^{-1}; a zero matrix: 0."""
+    rng = np.random.default_rng(3)
+    G = rng.normal(size=(7, 7))
+    mats = [np.array([[2.5]]), np.array([[2.0, 0.5], [0.5, 1.0]]), G @ G.T + 0.3 * np.eye(7), np.zeros((3, 3))]
+    out, rank, sweeps, info = lib.pinv([dev(q) for q in mats])
+    assert rank.tolist() == [1, 2, 7, 0] and np.all(info == 0)
+    for P, Q in zip(out[:3], mats[:3]):
+        inv = np.linalg.inv(Q)
+        assert np.max(np.abs(P.cpu().numpy() - inv)) <= 1e-12 * np.max(np.abs(inv))
+    assert np.all(out[3].cpu().numpy() == 0.0)
+
+
+@pytest.mark.parametrize("lik", ["poisson", "gaussian"])
+def test_woodbury_eval_matches_reference(lib, lik):
+    """A batch of uneven models and theta: pseudo-inverse per theta on the GPU,
+    then the Woodbury Newton iteration and the objective."""
+    from paper_2311_08050_amd.binding import DeviceModel
+    shapes = [(13, 7), (24, 10), (13, 7)]
+    models = [synth.rw1_besag(ns, nt, seed=50 + i, lik=lik) for i, (ns, nt) in enumerate(shapes)]
+    thetas = [synth.rw1_besag_theta0(nt, lik) + np.array([0.3 * i - 0.2, 0.05 * i]) for i, (_, nt) in enumerate(shapes)]
+    Qp = [WB.prior_precision(m, th) for m, th in zip(models, thetas)]
+    P, rank, _, info = lib.pinv([dev(q) for q in Qp])
+    assert np.all(info == 0)
+    dms = [DeviceModel(m) for m in models]
+    res, xs = lib.woodbury_eval(dms, [th[1] for th in thetas], P)
+    for i, (m, th, r, x) in enumerate(zip(models, thetas, res, xs)):
+        ref = WB.laplace_eval(m, th)
+        xg = x.cpu().numpy()
+        say(f"{lik} theta {i}: n={m['n']} rank {rank[i]}, GPU {r['iters']} it objective {r['objective']:.10f}, "
+            f"reference {ref['iters']} it {ref['objective']:.10f}")
+        assert r["info"] == 0 and ref["info"] == 0 and rank[i] == ref["rank"]
+        assert abs(r["iters"] - ref["iters"]) <= 1
+        assert np.max(np.abs(xg - ref["x"])) <= 1e-9 * max(1.0, np.max(np.abs(ref["x"])))
+        assert abs(r["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
+        assert abs(r["xqx"] - ref["xqx"]) <= 1e-9 * max(1.0, abs(ref["xqx"]))
+        assert abs(r["loglik"] - ref["loglik"]) <= 1e-9 * abs(ref["loglik"])
+        if lik == "gaussian":
+            assert r["iters"] == 1
+
+
+def test_woodbury_equals_gpu_kriging_route(lib):
+    """The same posterior through the kriging route on the GPU: proper prior
+    Q + N N^T with the per-region and per-time sum-to-zero constraints."""
+    from paper_2311_08050_amd.binding import DeviceModel
+    from tests.test_oracle_woodbury import known_null_basis
+    ns, nt = 24, 10
+    m = synth.rw1_besag(ns, nt, seed=61)
+    th = synth.rw1_besag_theta0(nt) + np.array([0.1, -0.05])
+    Q = WB.prior_precision(m, th)
+    P, _, _, _ = lib.pinv([dev(Q)])
+    rw, xw = lib.woodbury_eval([DeviceModel(m)], [th[1]], P)
+    N = known_null_basis(ns, nt)
+    C = null_rows(ns, nt)
+    km = {"n": m["n"], "lik": "poisson", "prior": "dense", "y": m["y"], "E": m["E"], "A": None, "C": C,
+          "e": np.zeros(C.shape[0]), "Qprior": Q + N @ N.T}
+    rk, xk = lib.laplace_eval([DeviceModel(km)], np.array([[th[1]]]))
+    say(f"Woodbury {rw[0]['objective']:.10f} ({rw[0]['iters']} it), kriging {rk[0]['objective']:.10f} "
+        f"({rk[0]['iters']} it)")
+    assert rw[0]["info"] == 0 and rk[0]["info"] == 0
+    assert abs(rw[0]["objective"] - rk[0]["objective"]) <= 1e-9 * abs(rk[0]["objective"])
+    a, b = xw[0].cpu().numpy(), xk[0].cpu().numpy()
+    assert np.max(np.abs(a - b)) <= 1e-9 * max(1.0, np.max(np.abs(b)))
+
+
+def test_woodbury_warm_start_and_errors(lib):
+    from paper_2311_08050_amd.binding import DeviceModel, LibraryError
+    m = synth.rw1_besag(13, 7, seed=70)
+    th = synth.rw1_besag_theta0(7)
+    P, _, _, _ = lib.pinv([dev(WB.prior_precision(m, th))])
+    dm = DeviceModel(m)
+    r0, x0 = lib.woodbury_eval([dm], [th[1]], P)
+    r1, x1 = lib.woodbury_eval([dm], [th[1]], P, x=[x0[0].clone()], start=1)
+    assert r1[0]["info"] == 0 and r1[0]["iters"] <= 2
+    assert np.max(np.abs(x1[0].cpu().numpy() - x0[0].cpu().numpy())) <= 1e-10
+    assert abs(r1[0]["objective"] - r0[0]["objective"]) <= 1e-11 * abs(r0[0]["objective"])
+    # max_iter reached: reported, last iterate and objective kept
+    r2, _ = lib.woodbury_eval([dm], [th[1]], P, max_iter=2)
+    assert r2[0]["info"] == -1 and r2[0]["iters"] == 2
+    # non-finite likelihood parameter
+    r3, _ = lib.woodbury_eval([dm], [float("nan")], P)
+    assert r3[0]["info"] == -3
+    with pytest.raises(LibraryError):
+        lib.pinv([dev(np.eye(4097))[:4097, :4097]])
+
+
+def test_woodbury_n3000(lib):
+    """n = 3000 (100 regions x 30 times, rank 2871): one pseudo-inverse on the
+    GPU, three theta with Q^+(tau) = Q(1)^+ / tau, against the reference at one
+    theta."""
+    import time
+
+    from paper_2311_08050_amd.binding import DeviceModel
+    m = synth.rw1_besag(100, 30, seed=72)
+    R = WB.structure(m)
+    t0 = time.perf_counter()
+    P1, rank, sweeps, info = lib.pinv([dev(R)])
+    lib.torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    say(f"n=3000 pinv: rank {rank[0]}, {sweeps[0]} sweeps, {t1 - t0:.2f} s")
+    assert info[0] == 0 and rank[0] == 3000 - 129
+    th0 = synth.rw1_besag_theta0(30)
+    thetas = [th0 + np.array([d, 0.02 * d]) for d in (-0.3, 0.0, 0.3)]
+    Ps = [P1[0] / math.exp(th[0]) for th in thetas]
+    dm = DeviceModel(m)
+    res, xs = lib.woodbury_eval([dm] * 3, [th[1] for th in thetas], Ps)
+    lib.torch.cuda.synchronize()
+    say(f"n=3000 Woodbury eval of 3 theta: {time.perf_counter() - t1:.2f} s, iters {[r['iters'] for r in res]}")
+    ref = WB.laplace_eval(m, thetas[1])
+    r, x = res[1], xs[1].cpu().numpy()
+    assert all(q["info"] == 0 for q in res)
+    assert np.max(np.abs(x - ref["x"])) <= 1e-9 * max(1.0, np.max(np.abs(ref["x"])))
+    assert abs(r["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
+    # the GPU pseudo-inverse itself, sampled columns
+    Pr, _, _ = WB.pseudo_inverse(R)
+    cols = np.random.default_rng(0).choice(3000, 16, replace=False)
+    Pg = P1[0][:, cols].cpu().numpy()
+    assert np.max(np.abs(Pg - Pr[:, cols])) <= 1e-11 * np.max(np.abs(Pr))
