@@ -194,8 +194,9 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
 def run_extras(lib, binding, synth, dms, thetas, xs):
     """Separately timed figures (not part of `value`): marginal variances and the
     variational-Bayes mean correction of the headline batch (FP64, from the modes
-    the last variant left in xs), and Stage 1 plus the CCD exploration on the
-    n = 3000 space-time configuration."""
+    the last variant left in xs), Stage 1 plus the CCD exploration on the
+    n = 3000 space-time configuration, and the Moore-Penrose route against
+    kriging on an intrinsic n = 3000 model."""
     import numpy as np
     import torch
 
@@ -236,7 +237,79 @@ def run_extras(lib, binding, synth, dms, thetas, xs):
                            "evaluations": g["evals"], "theta_evals_per_s": g["evals"] / (t1 - t0),
                            "hessian_and_ccd_s": t2 - t1, "ccd_points": len(pts), "info": [g["info"], hinfo]}
     log(f"stage 1 at n=3000: {t1 - t0:.2f} s ({g['iters']} iterations), Hessian + CCD {t2 - t1:.2f} s")
+    out["moore_penrose_n3000"] = run_moore_penrose(lib, binding, synth)
     return out
+
+
+def intrinsic_inputs(model):
+    """Caller-side inputs of the intrinsic RW1 x Besag model: its structure
+    matrix R = R_t kron (D - Adj) and an orthonormal basis of its null space
+    (time-constant per region, region-constant per time)."""
+    import numpy as np
+    n_s, n_t = model["n_s"], model["n_t"]
+    Rt = np.diag(np.r_[1.0, 2.0 * np.ones(n_t - 2), 1.0]) - np.eye(n_t, k=1) - np.eye(n_t, k=-1)
+    Rs = np.zeros((n_s, n_s))
+    for i, j in model["edges"]:
+        Rs[i, j] = Rs[j, i] = -1.0
+    Rs -= np.diag(Rs.sum(axis=1))
+    cols = np.hstack([np.kron(np.ones((n_t, 1)), np.eye(n_s)), np.kron(np.eye(n_t), np.ones((n_s, 1)))])
+    Qr, Rr = np.linalg.qr(cols)
+    return np.kron(Rt, Rs), Qr[:, np.abs(np.diag(Rr)) > 1e-10]
+
+
+def run_moore_penrose(lib, binding, synth, B=9):
+    """The paper's comparison of its Moore-Penrose route with kriging, on one
+    posterior: the intrinsic RW1 x Besag Poisson model at n = 3000 (100 regions
+    x 30 times, null space of dimension 129), B theta.  Woodbury route:
+    Q_prior(theta)^+ = R^+ / tau from one GPU pseudo-inverse of R (timed apart),
+    then inla_woodbury_eval.  Kriging route: inla_laplace_eval on the proper
+    prior tau R + N N^T with the 129 sum-to-zero constraints.  Both FP64; the two
+    objectives agree to rounding."""
+    import math
+
+    import numpy as np
+    import torch
+    m = synth.rw1_besag(100, 30, seed=72)
+    R, N = intrinsic_inputs(m)
+    th0 = synth.rw1_besag_theta0(30)
+    thetas = synth.normal_batch(th0, B, 0.3, seed=73)
+    Rd = torch.as_tensor(R).cuda()
+    lib.pinv([Rd])                     # warm-up (workspace)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P, rank, sweeps, info = lib.pinv([Rd])
+    torch.cuda.synchronize()
+    t_pinv = time.perf_counter() - t0
+    Ps = [P[0] / math.exp(th[0]) for th in thetas]
+    dm = binding.DeviceModel(m)
+    lib.woodbury_eval([dm], [thetas[0][1]], Ps[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rw, _ = lib.woodbury_eval([dm] * B, thetas[:, 1], Ps)
+    torch.cuda.synchronize()
+    t_wood = time.perf_counter() - t0
+    C = synth.sum_to_zero_rows(100, 30)
+    kms = [binding.DeviceModel({"n": m["n"], "lik": "poisson", "prior": "dense", "y": m["y"], "E": m["E"], "A": None,
+                                "C": C, "e": np.zeros(C.shape[0]),
+                                "Qprior": math.exp(th[0]) * R + N @ N.T}) for th in thetas]
+    lib.laplace_eval(kms[:1], thetas[:1, 1:])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rk, _ = lib.laplace_eval(kms, thetas[:, 1:])
+    torch.cuda.synchronize()
+    t_krig = time.perf_counter() - t0
+    d = max(abs(a["objective"] - b["objective"]) / abs(b["objective"]) for a, b in zip(rw, rk))
+    res = {"workload": "Poisson RW1 x Besag (intrinsic) n=3000 (100 regions x 30 times), null space 129, "
+                       f"batch {B} theta ~ N(theta0, 0.3^2 I)",
+           "pinv_s": t_pinv, "pinv_sweeps": int(sweeps[0]), "pinv_rank": int(rank[0]), "pinv_info": int(info[0]),
+           "woodbury_theta_evals_per_s": B / t_wood, "kriging_theta_evals_per_s": B / t_krig,
+           "woodbury_iters_mean": float(np.mean([r["iters"] for r in rw])),
+           "kriging_iters_mean": float(np.mean([r["iters"] for r in rk])),
+           "max_rel_objective_diff": d, "info": [r["info"] for r in rw] + [r["info"] for r in rk],
+           "precision": "fp64"}
+    log(f"Moore-Penrose n=3000: pinv {t_pinv:.2f} s ({int(sweeps[0])} sweeps); Woodbury {B / t_wood:.1f} vs "
+        f"kriging {B / t_krig:.1f} theta-evals/s; objectives agree to {d:.1e}")
+    return res
 
 
 def main():
@@ -263,6 +336,8 @@ def main():
                     help="window the trailing-update kernel of this precision instead of the roofline kernel")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (HBM counter calibration)")
+    ap.add_argument("--moore-penrose-only", action="store_true",
+                    help="only run the Moore-Penrose vs kriging comparison at n = 3000 (for profiling)")
     args = ap.parse_args()
     if args.rocprof_window:
         print(json.dumps(rocprof_window(args.rocprof_window, args.bench_json, args.window_precision)))
@@ -277,6 +352,10 @@ def main():
     from paper_2311_08050_amd import binding, synth
 
     torch.cuda.set_device(0)
+    if args.moore_penrose_only:
+        lib = binding.Library()
+        print(json.dumps({"moore_penrose_n3000": run_moore_penrose(lib, binding, synth)}), flush=True)
+        return
     if args.calibrate_copy:
         nbytes = 1 << 30
         a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
