@@ -43,12 +43,14 @@ Ctx *handle_ctx(inla_handle *h);
 constexpr int JAC_MAX_N = 4096;      // two columns of the working matrix fit the 64 KiB of LDS
 constexpr int JAC_MAX_SWEEPS = 40;
 constexpr double JAC_RTOL_DEFAULT = 1e-9;
+constexpr int JAC_NORM_BLOCKS = 256;
 
 struct JacDesc {
   const double *Q;   // input, lower triangle read (ld ldq)
   double *A, *V;     // ne x ne working matrix and eigenvectors (ld ne)
   double *side;      // 2 slots x 2 x ne: [slot][0][k] = a_kk, [slot][1][k] = a_{partner(k), k}
   double *f;         // [ne] 1/lambda_k or 0
+  double *part;      // [2 * JAC_NORM_BLOCKS] per-workgroup partial sums of squares
   double *norms;     // [4] off-diagonal sum of squares, sum of squares, max|lambda|, rank
   double *P;         // output Q^+ (ld ldp), full symmetric
   int n, ne, ldq, ldp;
@@ -157,14 +159,15 @@ __global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc *__rest
   }
 }
 
-// Sums of squares of the off-diagonal and of all entries.  One workgroup per
-// matrix (grid B).
+// Sums of squares of the off-diagonal and of all entries: workgroup g sums
+// columns g, g + JAC_NORM_BLOCKS, ... (grid (JAC_NORM_BLOCKS, B)); the second
+// kernel adds the partials in a fixed order (grid B).
 __global__ __launch_bounds__(256) void jacobi_norms_kernel(const JacDesc *__restrict__ jd) {
-  const JacDesc J = jd[blockIdx.x];
+  const JacDesc J = jd[blockIdx.y];
   __shared__ double sh[4];
   double off = 0.0, fro = 0.0;
   const auto *A = gptr((const double *)J.A);
-  for (int c = 0; c < J.ne; ++c) {
+  for (int c = blockIdx.x; c < J.ne; c += JAC_NORM_BLOCKS) {
     for (int i = threadIdx.x; i < J.ne; i += 256) {
       const double a = A[(size_t)c * J.ne + i];
       fro += a * a;
@@ -174,10 +177,21 @@ __global__ __launch_bounds__(256) void jacobi_norms_kernel(const JacDesc *__rest
   off = block_sum256(off, sh);
   fro = block_sum256(fro, sh);
   if (threadIdx.x == 0) {
+    J.part[2 * blockIdx.x] = off;
+    J.part[2 * blockIdx.x + 1] = fro;
+  }
+}
+__global__ __launch_bounds__(256) void jacobi_norms_sum_kernel(const JacDesc *__restrict__ jd) {
+  const JacDesc J = jd[blockIdx.x];
+  __shared__ double sh[4];
+  const double off = block_sum256(J.part[2 * threadIdx.x], sh);
+  const double fro = block_sum256(J.part[2 * threadIdx.x + 1], sh);
+  if (threadIdx.x == 0) {
     J.norms[0] = off;
     J.norms[1] = fro;
   }
 }
+static_assert(JAC_NORM_BLOCKS == 256, "jacobi_norms_sum_kernel adds one partial per thread");
 
 // f_k = 1 / lambda_k for |lambda_k| > rtol * max|lambda|, else 0; the rank.
 // One workgroup per matrix (grid B).
@@ -268,7 +282,8 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
   for (int b = 0; b < B; ++b) {
     const int ne = n[b] + (n[b] & 1);
     off[b] = total;
-    total += 2 * a256(sizeof(double) * (size_t)ne * ne) + a256(sizeof(double) * 5 * ne) + a256(sizeof(double) * 4);
+    total += 2 * a256(sizeof(double) * (size_t)ne * ne) + a256(sizeof(double) * (5 * ne + 2 * JAC_NORM_BLOCKS)) +
+             a256(sizeof(double) * 4);
     ne_max = std::max(ne_max, ne);
   }
   if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
@@ -283,7 +298,8 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
     base += a256(sizeof(double) * (size_t)ne * ne);
     J.side = (double *)base;
     J.f = J.side + 4 * ne;
-    base += a256(sizeof(double) * 5 * ne);
+    J.part = J.f + ne;
+    base += a256(sizeof(double) * (5 * ne + 2 * JAC_NORM_BLOCKS));
     J.norms = (double *)base;
   }
   const JacDesc *dall = (const JacDesc *)ctx.upload(hd.data(), sizeof(JacDesc) * B);
@@ -311,7 +327,10 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
       });
     }
     ctx.launch(INLA_K_SOLVE, 0.0, 8.0 * ne_act * ne_act * nb, [&] {
-      hipLaunchKernelGGL(jacobi_norms_kernel, dim3(nb), dim3(256), 0, ctx.stream, da);
+      hipLaunchKernelGGL(jacobi_norms_kernel, dim3(JAC_NORM_BLOCKS, nb), dim3(256), 0, ctx.stream, da);
+    });
+    ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+      hipLaunchKernelGGL(jacobi_norms_sum_kernel, dim3(nb), dim3(256), 0, ctx.stream, da);
     });
     for (int q = 0; q < nb; ++q)
       if (hipMemcpyAsync(hn.data() + 4 * q, ha[q].norms, sizeof(double) * 2, hipMemcpyDeviceToHost, ctx.stream) !=
