@@ -404,6 +404,19 @@ int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *
 int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
                        double *const *x, const inla_opts *opts, inla_result *res);
 
+/* inla_woodbury_var: marginal variances diag(Sigma*) of the Woodbury covariance
+ * (Eq. (woodeqn)) at given modes, models and theta as for inla_woodbury_eval:
+ * var_i = Q^+_ii - ||L^{-1} S Q^+ e_i||^2 with S = diag(sqrt(W(x_mode))) and
+ * M = I + S Q^+ S = L L^T, factored in FP64 with the n border rows Q^+ S (about
+ * 4/3 n^3 flops and 2 n_pad^2 doubles of workspace per theta).
+ *   x_mode  host array of B device pointers [n] (read)
+ *   var     host array of B device pointers [n] (written)
+ *   info    host [B]: 0 or the leading minor of M that is not positive definite
+ * Returns -i for an invalid i-th argument (a model not of the form above as -3,
+ * a non-finite likelihood parameter as -4), INLA_ERR_NOMEM or INLA_ERR_HIP. */
+int inla_woodbury_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                      const double *const *x_mode, double *const *var, int32_t *info);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */
 enum {

@@ -37,7 +37,7 @@ EXPORTS = [
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
     "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats",
     "inla_vb_mean", "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
-    "inla_pinv", "inla_woodbury_eval",
+    "inla_pinv", "inla_woodbury_eval", "inla_woodbury_var",
 ]
 # Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
 # reports their times; the fastest is then timed with lookahead as well.
@@ -101,6 +101,7 @@ def load_library(path: str = LIBPATH):
         f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
     lib.inla_pinv.argtypes = [P, i32, pi32, C.POINTER(P), pi32, C.POINTER(P), pi32, C.c_double, pi32, pi32, pi32]
     lib.inla_marginal_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
+    lib.inla_woodbury_var.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(P), pi32]
     lib.inla_profile.argtypes = [P, i32]
     lib.inla_profile_get.argtypes = [P, i32, i32, C.POINTER(KStats)]
     pf = C.c_void_p
@@ -281,12 +282,7 @@ class Library:
         Q_prior(theta_b)^+.  Returns (results, modes)."""
         B = len(dmodels)
         th = np.ascontiguousarray(np.asarray(lik_params, dtype=np.float64).reshape(B, 1))
-        structs = []
-        for dm, P in zip(dmodels, qpinv):
-            s = Model.from_buffer_copy(dm.struct)
-            s.prior, s.k, s.C, s.e, s.Qprior, s.ldq = 3, 0, None, None, P.data_ptr(), int(P.shape[0])
-            structs.append(s)
-        models = (Model * B)(*structs)
+        models = self._pinv_models(dmodels, qpinv)
         if x is None:
             x = [self.torch.zeros(m.n, dtype=self.torch.float64, device="cuda") for m in dmodels]
         ptrs = (C.c_void_p * B)(*[t.data_ptr() for t in x])
@@ -296,6 +292,28 @@ class Library:
                                          C.byref(opts), res)
         self._check(rc, "inla_woodbury_eval")
         return [r.asdict() for r in res], x
+
+    def _pinv_models(self, dmodels, qpinv):
+        structs = []
+        for dm, P in zip(dmodels, qpinv):
+            s = Model.from_buffer_copy(dm.struct)
+            s.prior, s.k, s.C, s.e, s.Qprior, s.ldq = 3, 0, None, None, P.data_ptr(), int(P.shape[0])
+            structs.append(s)
+        return (Model * len(structs))(*structs)
+
+    def woodbury_var(self, dmodels, lik_params, qpinv, x_modes):
+        """diag(Sigma*) of the Woodbury covariance at the given device modes
+        (inla_woodbury_var).  Returns (list of device tensors, info)."""
+        B = len(dmodels)
+        th = np.ascontiguousarray(np.asarray(lik_params, dtype=np.float64).reshape(B, 1))
+        models = self._pinv_models(dmodels, qpinv)
+        var = [self.torch.empty(m.n, dtype=self.torch.float64, device="cuda") for m in dmodels]
+        xp = (C.c_void_p * B)(*[t.data_ptr() for t in x_modes])
+        vp = (C.c_void_p * B)(*[t.data_ptr() for t in var])
+        info = (C.c_int32 * B)()
+        rc = self.lib.inla_woodbury_var(self.h, B, models, th.ctypes.data_as(C.POINTER(C.c_double)), 1, xp, vp, info)
+        self._check(rc, "inla_woodbury_var")
+        return var, np.array(info[:], dtype=np.int32)
 
     def marginal_var(self, dmodels, theta, x_modes):
         B, theta, models, x_modes, xptrs = self._common(dmodels, theta, x_modes)

@@ -22,7 +22,8 @@
 //     x_new = Sigma* b = Q^+ (b - S M^{-1} S Q^+ b),   b = g + W x,
 // the forward substitution L^{-1} r (r = S Q^+ b) comes out of the
 // factorisation as its border row, and x_new^T Q_prior x_new = z^T x_new with
-// z = b - S M^{-1} r, because Q^+ Q_prior Q^+ = Q^+.
+// z = b - S M^{-1} r, because Q^+ Q_prior Q^+ = Q^+.  The marginal variances
+// diag(Sigma*) factor M once more with the n border rows Q^+ S.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -386,6 +387,7 @@ struct WbDesc {
   const double *Pq;    // Q^+ (caller's), full symmetric, column-major, ld ldq
   const double *y, *E;
   double *xext;        // caller's start / output vector [n]
+  double *vext;        // caller's variance output [n] (inla_woodbury_var)
   double *M;           // factor storage: ldm = n_pad + PADN rows (row n_pad: border), n_pad columns
   double *linv;
   double *x, *b, *sw, *u, *s, *t, *w;   // [n_pad]
@@ -464,21 +466,42 @@ __global__ __launch_bounds__(256) void wb_symv_reduce_kernel(const WbDesc *__res
   if (border) D.M[(size_t)i * D.ldm + D.n_pad] = D.sw[i] * s;
 }
 
-// M = I + diag(sw) Q^+ diag(sw), lower triangle, identity on the padding, zero
-// border rows below row n_pad (row n_pad is written by the reduction).  Grid
-// (ldm / 256, n_pad, B).
-__global__ __launch_bounds__(256) void wb_assemble_kernel(const WbDesc *__restrict__ wd) {
+// M = I + diag(sw) Q^+ diag(sw), lower triangle, identity on the padding.
+// Border rows (i >= n_pad): Newton (var = 0): zero below row n_pad, whose r is
+// written by the reduction; variances (var = 1): row n_pad + a holds
+// (Q^+ S)_{a, j} = Q^+_{a j} sw_j for a < n, zero beyond.  Grid (ldm / 256,
+// n_pad, B).
+__global__ __launch_bounds__(256) void wb_assemble_kernel(const WbDesc *__restrict__ wd, int var) {
   const WbDesc D = wd[blockIdx.z];
   const int j = blockIdx.y;
   if (j >= D.n_pad) return;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= D.ldm || i < j || i == D.n_pad) return;
+  if (i >= D.ldm || i < j || (!var && i == D.n_pad)) return;
   double v = 0.0;
   if (i < D.n_pad) {
     v = i == j ? 1.0 : 0.0;
     if (i < D.n && j < D.n) v += D.sw[i] * D.Pq[(size_t)j * D.ldq + i] * D.sw[j];
+  } else if (var) {
+    const int a = i - D.n_pad;
+    if (a < D.n && j < D.n) v = D.Pq[(size_t)j * D.ldq + a] * D.sw[j];
   }
   D.M[(size_t)j * D.ldm + i] = v;
+}
+
+// var_a = Q^+_aa - ||row a of the factored border||^2 = diag(Sigma*)_a, written
+// to the caller's vector.  Grid (n_pad / 256, B); the column reads of the
+// border are coalesced across the rows.
+__global__ __launch_bounds__(256) void wb_var_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.y];
+  const int a = blockIdx.x * 256 + threadIdx.x;
+  if (a >= D.n) return;
+  const auto *G = gptr((const double *)D.M) + D.n_pad + a;
+  double s = 0.0;
+  for (int j = 0; j < D.n; ++j) {
+    const double g = G[(size_t)j * D.ldm];
+    s = fma(g, g, s);
+  }
+  D.vext[a] = D.Pq[(size_t)a * D.ldq + a] - s;
 }
 
 // s = L^{-1} r from the factored border row.  Grid (n_pad / 256, B).
@@ -648,7 +671,7 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
       hipLaunchKernelGGL(wb_symv_reduce_kernel, gv, dim3(256), 0, ctx.stream, da, WV_U, 1);
     });
     ctx.launch(INLA_K_ASSEMBLE, 0.0, qbytes, [&] {
-      hipLaunchKernelGGL(wb_assemble_kernel, dim3((ldm + 255) / 256, np, na), dim3(256), 0, ctx.stream, da);
+      hipLaunchKernelGGL(wb_assemble_kernel, dim3((ldm + 255) / 256, np, na), dim3(256), 0, ctx.stream, da, 0);
     });
     int rc = factor_batch(ctx, fs, INLA_PREC_FP64);
     if (rc) return rc;
@@ -716,6 +739,72 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
   return ctx.check();
 }
 
+// Marginal variances diag(Sigma*) at given modes: M = I + S Q^+ S with W at the
+// mode, factored with the n border rows Q^+ S, which come out as (L^{-1} S Q^+)^T.
+static int woodbury_var(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
+                        const double *const *x, double *const *var, int *info) {
+  std::vector<WbDesc> hd(B);
+  std::vector<size_t> off(B);
+  size_t total = a256(sizeof(int) * B);
+  int np_max = 0, ldm_max = 0;
+  for (int b = 0; b < B; ++b) {
+    const int np = round_up(models[b].n, PADN), ldm = 2 * np;
+    off[b] = total;
+    total += a256(sizeof(double) * (size_t)ldm * np) + a256(sizeof(double) * (size_t)np * NBI) +
+             a256(sizeof(double) * (size_t)3 * np);
+    np_max = std::max(np_max, np);
+    ldm_max = std::max(ldm_max, ldm);
+  }
+  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  int *dinfo = (int *)ctx.ws;
+  std::vector<HostFactor> fs;
+  for (int b = 0; b < B; ++b) {
+    const inla_model &m = models[b];
+    WbDesc &D = hd[b];
+    D = WbDesc{};
+    D.Pq = m.Qprior; D.ldq = m.ldq; D.y = m.y; D.E = m.E; D.xext = (double *)x[b]; D.vext = var[b];
+    D.n = m.n; D.n_pad = round_up(m.n, PADN); D.ldm = 2 * D.n_pad; D.lik = m.lik;
+    const double lp = theta[(size_t)b * ldtheta];
+    D.lpar = m.lik == INLA_LIK_GAUSSIAN ? std::exp(lp) : lp;
+    char *base = ctx.ws + off[b];
+    D.M = (double *)base;
+    base += a256(sizeof(double) * (size_t)D.ldm * D.n_pad);
+    D.linv = (double *)base;
+    base += a256(sizeof(double) * (size_t)D.n_pad * NBI);
+    double *v = (double *)base;
+    D.x = v; D.b = v + D.n_pad; D.sw = v + 2 * D.n_pad;
+    D.info = dinfo + b;
+    HostFactor h{};
+    h.d.A = D.M; h.d.linv = D.linv; h.d.info = D.info; h.d.ld = D.ldm; h.d.nf = D.n_pad;
+    h.d.nrows = D.ldm; h.d.ncols = D.n_pad; h.d.id_row0 = std::numeric_limits<int>::max();
+    h.n_real = D.n; h.kb_real = D.n; h.ks_real = 0;
+    fs.push_back(h);
+  }
+  const WbDesc *dd = (const WbDesc *)ctx.upload(hd.data(), sizeof(WbDesc) * B);
+  if (!dd) return INLA_ERR_NOMEM;
+  const dim3 gv((np_max + 255) / 256, B);
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_start_kernel, gv, dim3(256), 0, ctx.stream, dd, 1);
+  });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_lik_kernel, gv, dim3(256), 0, ctx.stream, dd);
+  });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_assemble_kernel, dim3((ldm_max + 255) / 256, np_max, B), dim3(256), 0, ctx.stream, dd, 1);
+  });
+  int rc = factor_batch(ctx, fs, INLA_PREC_FP64);
+  if (rc) return rc;
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_var_kernel, gv, dim3(256), 0, ctx.stream, dd);
+  });
+  std::vector<int> hinfo(B);
+  if (hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * B, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess)
+    return INLA_ERR_HIP;
+  if (hipStreamSynchronize(ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+  for (int b = 0; b < B; ++b) info[b] = hinfo[b];
+  return ctx.check();
+}
+
 }  // namespace inla
 
 extern "C" {
@@ -743,6 +832,29 @@ int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *
   }
   if (!(rtol < 1.0)) return -8;
   return pinv_batch(*handle_ctx(h), B, n, Q, ldq, Qpinv, ldp, rtol, rank, sweeps, info);
+}
+
+int inla_woodbury_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
+                      const double *const *x_mode, double *const *var, int32_t *info) {
+  using namespace inla;
+  if (!h) return -1;
+  if (B < 0) return -2;
+  if (B == 0) return INLA_OK;
+  if (!models) return -3;
+  if (!theta || ldtheta < 1) return -4;
+  if (!x_mode) return -6;
+  if (!var) return -7;
+  if (!info) return -8;
+  for (int b = 0; b < B; ++b) {
+    const inla_model &m = models[b];
+    if (m.prior != INLA_PRIOR_PINV || m.n < 1 || m.k != 0 || m.m != 0 || !m.Qprior || m.ldq < m.n || !m.y ||
+        (m.lik != INLA_LIK_GAUSSIAN && m.lik != INLA_LIK_POISSON))
+      return -3;
+    if (!std::isfinite(theta[(size_t)b * ldtheta])) return -4;
+    if (!x_mode[b]) return -6;
+    if (!var[b]) return -7;
+  }
+  return woodbury_var(*handle_ctx(h), B, models, theta, ldtheta, x_mode, var, info);
 }
 
 int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,

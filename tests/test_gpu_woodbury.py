@@ -1,4 +1,5 @@
-"""GPU parity of the Moore-Penrose route (inla_pinv, inla_woodbury_eval) against
+"""GPU parity of the Moore-Penrose route (inla_pinv, inla_woodbury_eval,
+inla_woodbury_var) against
 the CPU reference (``oracle/woodbury_oracle.py``) on the same seeded intrinsic
 RW1 x Besag models, and against the GPU kriging route on the equivalent proper
 prior with sum-to-zero constraints.
@@ -172,3 +173,41 @@ def test_woodbury_n3000(lib):
     cols = np.random.default_rng(0).choice(3000, 16, replace=False)
     Pg = P1[0][:, cols].cpu().numpy()
     assert np.max(np.abs(Pg - Pr[:, cols])) <= 1e-11 * np.max(np.abs(Pr))
+
+
+@pytest.mark.parametrize("lik", ["poisson", "gaussian"])
+def test_woodbury_marginal_variances(lib, lik):
+    """diag(Sigma*) at the mode against the reference covariance (Eq. (woodeqn)
+    as printed) and against the GPU kriging route's marginal variances on the
+    same posterior.  The variance is Q^+_ii minus a term of the same size, so
+    the bound is relative to max_i Q^+_ii (1e-10; each term is accurate to a few
+    n u)."""
+    from paper_2311_08050_amd.binding import DeviceModel
+    from tests.test_oracle_woodbury import known_null_basis
+    shapes = [(13, 7), (24, 10)]
+    models = [synth.rw1_besag(ns, nt, seed=80 + i, lik=lik) for i, (ns, nt) in enumerate(shapes)]
+    thetas = [synth.rw1_besag_theta0(nt, lik) + np.array([0.2, 0.03]) for _, nt in shapes]
+    Qp = [WB.prior_precision(m, th) for m, th in zip(models, thetas)]
+    P, _, _, _ = lib.pinv([dev(q) for q in Qp])
+    dms = [DeviceModel(m) for m in models]
+    lp = [th[1] for th in thetas]
+    res, xs = lib.woodbury_eval(dms, lp, P)
+    var, info = lib.woodbury_var(dms, lp, P, xs)
+    assert np.all(info == 0)
+    for i, ((ns, nt), m, th, v) in enumerate(zip(shapes, models, thetas, var)):
+        ref = WB.laplace_eval(m, th)
+        vr = np.diag(ref["Sigma"])
+        vg = v.cpu().numpy()
+        scale = np.max(np.diag(P[i].cpu().numpy()))
+        say(f"{lik} var n={m['n']}: max |GPU - reference| {np.max(np.abs(vg - vr)):.2e} (Q+ diag up to {scale:.2f}, "
+            f"variances {vr.min():.4f} .. {vr.max():.4f})")
+        assert np.all(vg > 0)
+        assert np.max(np.abs(vg - vr)) <= 1e-10 * scale
+        # the kriging route on Q + N N^T with the sum-to-zero constraints
+        N = known_null_basis(ns, nt)
+        C = null_rows(ns, nt)
+        km = {"n": m["n"], "lik": lik, "prior": "dense", "y": m["y"], "E": m["E"], "A": None, "C": C,
+              "e": np.zeros(C.shape[0]), "Qprior": Qp[i] + N @ N.T}
+        vk, kinfo = lib.marginal_var([DeviceModel(km)], np.array([[th[1]]]), [xs[i]])
+        assert np.all(kinfo == 0)
+        assert np.max(np.abs(vg - vk[0].cpu().numpy())) <= 1e-10 * scale
