@@ -288,6 +288,14 @@ def run_moore_penrose(lib, binding, synth, B=9):
     rw, _ = lib.woodbury_eval([dm] * B, thetas[:, 1], Ps)
     torch.cuda.synchronize()
     t_wood = time.perf_counter() - t0
+    xw = [torch.zeros(m["n"], dtype=torch.float64, device="cuda") for _ in range(B)]
+    lib.woodbury_eval([dm] * B, thetas[:, 1], Ps, x=xw)
+    lib.woodbury_var([dm], [thetas[0][1]], Ps[:1], xw[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, vinfo = lib.woodbury_var([dm] * B, thetas[:, 1], Ps, xw)
+    torch.cuda.synchronize()
+    t_var = time.perf_counter() - t0
     C = synth.sum_to_zero_rows(100, 30)
     kms = [binding.DeviceModel({"n": m["n"], "lik": "poisson", "prior": "dense", "y": m["y"], "E": m["E"], "A": None,
                                 "C": C, "e": np.zeros(C.shape[0]),
@@ -303,12 +311,13 @@ def run_moore_penrose(lib, binding, synth, B=9):
                        f"batch {B} theta ~ N(theta0, 0.3^2 I)",
            "pinv_s": t_pinv, "pinv_sweeps": int(sweeps[0]), "pinv_rank": int(rank[0]), "pinv_info": int(info[0]),
            "woodbury_theta_evals_per_s": B / t_wood, "kriging_theta_evals_per_s": B / t_krig,
+           "woodbury_var_evals_per_s": B / t_var, "woodbury_var_info": [int(v) for v in vinfo],
            "woodbury_iters_mean": float(np.mean([r["iters"] for r in rw])),
            "kriging_iters_mean": float(np.mean([r["iters"] for r in rk])),
            "max_rel_objective_diff": d, "info": [r["info"] for r in rw] + [r["info"] for r in rk],
            "precision": "fp64"}
     log(f"Moore-Penrose n=3000: pinv {t_pinv:.2f} s ({int(sweeps[0])} sweeps); Woodbury {B / t_wood:.1f} vs "
-        f"kriging {B / t_krig:.1f} theta-evals/s; objectives agree to {d:.1e}")
+        f"kriging {B / t_krig:.1f} theta-evals/s; objectives agree to {d:.1e}; variances {B / t_var:.1f}/s")
     return res
 
 
