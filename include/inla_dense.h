@@ -380,35 +380,44 @@ int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_po
 int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *Q, const int32_t *ldq,
               double *const *Qpinv, const int32_t *ldp, double rtol, int32_t *rank, int32_t *sweeps, int32_t *info);
 
-/* inla_woodbury_eval: log pi~(y | theta) with an intrinsic prior, A = I.  Each
- * model has prior INLA_PRIOR_PINV, k = 0 and m = 0; model.Qprior is the device
+/* inla_woodbury_eval: log pi~(y | theta) with an intrinsic prior.  Each model
+ * has prior INLA_PRIOR_PINV and k = 0; model.Qprior is the device
  * pseudo-inverse Q_prior(theta_b)^+ (full symmetric, ld model.ldq; the caller
  * scales it with theta), and theta row b holds the likelihood parameter only:
  * (lik), lik = log sigma^2 (Gaussian) or beta0 (Poisson).  Newton in covariance
  * form: b = g + W x, x_new = Sigma* b with Sigma* = Q^+ - Q^+ S M^{-1} S Q^+,
- * S = diag(sqrt(W)), M = I + S Q^+ S factored by the blocked Cholesky (FP64);
- * the stopping rule is that of inla_laplace_eval (Gaussian: one step).  The
- * objective is the Laplace approximation on range(Q_prior):
+ * S = diag(sqrt(W)), M = I + S Q^+ S factored by the blocked Cholesky (FP64).
+ * A general design matrix (model.m > 0, CSR as for inla_laplace_eval, checked
+ * on the host) runs the same iteration on eta = A x with Q^+ replaced by
+ * K = A Q^+ A^T (M is m x m) and maps back with x = Q^+ A^T z; the library
+ * forms Q^+ A^T and K once per call (n m + m^2 doubles per theta).  The
+ * stopping rule is that of inla_laplace_eval (Gaussian: one step), plus: a
+ * step below 1e-7 of max(1, |x|_inf) that is larger than half the previous one
+ * ends the iteration (the covariance form's rounding floor, which the condition
+ * of M sets, can lie above tol).  The objective is the Laplace approximation on
+ * range(Q_prior):
  *   objective = loglik - 1/2 x*^T Q_prior x* - 1/2 log|M|,
  * which equals 1/2 log pdet(Q_prior) + 1/2 log pdet(Sigma*) - 1/2 x*^T Q_prior x*
  * + loglik (pdet: product of the non-zero eigenvalues), and the kriging
  * objective with constraints spanning null(Q_prior).  M comes from the last
- * Newton step.
+ * Newton step.  For A = I, x*^T Q_prior x* = z^T x*; for a general A, z^T A x*.
  *   x     host array of B device pointers [n]: start (opts->start = 1) and the mode
  *   opts  as for inla_laplace_eval; prec must be INLA_PREC_FP64
  *   res   host [B]: objective, xqx = x*^T Q_prior x*, loglik, logdet_qstar =
  *         log|M| (= log pdet(Q*) - log pdet(Q_prior) on range(Q_prior)), step,
  *         iters, info; the prior and constraint log-det fields are 0.
- * Returns -i for an invalid i-th argument (a model that is not of this form as
- * -3), INLA_ERR_UNSUPPORTED for another precision, INLA_ERR_NOMEM, INLA_ERR_HIP. */
+ * Returns -i for an invalid i-th argument (a model that is not of this form, or
+ * a malformed CSR, as -3), INLA_ERR_UNSUPPORTED for another precision,
+ * INLA_ERR_NOMEM, INLA_ERR_HIP. */
 int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
                        double *const *x, const inla_opts *opts, inla_result *res);
 
 /* inla_woodbury_var: marginal variances diag(Sigma*) of the Woodbury covariance
  * (Eq. (woodeqn)) at given modes, models and theta as for inla_woodbury_eval:
- * var_i = Q^+_ii - ||L^{-1} S Q^+ e_i||^2 with S = diag(sqrt(W(x_mode))) and
- * M = I + S Q^+ S = L L^T, factored in FP64 with the n border rows Q^+ S (about
- * 4/3 n^3 flops and 2 n_pad^2 doubles of workspace per theta).
+ * var_i = Q^+_ii - ||L^{-1} S A Q^+ e_i||^2 with S = diag(sqrt(W(A x_mode))) and
+ * M = I + S A Q^+ A^T S = L L^T (A = I for m = 0), factored in FP64 with the n
+ * border rows Q^+ A^T S (about n_o^3 / 3 + n n_o^2 flops, n_o = m or n, and
+ * (n_o + n) n_o doubles of factor workspace per theta).
  *   x_mode  host array of B device pointers [n] (read)
  *   var     host array of B device pointers [n] (written)
  *   info    host [B]: 0 or the leading minor of M that is not positive definite

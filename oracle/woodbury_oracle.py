@@ -32,7 +32,14 @@ Model dict (as in ``inla_oracle``) with prior kind
                  region graph ``edges`` (pairs (i, j), i != j) on n_s regions,
                  latent index t*n_s + s;
     'intrinsic': Q_prior = tau * R with R = model['R'] given;
-theta = (log tau, lik), lik = log sigma^2 (Gaussian) or beta0 (Poisson).
+    'type4':     the simulation study's model (section "Simulation study"),
+                 latent [mu, beta_t, alpha_time (n_t), alpha_space (n_s), zeta]
+                 with Q_prior = blockdiag(c, c, tau_t R2_t, tau_s R_s,
+                 tau_st R2_t kron R_s), c = model['fixed_precision'], R2_t the
+                 second-order random walk structure, R_s the Besag structure,
+                 and the design matrix model['A'];
+theta = (log tau, lik) or, for 'type4', (log tau_t, log tau_s, log tau_st, lik);
+lik = log sigma^2 (Gaussian) or beta0 (Poisson).
 """
 from __future__ import annotations
 
@@ -64,6 +71,19 @@ def besag_structure(n_s, edges):
     return R
 
 
+def rw2_structure(n_t):
+    """Second-order random walk structure D^T D, D the (n_t - 2) x n_t matrix of
+    second differences (rank n_t - 2; constants and linear trends are free)."""
+    D = np.zeros((max(n_t - 2, 0), n_t))
+    for i in range(n_t - 2):
+        D[i, i], D[i, i + 1], D[i, i + 2] = 1.0, -2.0, 1.0
+    return D.T @ D
+
+
+def n_prior_params(model):
+    return 3 if model["prior"] == "type4" else 1
+
+
 def structure(model):
     """The unscaled structure matrix R (Q_prior = tau R)."""
     if model["prior"] == "rw1_besag":
@@ -74,7 +94,22 @@ def structure(model):
 
 
 def prior_precision(model, theta):
-    return math.exp(float(theta[0])) * structure(model)
+    if model["prior"] != "type4":
+        return math.exp(float(theta[0])) * structure(model)
+    n_s, n_t = model["n_s"], model["n_t"]
+    R2 = rw2_structure(n_t)
+    Rs = besag_structure(n_s, model["edges"])
+    blocks = [np.array([[model["fixed_precision"]]]), np.array([[model["fixed_precision"]]]),
+              math.exp(float(theta[0])) * R2, math.exp(float(theta[1])) * Rs,
+              math.exp(float(theta[2])) * np.kron(R2, Rs)]
+    n = sum(b.shape[0] for b in blocks)
+    Q = np.zeros((n, n))
+    o = 0
+    for b in blocks:
+        k = b.shape[0]
+        Q[o:o + k, o:o + k] = b
+        o += k
+    return Q
 
 
 def lik_view(model):
@@ -85,9 +120,9 @@ def lik_view(model):
     return v
 
 
-def theta_lik(theta):
+def theta_lik(model, theta):
     """(lik,) -- the theta the likelihood helpers take for a 'dense' view."""
-    return np.asarray(theta, dtype=np.float64)[1:]
+    return np.asarray(theta, dtype=np.float64)[n_prior_params(model):]
 
 
 # --------------------------------------------------------------------------- #
@@ -122,7 +157,7 @@ def pseudo_logdet(M, rank):
 # Newton in covariance form and the objective                                  #
 # --------------------------------------------------------------------------- #
 def _lik(model, theta, x):
-    view, th = lik_view(model), theta_lik(theta)
+    view, th = lik_view(model), theta_lik(model, theta)
     eta = O.linear_predictor(view, th, x)
     g, W, ll = O.lik_terms(view, th, eta)
     return view, th, g, W, ll
@@ -133,11 +168,21 @@ def q_like(model, W):
     return np.diag(W) if A is None else A.T @ (W[:, None] * A)
 
 
+# The covariance form loses accuracy in proportion to the condition of
+# I + Q_l Q^+ (weak priors on fixed effects make Q^+ large), so its iterates
+# settle on a rounding floor that can lie above NEWTON_TOL.  A step below
+# FLOOR_TOL relative that is no longer at most half the previous one ends the
+# iteration there.
+FLOOR_TOL = 1e-7
+
+
 def newton_mode(model, theta, Qpinv, x0=None, tol=NEWTON_TOL, max_iter=NEWTON_MAX_ITER):
-    """x_new = Sigma*(x) b(x) until ||x_new - x||_inf <= tol * max(1, ||x_new||_inf).
+    """x_new = Sigma*(x) b(x) until ||x_new - x||_inf <= tol * max(1, ||x_new||_inf),
+    or until the step stops contracting below FLOOR_TOL relative.
     Returns (x, iters, info)."""
     n = model["n"]
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
+    prev = math.inf
     for it in range(1, max_iter + 1):
         view, th, g, W, _ = _lik(model, theta, x)
         b = O.rhs(view, g, W, x)
@@ -149,6 +194,9 @@ def newton_mode(model, theta, Qpinv, x0=None, tol=NEWTON_TOL, max_iter=NEWTON_MA
         x = x_new
         if model["lik"] == "gaussian" or step <= tol * scale:
             return x, it, O.INFO_OK
+        if step <= FLOOR_TOL * scale and step > 0.5 * prev:
+            return x, it, O.INFO_OK
+        prev = step
     return x, max_iter, O.INFO_NEWTON_MAXIT
 
 

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libinla_dense.so")
 
 LIK = {"gaussian": 0, "poisson": 1}
-PRIOR = {"dense": 0, "expcov": 1, "kron": 2, "pinv": 3, "rw1_besag": 3, "intrinsic": 3}
+PRIOR = {"dense": 0, "expcov": 1, "kron": 2, "pinv": 3, "rw1_besag": 3, "intrinsic": 3, "type4": 3}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 N_PRIOR_PARAMS = {"dense": 0, "expcov": 2, "kron": 3}
 

@@ -3,7 +3,7 @@
 // matrices": the pseudo-inverse Q^+ of the prior precision by a cyclic two-sided
 // Jacobi eigen-decomposition (one per evaluation where the prior changes), and
 // the Laplace evaluation with the posterior covariance in the Woodbury form of
-// Eq. (woodeqn), A = I.
+// Eq. (woodeqn), for A = I or a general sparse design matrix.
 //
 // Jacobi: the pairs of a round follow the round-robin (circle) schedule, so the
 // n/2 rotations of a round are disjoint and one launch applies all of them: the
@@ -379,35 +379,87 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
 }
 
 // ------------------------------------------------------------------ Woodbury Newton
-constexpr int WB_CH = 32;   // column chunks of the Q^+ products
+// A general design matrix A (m observations, eta = offset + A x) reduces to the
+// A = I iteration in observation space: eta has the prior covariance
+// K = A Q^+ A^T, the Newton step of eta is the A = I step with Q^+ replaced by
+// K (b = g + W eta, M = I + S K S), and the latent step is x_new = HT z with
+// HT = Q^+ A^T and the same z = b - S t, so that x_new^T Q_prior x_new =
+// z^T (A x_new) and log|M| = log|I + Q^+ A^T W A|.  HT and K are formed once per
+// call from the CSR rows of A.
+constexpr int WB_CH = 32;   // column chunks of the matrix-vector products
+// The covariance form settles on a rounding floor set by the condition of M
+// (weak priors make Q^+ large); below this relative step, a step that is no
+// longer at most half the previous one ends the iteration there.
+constexpr double WB_FLOOR_TOL = 1e-7;
 enum { WR_STEP = 0, WR_SCALE = 1, WR_ZTX = 2, WR_LOGDET = 3, WR_LOGLIK = 4, WR_NONFINITE = 5, WR_COUNT = 8 };
 enum { WV_X = 0, WV_B = 1, WV_U = 2, WV_T = 3, WV_W = 4 };
 
 struct WbDesc {
-  const double *Pq;    // Q^+ (caller's), full symmetric, column-major, ld ldq
+  const double *Pq;    // observation-space covariance: Q^+ (A = I, caller's) or K (workspace); ld ldq
   const double *y, *E;
-  double *xext;        // caller's start / output vector [n]
-  double *vext;        // caller's variance output [n] (inla_woodbury_var)
-  double *M;           // factor storage: ldm = n_pad + PADN rows (row n_pad: border), n_pad columns
+  double *xext;        // caller's start / mode [n_lat]
+  double *vext;        // caller's variances [n_lat] (inla_woodbury_var)
+  double *M;           // factor storage: ldm rows (border rows from n_pad), n_pad columns
   double *linv;
-  double *x, *b, *sw, *u, *s, *t, *w;   // [n_pad]
-  double *part;        // [WB_CH][n_pad]
+  double *x, *b, *sw, *u, *s, *t, *w, *z;   // observation-space vectors [n_pad]; x holds A x
+  double *part;        // [WB_CH][max(n_pad, n_lat_pad)]
   double *res;         // [WR_COUNT]
   int *info;
+  const double *Plat;  // caller's Q^+ (latent space), ld ldlat
+  double *HT;          // Q^+ A^T: n_lat_pad x n, ld ldh (general A only)
+  double *xl;          // latent iterate [n_lat_pad] (general A only)
+  const int *rp, *ci;  // CSR of A (general A only)
+  const double *av;
   double lpar;         // Gaussian: sigma^2; Poisson: beta0
-  int n, n_pad, ldq, ldm, lik, pad_;
+  int n, n_pad, ldq, ldm, lik, general;
+  int n_lat, n_lat_pad, ldlat, ldh;
 };
 
 __device__ __forceinline__ double *wb_vec(const WbDesc &D, int v) {
   return v == WV_X ? D.x : v == WV_B ? D.b : v == WV_U ? D.u : v == WV_T ? D.t : D.w;
 }
 
-// x <- caller's vector (start = 1) or 0, padding zero.  Grid (n_pad / 256, B).
+// HT = Q^+ A^T: column i = sum over row i of A of a_ik Q^+[:, k].  Grid
+// (n_lat_pad / 256, n, B).
+__global__ __launch_bounds__(256) void wb_ht_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.z];
+  const int i = blockIdx.y, j = blockIdx.x * 256 + threadIdx.x;
+  if (!D.general || i >= D.n || j >= D.n_lat_pad) return;
+  double acc = 0.0;
+  if (j < D.n_lat)
+    for (int e = D.rp[i]; e < D.rp[i + 1]; ++e) acc = fma(D.av[e], D.Plat[(size_t)D.ci[e] * D.ldlat + j], acc);
+  D.HT[(size_t)i * D.ldh + j] = acc;
+}
+
+// K = A HT (the observation-space covariance, n x n, ld ldq): column i, row r =
+// sum over row r of A of a_rk HT[k, i].  Grid (n_pad / 256, n_pad, B).
+__global__ __launch_bounds__(256) void wb_k_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.z];
+  const int i = blockIdx.y, r = blockIdx.x * 256 + threadIdx.x;
+  if (!D.general || i >= D.n || r >= D.n) return;
+  const double *col = D.HT + (size_t)i * D.ldh;
+  double acc = 0.0;
+  for (int e = D.rp[r]; e < D.rp[r + 1]; ++e) acc = fma(D.av[e], col[D.ci[e]], acc);
+  ((double *)D.Pq)[(size_t)i * D.ldq + r] = acc;
+}
+
+// Start: A = I: x <- caller's vector (start = 1) or 0.  General A: latent
+// iterate from the caller or 0, and x = A x_latent.  Grid (max(n_pad,
+// n_lat_pad) / 256, B).
 __global__ __launch_bounds__(256) void wb_start_kernel(const WbDesc *__restrict__ wd, int start) {
   const WbDesc D = wd[blockIdx.y];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= D.n_pad) return;
-  D.x[i] = (start && i < D.n) ? D.xext[i] : 0.0;
+  if (!D.general) {
+    if (i < D.n_pad) D.x[i] = (start && i < D.n) ? D.xext[i] : 0.0;
+    return;
+  }
+  if (i < D.n_lat_pad) D.xl[i] = (start && i < D.n_lat) ? D.xext[i] : 0.0;
+  if (i < D.n_pad) {
+    double acc = 0.0;
+    if (start && i < D.n)
+      for (int e = D.rp[i]; e < D.rp[i + 1]; ++e) acc = fma(D.av[e], D.xext[D.ci[e]], acc);
+    D.x[i] = acc;
+  }
 }
 
 // b = g + W x and sw = sqrt(W) at the current iterate (Q_l = diag(W), the
@@ -436,7 +488,7 @@ __global__ __launch_bounds__(256) void wb_lik_kernel(const WbDesc *__restrict__ 
   D.sw[i] = si;
 }
 
-// Partial products of Q^+ v over WB_CH column chunks (v = src, or sw * src).
+// Partial products of Pq v over WB_CH column chunks (v = src, or sw * src).
 // Grid (n_pad / 256, WB_CH, B); the row reads of each column are coalesced.
 __global__ __launch_bounds__(256) void wb_symv_part_kernel(const WbDesc *__restrict__ wd, int src, int scaled) {
   const WbDesc D = wd[blockIdx.z];
@@ -466,11 +518,11 @@ __global__ __launch_bounds__(256) void wb_symv_reduce_kernel(const WbDesc *__res
   if (border) D.M[(size_t)i * D.ldm + D.n_pad] = D.sw[i] * s;
 }
 
-// M = I + diag(sw) Q^+ diag(sw), lower triangle, identity on the padding.
+// M = I + diag(sw) Pq diag(sw), lower triangle, identity on the padding.
 // Border rows (i >= n_pad): Newton (var = 0): zero below row n_pad, whose r is
 // written by the reduction; variances (var = 1): row n_pad + a holds
-// (Q^+ S)_{a, j} = Q^+_{a j} sw_j for a < n, zero beyond.  Grid (ldm / 256,
-// n_pad, B).
+// (Q^+ A^T S)_{a, j} = HT_{a j} sw_j (A = I: Q^+_{a j} sw_j) for a < n_lat,
+// zero beyond.  Grid (ldm / 256, n_pad, B).
 __global__ __launch_bounds__(256) void wb_assemble_kernel(const WbDesc *__restrict__ wd, int var) {
   const WbDesc D = wd[blockIdx.z];
   const int j = blockIdx.y;
@@ -483,25 +535,26 @@ __global__ __launch_bounds__(256) void wb_assemble_kernel(const WbDesc *__restri
     if (i < D.n && j < D.n) v += D.sw[i] * D.Pq[(size_t)j * D.ldq + i] * D.sw[j];
   } else if (var) {
     const int a = i - D.n_pad;
-    if (a < D.n && j < D.n) v = D.Pq[(size_t)j * D.ldq + a] * D.sw[j];
+    if (a < D.n_lat && j < D.n)
+      v = (D.general ? D.HT[(size_t)j * D.ldh + a] : D.Pq[(size_t)j * D.ldq + a]) * D.sw[j];
   }
   D.M[(size_t)j * D.ldm + i] = v;
 }
 
 // var_a = Q^+_aa - ||row a of the factored border||^2 = diag(Sigma*)_a, written
-// to the caller's vector.  Grid (n_pad / 256, B); the column reads of the
+// to the caller's vector.  Grid (n_lat_pad / 256, B); the column reads of the
 // border are coalesced across the rows.
 __global__ __launch_bounds__(256) void wb_var_kernel(const WbDesc *__restrict__ wd) {
   const WbDesc D = wd[blockIdx.y];
   const int a = blockIdx.x * 256 + threadIdx.x;
-  if (a >= D.n) return;
+  if (a >= D.n_lat) return;
   const auto *G = gptr((const double *)D.M) + D.n_pad + a;
   double s = 0.0;
   for (int j = 0; j < D.n; ++j) {
     const double g = G[(size_t)j * D.ldm];
     s = fma(g, g, s);
   }
-  D.vext[a] = D.Pq[(size_t)a * D.ldq + a] - s;
+  D.vext[a] = D.Plat[(size_t)a * D.ldlat + a] - s;
 }
 
 // s = L^{-1} r from the factored border row.  Grid (n_pad / 256, B).
@@ -512,8 +565,8 @@ __global__ __launch_bounds__(256) void wb_border_kernel(const WbDesc *__restrict
   D.s[i] = D.M[(size_t)i * D.ldm + D.n_pad];
 }
 
-// x_new = u - w, the step, max(1, |x_new|_inf), z^T x_new with
-// z = b - sw * t, and log|M| = 2 sum log L_ii.  One workgroup per theta.
+// x_new = u - w, the step, max(1, |x_new|_inf), z = b - sw * t and z^T x_new,
+// and log|M| = 2 sum log L_ii.  One workgroup per theta.
 __global__ __launch_bounds__(256) void wb_update_kernel(const WbDesc *__restrict__ wd) {
   const WbDesc D = wd[blockIdx.x];
   __shared__ double sh[4];
@@ -527,6 +580,7 @@ __global__ __launch_bounds__(256) void wb_update_kernel(const WbDesc *__restrict
     ld += log(D.M[(size_t)i * D.ldm + i]);
     if (!isfinite(xn)) bad = 1.0;
     D.x[i] = xn;
+    D.z[i] = zi;
   }
   step = block_max256(step, sh);
   xmax = block_max256(xmax, sh);
@@ -539,6 +593,49 @@ __global__ __launch_bounds__(256) void wb_update_kernel(const WbDesc *__restrict
     D.res[WR_ZTX] = ztx;
     D.res[WR_LOGDET] = 2.0 * ld;
     D.res[WR_NONFINITE] = bad;
+  }
+}
+
+// General A: partial products HT z over WB_CH column chunks.  Grid
+// (n_lat_pad / 256, WB_CH, B).
+__global__ __launch_bounds__(256) void wb_xl_part_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.z];
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (!D.general || blockIdx.x * 256 >= D.n_lat_pad) return;
+  const int cs = (D.n + WB_CH - 1) / WB_CH;
+  const int i0 = blockIdx.y * cs, i1 = min(D.n, i0 + cs);
+  double acc = 0.0;
+  if (j < D.n_lat) {
+    const auto *row = gptr((const double *)D.HT) + j;
+#pragma unroll 8
+    for (int i = i0; i < i1; ++i) acc = fma(row[(size_t)i * D.ldh], D.z[i], acc);
+  }
+  if (j < D.n_lat_pad) D.part[(size_t)blockIdx.y * D.n_lat_pad + j] = acc;
+}
+
+// General A: x_latent = sum of the partials, and the latent step and scale
+// (these replace the observation-space ones in the stopping rule).  One
+// workgroup per theta.
+__global__ __launch_bounds__(256) void wb_xl_update_kernel(const WbDesc *__restrict__ wd) {
+  const WbDesc D = wd[blockIdx.x];
+  if (!D.general) return;
+  __shared__ double sh[4];
+  double step = 0.0, xmax = 0.0, bad = 0.0;
+  for (int j = threadIdx.x; j < D.n_lat; j += 256) {
+    double xn = 0.0;
+    for (int c = 0; c < WB_CH; ++c) xn += D.part[(size_t)c * D.n_lat_pad + j];
+    step = fmax(step, fabs(xn - D.xl[j]));
+    xmax = fmax(xmax, fabs(xn));
+    if (!isfinite(xn)) bad = 1.0;
+    D.xl[j] = xn;
+  }
+  step = block_max256(step, sh);
+  xmax = block_max256(xmax, sh);
+  bad = block_max256(bad, sh);
+  if (threadIdx.x == 0) {
+    D.res[WR_STEP] = step;
+    D.res[WR_SCALE] = fmax(1.0, xmax);
+    if (bad != 0.0) D.res[WR_NONFINITE] = 1.0;
   }
 }
 
@@ -558,10 +655,136 @@ __global__ __launch_bounds__(256) void wb_final_kernel(const WbDesc *__restrict_
       const double r = yi - xi;
       ll += -0.5 * log(2.0 * M_PI * D.lpar) - r * r / (2.0 * D.lpar);
     }
-    D.xext[i] = xi;
+    if (!D.general) D.xext[i] = xi;
   }
+  if (D.general)
+    for (int j = threadIdx.x; j < D.n_lat; j += 256) D.xext[j] = D.xl[j];
   ll = block_sum256(ll, sh);
   if (threadIdx.x == 0) D.res[WR_LOGLIK] = ll;
+}
+
+static bool wb_model_ok(const inla_model &m) {
+  if (m.prior != INLA_PRIOR_PINV || m.n < 1 || m.k != 0 || !m.Qprior || m.ldq < m.n || !m.y ||
+      (m.lik != INLA_LIK_GAUSSIAN && m.lik != INLA_LIK_POISSON))
+    return false;
+  if (m.m < 0 || (m.m > 0 && (m.nnz < 0 || !m.A_rowptr || (m.nnz > 0 && (!m.A_col || !m.A_val))))) return false;
+  return true;
+}
+
+// The CSR arrays of a general design matrix, copied back once per call: row
+// pointers non-decreasing from 0 to nnz, column indices in [0, n).  The kernels
+// index the caller's Q^+ and start vector through them.
+static bool wb_design_ok(const inla_model &m) {
+  if (m.m == 0) return true;
+  std::vector<int> rp(m.m + 1), ci(std::max(m.nnz, 0));
+  if (hipMemcpy(rp.data(), m.A_rowptr, sizeof(int) * rp.size(), hipMemcpyDeviceToHost) != hipSuccess) return false;
+  if (m.nnz > 0 && hipMemcpy(ci.data(), m.A_col, sizeof(int) * ci.size(), hipMemcpyDeviceToHost) != hipSuccess)
+    return false;
+  if (rp[0] != 0 || rp[m.m] != m.nnz) return false;
+  for (int i = 0; i < m.m; ++i)
+    if (rp[i + 1] < rp[i]) return false;
+  for (int c : ci)
+    if (c < 0 || c >= m.n) return false;
+  return true;
+}
+
+// Workspace of one theta: the factor (Newton: one border block; variances:
+// n_lat_pad border rows), diagonal-block inverses, vectors, partials, and for a
+// general A the matrices K and HT and the latent iterate.
+struct WbLayout {
+  std::vector<size_t> off;
+  size_t total = 0;
+  int np_max = 0, nlp_max = 0, ldm_max = 0, n_max = 0, any_general = 0;
+};
+
+static size_t wb_bytes(const inla_model &m, bool var) {
+  const bool gen = m.m > 0;
+  const int n = gen ? m.m : m.n, np = round_up(n, PADN), nlp = round_up(m.n, PADN);
+  const int ldm = var ? np + nlp : np + PADN;
+  size_t b = a256(sizeof(double) * (size_t)ldm * np) + a256(sizeof(double) * (size_t)np * NBI) +
+             a256(sizeof(double) * 8 * (size_t)np) + a256(sizeof(double) * WB_CH * (size_t)std::max(np, nlp));
+  if (gen)
+    b += a256(sizeof(double) * (size_t)np * np) + a256(sizeof(double) * (size_t)nlp * n) +
+         a256(sizeof(double) * (size_t)nlp);
+  return b;
+}
+
+static WbLayout wb_layout(int B, const inla_model *models, bool var, size_t head) {
+  WbLayout L;
+  L.total = head;
+  L.off.resize(B);
+  for (int b = 0; b < B; ++b) {
+    const inla_model &m = models[b];
+    const bool gen = m.m > 0;
+    const int n = gen ? m.m : m.n, np = round_up(n, PADN), nlp = round_up(m.n, PADN);
+    L.off[b] = L.total;
+    L.total += wb_bytes(m, var);
+    L.np_max = std::max(L.np_max, np);
+    L.nlp_max = std::max(L.nlp_max, nlp);
+    L.ldm_max = std::max(L.ldm_max, var ? np + nlp : np + PADN);
+    L.n_max = std::max(L.n_max, n);
+    L.any_general |= gen;
+  }
+  return L;
+}
+
+static WbDesc wb_desc(const inla_model &m, const double *theta, char *base, bool var, double *xext, double *vext,
+                      double *res, int *info) {
+  WbDesc D{};
+  const bool gen = m.m > 0;
+  D.general = gen;
+  D.n = gen ? m.m : m.n;
+  D.n_pad = round_up(D.n, PADN);
+  D.n_lat = m.n;
+  D.n_lat_pad = round_up(m.n, PADN);
+  D.ldm = var ? D.n_pad + D.n_lat_pad : D.n_pad + PADN;
+  D.y = m.y; D.E = m.E; D.lik = m.lik; D.xext = xext; D.vext = vext; D.res = res; D.info = info;
+  D.Plat = m.Qprior; D.ldlat = m.ldq;
+  const double lp = theta[0];
+  D.lpar = m.lik == INLA_LIK_GAUSSIAN ? std::exp(lp) : lp;
+  D.M = (double *)base;
+  base += a256(sizeof(double) * (size_t)D.ldm * D.n_pad);
+  D.linv = (double *)base;
+  base += a256(sizeof(double) * (size_t)D.n_pad * NBI);
+  double *v = (double *)base;
+  D.x = v; D.b = v + D.n_pad; D.sw = v + 2 * D.n_pad; D.u = v + 3 * D.n_pad; D.s = v + 4 * D.n_pad;
+  D.t = v + 5 * D.n_pad; D.w = v + 6 * D.n_pad; D.z = v + 7 * D.n_pad;
+  base += a256(sizeof(double) * 8 * (size_t)D.n_pad);
+  D.part = (double *)base;
+  base += a256(sizeof(double) * WB_CH * (size_t)std::max(D.n_pad, D.n_lat_pad));
+  if (gen) {
+    D.Pq = (const double *)base;
+    D.ldq = D.n_pad;
+    base += a256(sizeof(double) * (size_t)D.n_pad * D.n_pad);
+    D.HT = (double *)base;
+    D.ldh = D.n_lat_pad;
+    base += a256(sizeof(double) * (size_t)D.n_lat_pad * D.n);
+    D.xl = (double *)base;
+    D.rp = m.A_rowptr; D.ci = m.A_col; D.av = m.A_val;
+  } else {
+    D.Pq = m.Qprior;
+    D.ldq = m.ldq;
+  }
+  return D;
+}
+
+// HT and K of the general-A thetas (no-ops for A = I).
+static void wb_prepare(Ctx &ctx, const WbDesc *dd, int B, const WbLayout &L) {
+  if (!L.any_general) return;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_ht_kernel, dim3((L.nlp_max + 255) / 256, L.n_max, B), dim3(256), 0, ctx.stream, dd);
+  });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(wb_k_kernel, dim3((L.np_max + 255) / 256, L.np_max, B), dim3(256), 0, ctx.stream, dd);
+  });
+}
+
+static HostFactor wb_factor(const WbDesc &D, bool var) {
+  HostFactor h{};
+  h.d.A = D.M; h.d.linv = D.linv; h.d.info = D.info; h.d.ld = D.ldm; h.d.nf = D.n_pad;
+  h.d.nrows = D.ldm; h.d.ncols = D.n_pad; h.d.id_row0 = std::numeric_limits<int>::max();
+  h.n_real = D.n; h.kb_real = var ? D.n_lat : 1; h.ks_real = 0;
+  return h;
 }
 
 static int wb_validate(int B, const inla_model *models, const double *theta, int ldtheta, double *const *x,
@@ -574,12 +797,11 @@ static int wb_validate(int B, const inla_model *models, const double *theta, int
   if (!res) return -8;
   if (opts && opts->prec != INLA_PREC_FP64) return INLA_ERR_UNSUPPORTED;
   for (int b = 0; b < B; ++b) {
-    const inla_model &m = models[b];
-    if (m.prior != INLA_PRIOR_PINV || m.n < 1 || m.k != 0 || m.m != 0 || !m.Qprior || m.ldq < m.n || !m.y ||
-        (m.lik != INLA_LIK_GAUSSIAN && m.lik != INLA_LIK_POISSON))
-      return -3;
+    if (!wb_model_ok(models[b])) return -3;
     if (!x[b]) return -6;
   }
+  for (int b = 0; b < B; ++b)
+    if (!wb_design_ok(models[b])) return -3;
   return INLA_OK;
 }
 
@@ -588,71 +810,48 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
   const int max_iter = opts && opts->max_iter > 0 ? opts->max_iter : 50;
   const double tol = opts && opts->tol > 0 ? opts->tol : 1e-11;
   const int start = opts ? opts->start : 0;
-  std::vector<WbDesc> hd(B);
-  std::vector<size_t> off(B);
-  size_t total = a256(sizeof(double) * WR_COUNT * B) + a256(sizeof(int) * B);
-  int np_max = 0, ldm_max = 0;
-  for (int b = 0; b < B; ++b) {
-    const int np = round_up(models[b].n, PADN), ldm = np + PADN;
-    off[b] = total;
-    total += a256(sizeof(double) * (size_t)ldm * np) + a256(sizeof(double) * (size_t)np * NBI) +
-             a256(sizeof(double) * (size_t)(7 + WB_CH) * np);
-    np_max = std::max(np_max, np);
-    ldm_max = std::max(ldm_max, ldm);
-  }
-  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  const size_t head = a256(sizeof(double) * WR_COUNT * B) + a256(sizeof(int) * B);
+  const WbLayout L = wb_layout(B, models, false, head);
+  if (!ctx.reserve(L.total)) return INLA_ERR_NOMEM;
   double *dres = (double *)ctx.ws;
   int *dinfo = (int *)(ctx.ws + a256(sizeof(double) * WR_COUNT * B));
+  std::vector<WbDesc> hd(B);
   for (int b = 0; b < B; ++b) {
-    const inla_model &m = models[b];
-    WbDesc &D = hd[b];
-    D = WbDesc{};
-    D.Pq = m.Qprior; D.ldq = m.ldq; D.y = m.y; D.E = m.E; D.xext = x[b];
-    D.n = m.n; D.n_pad = round_up(m.n, PADN); D.ldm = D.n_pad + PADN; D.lik = m.lik;
-    const double lp = theta[(size_t)b * ldtheta];
-    D.lpar = m.lik == INLA_LIK_GAUSSIAN ? std::exp(lp) : lp;
-    char *base = ctx.ws + off[b];
-    D.M = (double *)base;
-    base += a256(sizeof(double) * (size_t)D.ldm * D.n_pad);
-    D.linv = (double *)base;
-    base += a256(sizeof(double) * (size_t)D.n_pad * NBI);
-    double *v = (double *)base;
-    D.x = v; D.b = v + D.n_pad; D.sw = v + 2 * D.n_pad; D.u = v + 3 * D.n_pad; D.s = v + 4 * D.n_pad;
-    D.t = v + 5 * D.n_pad; D.w = v + 6 * D.n_pad; D.part = v + 7 * D.n_pad;
-    D.res = dres + WR_COUNT * b;
-    D.info = dinfo + b;
+    hd[b] = wb_desc(models[b], theta + (size_t)b * ldtheta, ctx.ws + L.off[b], false, x[b], nullptr,
+                    dres + WR_COUNT * b, dinfo + b);
     res[b] = inla_result{};
-    if (!std::isfinite(lp)) res[b].info = INLA_INFO_NONFINITE;
+    if (!std::isfinite(theta[(size_t)b * ldtheta])) res[b].info = INLA_INFO_NONFINITE;
   }
   std::vector<int> act;
   for (int b = 0; b < B; ++b) if (res[b].info == INLA_INFO_OK) act.push_back(b);
   {
     const WbDesc *dall = (const WbDesc *)ctx.upload(hd.data(), sizeof(WbDesc) * B);
     if (!dall) return INLA_ERR_NOMEM;
+    wb_prepare(ctx, dall, B, L);
     ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
-      hipLaunchKernelGGL(wb_start_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dall, start);
+      hipLaunchKernelGGL(wb_start_kernel, dim3((std::max(L.np_max, L.nlp_max) + 255) / 256, B), dim3(256), 0,
+                         ctx.stream, dall, start);
     });
   }
   std::vector<double> hres((size_t)WR_COUNT * B);
+  std::vector<double> prev(B, std::numeric_limits<double>::infinity());
   std::vector<int> hinfo(B);
   std::vector<int> done;
   for (int it = 1; it <= max_iter && !act.empty(); ++it) {
     std::vector<WbDesc> ha;
     std::vector<HostFactor> fs;
     std::vector<ThetaDesc> td;
-    int np = 0, ldm = 0;
+    int np = 0, ldm = 0, nlp = 0, gen = 0;
     double qbytes = 0;
     for (int b : act) {
       const WbDesc &D = hd[b];
       ha.push_back(D);
       np = std::max(np, D.n_pad);
       ldm = std::max(ldm, D.ldm);
+      nlp = std::max(nlp, D.n_lat_pad);
+      gen |= D.general;
       qbytes += 8.0 * D.n * D.n;
-      HostFactor h{};
-      h.d.A = D.M; h.d.linv = D.linv; h.d.info = D.info; h.d.ld = D.ldm; h.d.nf = D.n_pad;
-      h.d.nrows = D.ldm; h.d.ncols = D.n_pad; h.d.id_row0 = std::numeric_limits<int>::max();
-      h.n_real = D.n; h.kb_real = 1; h.ks_real = 0;
-      fs.push_back(h);
+      fs.push_back(wb_factor(D, false));
       ThetaDesc t{};
       t.W = D.M; t.ldw = D.ldm; t.linv = D.linv; t.n_pad = D.n_pad; t.n = D.n; t.r = D.s; t.u = D.t;
       td.push_back(t);
@@ -688,6 +887,14 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
     ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
       hipLaunchKernelGGL(wb_update_kernel, dim3(na), dim3(256), 0, ctx.stream, da);
     });
+    if (gen) {
+      ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+        hipLaunchKernelGGL(wb_xl_part_kernel, dim3((nlp + 255) / 256, WB_CH, na), dim3(256), 0, ctx.stream, da);
+      });
+      ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+        hipLaunchKernelGGL(wb_xl_update_kernel, dim3(na), dim3(256), 0, ctx.stream, da);
+      });
+    }
     if (hipMemcpyAsync(hres.data(), dres, sizeof(double) * WR_COUNT * B, hipMemcpyDeviceToHost, ctx.stream) !=
             hipSuccess ||
         hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * B, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess)
@@ -702,7 +909,9 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
       o.step = R[WR_STEP];
       if (hinfo[b] > 0) { o.info = hinfo[b]; continue; }
       if (R[WR_NONFINITE] != 0.0 || !std::isfinite(R[WR_STEP])) { o.info = INLA_INFO_NONFINITE; continue; }
-      if (models[b].lik == INLA_LIK_GAUSSIAN || R[WR_STEP] <= tol * R[WR_SCALE]) {
+      const bool floor = R[WR_STEP] <= WB_FLOOR_TOL * R[WR_SCALE] && R[WR_STEP] > 0.5 * prev[b];
+      prev[b] = R[WR_STEP];
+      if (models[b].lik == INLA_LIK_GAUSSIAN || R[WR_STEP] <= tol * R[WR_SCALE] || floor) {
         done.push_back(b);
         continue;
       }
@@ -739,63 +948,40 @@ static int woodbury_eval(Ctx &ctx, int B, const inla_model *models, const double
   return ctx.check();
 }
 
-// Marginal variances diag(Sigma*) at given modes: M = I + S Q^+ S with W at the
-// mode, factored with the n border rows Q^+ S, which come out as (L^{-1} S Q^+)^T.
+// Marginal variances diag(Sigma*) at given modes: M = I + S K S with W at the
+// mode, factored with the n_lat border rows (Q^+ A^T S), which come out as
+// (L^{-1} S A Q^+)^T.
 static int woodbury_var(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta,
                         const double *const *x, double *const *var, int *info) {
-  std::vector<WbDesc> hd(B);
-  std::vector<size_t> off(B);
-  size_t total = a256(sizeof(int) * B);
-  int np_max = 0, ldm_max = 0;
-  for (int b = 0; b < B; ++b) {
-    const int np = round_up(models[b].n, PADN), ldm = 2 * np;
-    off[b] = total;
-    total += a256(sizeof(double) * (size_t)ldm * np) + a256(sizeof(double) * (size_t)np * NBI) +
-             a256(sizeof(double) * (size_t)3 * np);
-    np_max = std::max(np_max, np);
-    ldm_max = std::max(ldm_max, ldm);
-  }
-  if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
+  const size_t head = a256(sizeof(int) * B);
+  const WbLayout L = wb_layout(B, models, true, head);
+  if (!ctx.reserve(L.total)) return INLA_ERR_NOMEM;
   int *dinfo = (int *)ctx.ws;
+  std::vector<WbDesc> hd(B);
   std::vector<HostFactor> fs;
   for (int b = 0; b < B; ++b) {
-    const inla_model &m = models[b];
-    WbDesc &D = hd[b];
-    D = WbDesc{};
-    D.Pq = m.Qprior; D.ldq = m.ldq; D.y = m.y; D.E = m.E; D.xext = (double *)x[b]; D.vext = var[b];
-    D.n = m.n; D.n_pad = round_up(m.n, PADN); D.ldm = 2 * D.n_pad; D.lik = m.lik;
-    const double lp = theta[(size_t)b * ldtheta];
-    D.lpar = m.lik == INLA_LIK_GAUSSIAN ? std::exp(lp) : lp;
-    char *base = ctx.ws + off[b];
-    D.M = (double *)base;
-    base += a256(sizeof(double) * (size_t)D.ldm * D.n_pad);
-    D.linv = (double *)base;
-    base += a256(sizeof(double) * (size_t)D.n_pad * NBI);
-    double *v = (double *)base;
-    D.x = v; D.b = v + D.n_pad; D.sw = v + 2 * D.n_pad;
-    D.info = dinfo + b;
-    HostFactor h{};
-    h.d.A = D.M; h.d.linv = D.linv; h.d.info = D.info; h.d.ld = D.ldm; h.d.nf = D.n_pad;
-    h.d.nrows = D.ldm; h.d.ncols = D.n_pad; h.d.id_row0 = std::numeric_limits<int>::max();
-    h.n_real = D.n; h.kb_real = D.n; h.ks_real = 0;
-    fs.push_back(h);
+    hd[b] = wb_desc(models[b], theta + (size_t)b * ldtheta, ctx.ws + L.off[b], true, (double *)x[b], var[b],
+                    nullptr, dinfo + b);
+    fs.push_back(wb_factor(hd[b], true));
   }
   const WbDesc *dd = (const WbDesc *)ctx.upload(hd.data(), sizeof(WbDesc) * B);
   if (!dd) return INLA_ERR_NOMEM;
-  const dim3 gv((np_max + 255) / 256, B);
+  wb_prepare(ctx, dd, B, L);
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(wb_start_kernel, gv, dim3(256), 0, ctx.stream, dd, 1);
+    hipLaunchKernelGGL(wb_start_kernel, dim3((std::max(L.np_max, L.nlp_max) + 255) / 256, B), dim3(256), 0,
+                       ctx.stream, dd, 1);
   });
   ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(wb_lik_kernel, gv, dim3(256), 0, ctx.stream, dd);
+    hipLaunchKernelGGL(wb_lik_kernel, dim3((L.np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dd);
   });
   ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(wb_assemble_kernel, dim3((ldm_max + 255) / 256, np_max, B), dim3(256), 0, ctx.stream, dd, 1);
+    hipLaunchKernelGGL(wb_assemble_kernel, dim3((L.ldm_max + 255) / 256, L.np_max, B), dim3(256), 0, ctx.stream,
+                       dd, 1);
   });
   int rc = factor_batch(ctx, fs, INLA_PREC_FP64);
   if (rc) return rc;
   ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
-    hipLaunchKernelGGL(wb_var_kernel, gv, dim3(256), 0, ctx.stream, dd);
+    hipLaunchKernelGGL(wb_var_kernel, dim3((L.nlp_max + 255) / 256, B), dim3(256), 0, ctx.stream, dd);
   });
   std::vector<int> hinfo(B);
   if (hipMemcpyAsync(hinfo.data(), dinfo, sizeof(int) * B, hipMemcpyDeviceToHost, ctx.stream) != hipSuccess)
@@ -846,14 +1032,13 @@ int inla_woodbury_var(inla_handle *h, int32_t B, const inla_model *models, const
   if (!var) return -7;
   if (!info) return -8;
   for (int b = 0; b < B; ++b) {
-    const inla_model &m = models[b];
-    if (m.prior != INLA_PRIOR_PINV || m.n < 1 || m.k != 0 || m.m != 0 || !m.Qprior || m.ldq < m.n || !m.y ||
-        (m.lik != INLA_LIK_GAUSSIAN && m.lik != INLA_LIK_POISSON))
-      return -3;
+    if (!wb_model_ok(models[b])) return -3;
     if (!std::isfinite(theta[(size_t)b * ldtheta])) return -4;
     if (!x_mode[b]) return -6;
     if (!var[b]) return -7;
   }
+  for (int b = 0; b < B; ++b)
+    if (!wb_design_ok(models[b])) return -3;
   return woodbury_var(*handle_ctx(h), B, models, theta, ldtheta, x_mode, var, info);
 }
 

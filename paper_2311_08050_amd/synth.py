@@ -208,6 +208,75 @@ def rw1_besag_theta0(n_t, lik="poisson"):
     return np.array([math.log(tau0), 0.0 if lik == "poisson" else math.log(0.25)])
 
 
+def random_besag_graph(n_s, rng, p=0.3):
+    """Neighbour pairs of a random region graph in the manner of the paper's
+    appendix on simulating a random Besag graph: every region draws n_s binary
+    features with probability p, two regions are neighbours when they share a
+    feature, and draws repeat until the graph is connected."""
+    while True:
+        F = rng.random((n_s, n_s)) < p
+        share = (F.astype(np.int64) @ F.T.astype(np.int64)) > 0
+        np.fill_diagonal(share, False)
+        seen = np.zeros(n_s, dtype=bool)
+        stack = [0]
+        seen[0] = True
+        while stack:
+            i = stack.pop()
+            for j in np.nonzero(share[i] & ~seen)[0]:
+                seen[j] = True
+                stack.append(int(j))
+        if seen.all():
+            i, j = np.nonzero(np.triu(share, 1))
+            return np.stack([i, j], axis=1).astype(np.int64)
+
+
+def type4(n_s, n_t, seed, graph="random", p=0.3):
+    """The simulation study's space-time model (section "Simulation study"):
+        eta_{st} = mu + beta_t t_c + alpha_time_t + alpha_space_s + zeta_{ts},
+    Poisson counts y ~ Poisson(E exp(eta)), E ~ U(5, 50), t_c = (t - (n_t-1)/2) / n_t.
+    Latent layout (s = n_t n_s + n_s + n_t + 2 effects): [mu, beta_t,
+    alpha_time (n_t), alpha_space (n_s), zeta (index t*n_s + s)]; observation
+    index t*n_s + s; A is the dense (n_t n_s) x s design matrix.  Priors (built
+    by the consumers): low-precision Gaussian on mu and beta_t, RW2 in time,
+    Besag in space on ``edges`` (graph "random": the appendix's random graph;
+    "delaunay": the triangulation of random points), and the Type IV interaction
+    RW2 kron Besag.  The true effects are smooth draws with the sum-to-zero
+    and linear-trend parts removed."""
+    rng = np.random.default_rng(seed)
+    edges = random_besag_graph(n_s, rng, p) if graph == "random" else region_graph(points(rng, n_s))
+    m = n_s * n_t
+    n = m + n_s + n_t + 2
+    t = np.repeat(np.arange(n_t), n_s)
+    sidx = np.tile(np.arange(n_s), n_t)
+    tc = (t - (n_t - 1) / 2.0) / n_t
+    A = np.zeros((m, n))
+    rows = np.arange(m)
+    A[rows, 0] = 1.0
+    A[rows, 1] = tc
+    A[rows, 2 + t] = 1.0
+    A[rows, 2 + n_t + sidx] = 1.0
+    A[rows, 2 + n_t + n_s + rows] = 1.0
+    tt = np.arange(n_t) / max(1, n_t - 1)
+    a_time = 0.2 * np.sin(2.0 * math.pi * tt + rng.uniform(0, 2 * math.pi))
+    a_time -= np.polyval(np.polyfit(tt, a_time, 1), tt) if n_t > 2 else a_time.mean()
+    a_space = rng.normal(0.0, 0.2, size=n_s)
+    a_space -= a_space.mean()
+    zeta = rng.normal(0.0, 0.1, size=(n_t, n_s))
+    zeta = double_centre(zeta).reshape(-1)
+    x = np.concatenate([[0.1, 0.3], a_time, a_space, zeta])
+    E = rng.uniform(5.0, 50.0, size=m)
+    y = rng.poisson(E * np.exp(A @ x)).astype(np.float64)
+    return {
+        "n": n, "m": m, "lik": "poisson", "prior": "type4", "y": y, "E": E, "A": A, "C": None, "e": None,
+        "edges": edges, "n_s": n_s, "n_t": n_t, "x_true": x, "fixed_precision": 1e-3,
+    }
+
+
+def type4_theta0():
+    """(log tau_time, log tau_space, log tau_interaction, beta0 = 0)."""
+    return np.array([math.log(10.0), math.log(2.0), math.log(5.0), 0.0])
+
+
 def fd_batch(theta0, h, dims):
     """theta0 followed by theta0 +/- h e_j for each j in ``dims`` (the points of a
     central finite-difference gradient)."""

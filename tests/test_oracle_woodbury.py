@@ -146,3 +146,61 @@ def test_mode_invariants_poisson():
     # start independence
     r2 = WB.laplace_eval(m, th, x0=0.5 * x + 0.01)
     assert np.max(np.abs(r2["x"] - x)) <= 1e-10 * max(1.0, np.max(np.abs(x)))
+
+
+# ------------------------------------------------------------------ Type IV model
+def type4_null_basis(m):
+    """Orthonormal basis of null(Q_prior) of the Type IV model, written from the
+    structure of its blocks: alpha_time in span{1, t}, alpha_space constant,
+    zeta in span{1_t kron e_s, t kron e_s, e_t kron 1_s}; mu and beta_t have
+    proper priors."""
+    n_s, n_t, n = m["n_s"], m["n_t"], m["n"]
+    o_t, o_s, o_z = 2, 2 + n_t, 2 + n_t + n_s
+    tt = np.arange(n_t, dtype=float)
+    cols = []
+    for v in (np.ones(n_t), tt):
+        c = np.zeros(n); c[o_t:o_t + n_t] = v; cols.append(c)
+    c = np.zeros(n); c[o_s:o_s + n_s] = 1.0; cols.append(c)
+    for s in range(n_s):
+        for v in (np.ones(n_t), tt):
+            c = np.zeros(n); c[o_z:] = np.kron(v, np.eye(n_s)[s]); cols.append(c)
+    for t in range(n_t):
+        c = np.zeros(n); c[o_z:] = np.kron(np.eye(n_t)[t], np.ones(n_s)); cols.append(c)
+    Qr, Rr = np.linalg.qr(np.stack(cols, axis=1))
+    return Qr[:, np.abs(np.diag(Rr)) > 1e-10]
+
+
+def test_type4_sizes_of_table3():
+    """Effects size s = n_t n_s + n_s + n_t + 2 and constraint count k = the
+    null-space dimension of Q_prior, as printed (first two rows; the third by
+    the same formulas)."""
+    with open(os.path.join(GOLDEN, "table3_sizes.json")) as f:
+        rows = json.load(f)["rows"]
+    for r in rows:
+        m = synth.type4(r["n_s"], r["n_t"], seed=1)
+        assert m["n"] == r["s"] and m["A"].shape == (r["n_s"] * r["n_t"], r["s"])
+        assert r["k"] == r["n_t"] + 2 * r["n_s"] + 1
+        if r["s"] <= 2500:
+            Q = WB.prior_precision(m, synth.type4_theta0())
+            _, rank, _ = WB.pseudo_inverse(Q)
+            assert m["n"] - rank == r["k"]
+            assert type4_null_basis(m).shape[1] == r["k"]
+
+
+@pytest.mark.parametrize("graph", ["delaunay", "random"])
+def test_type4_equals_kriging_route(graph):
+    """Woodbury on the intrinsic Type IV prior with its design matrix equals
+    kriging on Q + N N^T with the n_t + 2 n_s + 1 constraints N^T x = 0."""
+    m = synth.type4(12, 5, seed=4, graph=graph)
+    th = synth.type4_theta0() + np.array([0.2, -0.1, 0.3, 0.0])
+    r = WB.laplace_eval(m, th)
+    N = type4_null_basis(m)
+    Q = WB.prior_precision(m, th)
+    assert N.shape[1] == 5 + 2 * 12 + 1 and r["rank"] == m["n"] - N.shape[1]
+    assert np.max(np.abs(Q @ N)) <= 1e-12 * np.max(np.abs(Q))
+    km = {"n": m["n"], "lik": "poisson", "prior": "dense", "y": m["y"], "E": m["E"], "A": m["A"],
+          "C": N.T, "e": np.zeros(N.shape[1]), "Qprior": Q + N @ N.T}
+    k = O.laplace_eval(km, th[3:])
+    assert r["info"] == k["info"] == O.INFO_OK
+    assert np.max(np.abs(r["x"] - k["x"])) <= 1e-9 * max(1.0, np.max(np.abs(k["x"])))
+    assert abs(r["objective"] - k["objective"]) <= 1e-9 * abs(k["objective"])
