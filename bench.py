@@ -238,6 +238,7 @@ def run_extras(lib, binding, synth, dms, thetas, xs):
                            "hessian_and_ccd_s": t2 - t1, "ccd_points": len(pts), "info": [g["info"], hinfo]}
     log(f"stage 1 at n=3000: {t1 - t0:.2f} s ({g['iters']} iterations), Hessian + CCD {t2 - t1:.2f} s")
     out["moore_penrose_n3000"] = run_moore_penrose(lib, binding, synth)
+    out["table3_type4"] = run_table3(lib, binding, synth)
     return out
 
 
@@ -255,6 +256,125 @@ def intrinsic_inputs(model):
     cols = np.hstack([np.kron(np.ones((n_t, 1)), np.eye(n_s)), np.kron(np.eye(n_t), np.ones((n_s, 1)))])
     Qr, Rr = np.linalg.qr(cols)
     return np.kron(Rt, Rs), Qr[:, np.abs(np.diag(Rr)) > 1e-10]
+
+
+def type4_inputs(model, theta):
+    """Caller-side inputs of the Type IV model: the structure blocks of its
+    prior (RW2 in time, Besag in space and their Kronecker product), the full
+    Q_prior(theta), and an orthonormal basis of its null space written from the
+    blocks (time effect: constant and linear trend; space effect: constant;
+    interaction: constant and linear in time per region, constant over regions
+    per time)."""
+    import math
+
+    import numpy as np
+    n_s, n_t, n = model["n_s"], model["n_t"], model["n"]
+    D = np.zeros((n_t - 2, n_t))
+    for i in range(n_t - 2):
+        D[i, i:i + 3] = (1.0, -2.0, 1.0)
+    R2 = D.T @ D
+    Rs = np.zeros((n_s, n_s))
+    Rs[model["edges"][:, 0], model["edges"][:, 1]] = -1.0
+    Rs[model["edges"][:, 1], model["edges"][:, 0]] = -1.0
+    Rs -= np.diag(Rs.sum(axis=1))
+    Rk = np.kron(R2, Rs)
+    c = model["fixed_precision"]
+    tau = [math.exp(v) for v in theta[:3]]
+    Q = np.zeros((n, n))
+    Q[0, 0] = Q[1, 1] = c
+    o = 2
+    for blk, t in ((R2, tau[0]), (Rs, tau[1]), (Rk, tau[2])):
+        k = blk.shape[0]
+        Q[o:o + k, o:o + k] = t * blk
+        o += k
+    tt = np.arange(n_t, dtype=float)
+    cols = []
+    o_t, o_s, o_z = 2, 2 + n_t, 2 + n_t + n_s
+    for v in (np.ones(n_t), tt):
+        col = np.zeros(n); col[o_t:o_t + n_t] = v; cols.append(col)
+    col = np.zeros(n); col[o_s:o_s + n_s] = 1.0; cols.append(col)
+    for sr in range(n_s):
+        for v in (np.ones(n_t), tt):
+            col = np.zeros(n); col[o_z + sr:o_z + n_t * n_s:n_s] = v; cols.append(col)
+    for t in range(n_t):
+        col = np.zeros(n); col[o_z + t * n_s:o_z + (t + 1) * n_s] = 1.0; cols.append(col)
+    Qr, Rr = np.linalg.qr(np.stack(cols, axis=1))
+    return (R2, Rs, Rk), Q, Qr[:, np.abs(np.diag(Rr)) > 1e-10]
+
+
+def run_table3(lib, binding, synth, B=8, sizes=((200, 5), (400, 5), (800, 5))):
+    """The paper's comparison table of the simulation study (kriging against the
+    Moore-Penrose route on the Type IV model with intercept, trend, RW2 time,
+    random-graph Besag space and RW2 x Besag interaction), at its three sizes:
+    B theta ~ N(theta0, 0.3^2 I) each.  Moore-Penrose: the pseudo-inverses of
+    the three structure blocks from one batched GPU Jacobi call (timed apart),
+    Q_prior(theta)^+ assembled block-diagonally with the 1/tau scalings, then
+    inla_woodbury_eval with the design matrix.  Kriging: inla_laplace_eval on
+    Q_prior + N N^T with the n_t + 2 n_s + 1 constraints N^T x = 0.  FP64."""
+    import math
+
+    import numpy as np
+    import torch
+    out = []
+    for n_s, n_t in sizes:
+        m = synth.type4(n_s, n_t, seed=90 + n_s)
+        th0 = synth.type4_theta0()
+        thetas = synth.normal_batch(th0, B, 0.3, seed=91 + n_s)
+        thetas[:, 3] = 0.0
+        blocks, _, N = type4_inputs(m, th0)
+        mats = [torch.as_tensor(b).cuda() for b in blocks]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Pb, ranks, sweeps, pinfo = lib.pinv(mats)
+        torch.cuda.synchronize()
+        t_pinv = time.perf_counter() - t0
+        n = m["n"]
+        Ps = []
+        for th in thetas:
+            P = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+            P[0, 0] = P[1, 1] = 1.0 / m["fixed_precision"]
+            o = 2
+            for Pk, v in zip(Pb, th[:3]):
+                k = Pk.shape[0]
+                P[o:o + k, o:o + k] = Pk / math.exp(v)
+                o += k
+            Ps.append(P)
+        dm = binding.DeviceModel(m)
+        lib.woodbury_eval([dm], [0.0], Ps[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rw, xw = lib.woodbury_eval([dm] * B, thetas[:, 3], Ps)
+        torch.cuda.synchronize()
+        t_wood = time.perf_counter() - t0
+        kms = []
+        for th in thetas:
+            _, Q, _ = type4_inputs(m, th)
+            kms.append(binding.DeviceModel({"n": n, "lik": "poisson", "prior": "dense", "y": m["y"], "E": m["E"],
+                                            "A": m["A"], "C": N.T, "e": np.zeros(N.shape[1]),
+                                            "Qprior": Q + N @ N.T}))
+        lib.laplace_eval(kms[:1], thetas[:1, 3:])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rk, xk = lib.laplace_eval(kms, thetas[:, 3:])
+        torch.cuda.synchronize()
+        t_krig = time.perf_counter() - t0
+        d = max(abs(a["objective"] - b["objective"]) / abs(b["objective"]) for a, b in zip(rw, rk))
+        dx = max(float((xa - xb).abs().max()) for xa, xb in zip(xw, xk))
+        row = {"n_s": n_s, "n_t": n_t, "effects": n, "constraints": int(N.shape[1]), "observations": m["m"],
+               "pinv_blocks": [int(b.shape[0]) for b in blocks], "pinv_s": t_pinv,
+               "pinv_sweeps": [int(v) for v in sweeps], "pinv_info": [int(v) for v in pinfo],
+               "woodbury_theta_evals_per_s": B / t_wood, "kriging_theta_evals_per_s": B / t_krig,
+               "woodbury_iters_mean": float(np.mean([r["iters"] for r in rw])),
+               "kriging_iters_mean": float(np.mean([r["iters"] for r in rk])),
+               "max_rel_objective_diff": d, "max_abs_mode_diff": dx,
+               "info": [r["info"] for r in rw] + [r["info"] for r in rk]}
+        log(f"table 3 size s={n} k={N.shape[1]}: pinv of blocks {t_pinv:.2f} s; Woodbury {B / t_wood:.1f} vs "
+            f"kriging {B / t_krig:.1f} theta-evals/s; objectives agree to {d:.1e}, modes to {dx:.1e}")
+        out.append(row)
+        del Ps, kms, dm
+        torch.cuda.empty_cache()
+    return {"workload": f"Type IV Poisson model of the simulation study, random Besag graph, batch {B} theta ~ "
+                        "N(theta0, 0.3^2 I) per size", "rows": out, "precision": "fp64"}
 
 
 def run_moore_penrose(lib, binding, synth, B=9):
@@ -363,7 +483,8 @@ def main():
     torch.cuda.set_device(0)
     if args.moore_penrose_only:
         lib = binding.Library()
-        print(json.dumps({"moore_penrose_n3000": run_moore_penrose(lib, binding, synth)}), flush=True)
+        print(json.dumps({"moore_penrose_n3000": run_moore_penrose(lib, binding, synth),
+                          "table3_type4": run_table3(lib, binding, synth)}), flush=True)
         return
     if args.calibrate_copy:
         nbytes = 1 << 30
