@@ -451,7 +451,7 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--ns", type=int, default=128)
     ap.add_argument("--nt", type=int, default=64)
-    ap.add_argument("--variants", default="fp64,fp32,bf16,fp32+mlp,bf16+mlp")
+    ap.add_argument("--variants", default="fp64,fp32,bf16,bf16+mlp,fp32+mlp")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="factor with the default panel width and tile instead of tuning them first")
