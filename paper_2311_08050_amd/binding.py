@@ -43,7 +43,7 @@ EXPORTS = [
 # reports their times; the fastest is then timed with lookahead as well.
 TUNE_CANDIDATES = {p: [(nb, tm) for nb in (128, 256, 512, 1024) for tm in (64, 128) if p != "bf16" or tm == 128]
                    for p in PREC}
-TUNE_DEFAULT = (512, 128, 0)
+TUNE_DEFAULT = {"fp64": (512, 64, 0), "fp32": (512, 128, 0), "bf16": (512, 128, 0)}
 
 
 class Model(C.Structure):

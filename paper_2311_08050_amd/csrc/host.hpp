@@ -118,6 +118,8 @@ struct PrecScope {
 // Library entry points implemented in other translation units.
 // cfg == nullptr: the tuned (or default) configuration for this batch.
 int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int prec, const TuneCfg *cfg = nullptr);
+// The configuration used without a tuning table entry.
+TuneCfg default_config(int prec);
 // The configuration factor_batch uses for a batch of `B` factorisations whose
 // largest padded order is `nf_max`.
 TuneCfg tuned_config(const Ctx &ctx, int prec, int nf_max, int B);
