@@ -359,13 +359,15 @@ int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_po
  * place of explicit constraints, and the posterior covariance follows the
  * Woodbury form of Eq. (woodeqn).
  *
- * inla_pinv: Q^+ of B symmetric matrices by a cyclic two-sided Jacobi
- * eigen-decomposition Q = V diag(lambda) V^T (round-robin rotation order, sweeps
- * until the off-diagonal Frobenius norm is at most 4 eps ||A||_F, or below
- * 1e-14 ||A||_F and shrinking by less than 10% per sweep; at most 40 sweeps),
+ * inla_pinv: Q^+ of B symmetric matrices by a block Jacobi eigen-decomposition
+ * Q = V diag(lambda) V^T: blocks of 32 indices, block pairs in round-robin
+ * order, each pair's 64 x 64 principal submatrix diagonalised by cyclic Jacobi
+ * and applied to A and V as 64-wide tile products; sweeps until the
+ * off-diagonal Frobenius norm is at most 4 eps ||A||_F, or below 1e-14 ||A||_F
+ * and shrinking by less than 10% per sweep (at most 40 sweeps).
  * Q^+ = V diag(f) V^T with f_k = 1 / lambda_k where |lambda_k| > rtol *
  * max|lambda| and 0 otherwise.
- *   n        host [B] orders, 1 <= n[b] <= 4096
+ *   n        host [B] orders, 1 <= n[b] <= 16384
  *   Q        host array of B device pointers: column-major, lower triangle read
  *   ldq      host [B] leading dimensions (>= n[b])
  *   Qpinv    host array of B device pointers: output, full symmetric n x n
@@ -374,9 +376,10 @@ int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_po
  *   rank     host [B] output: number of eigenvalues kept
  *   sweeps   host [B] output: Jacobi sweeps taken
  *   info     host [B] output: 0, INLA_INFO_EIG_MAXIT or INLA_INFO_NONFINITE
- * Uses the handle's workspace (2 n^2 + O(n) doubles per matrix) and
- * synchronises the handle's stream once per sweep.  Returns -i for an invalid
- * i-th argument (a bad n[b] as -3), INLA_ERR_NOMEM or INLA_ERR_HIP. */
+ * Uses the handle's workspace (2 ne^2 + O(ne) doubles per matrix, ne = n
+ * rounded up to 64) and synchronises the handle's stream once per sweep.
+ * Returns -i for an invalid i-th argument (a bad n[b] as -3), INLA_ERR_NOMEM
+ * or INLA_ERR_HIP. */
 int inla_pinv(inla_handle *h, int32_t B, const int32_t *n, const double *const *Q, const int32_t *ldq,
               double *const *Qpinv, const int32_t *ldp, double rtol, int32_t *rank, int32_t *sweeps, int32_t *info);
 

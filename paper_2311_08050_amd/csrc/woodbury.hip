@@ -5,14 +5,13 @@
 // the Laplace evaluation with the posterior covariance in the Woodbury form of
 // Eq. (woodeqn), for A = I or a general sparse design matrix.
 //
-// Jacobi: the pairs of a round follow the round-robin (circle) schedule, so the
-// n/2 rotations of a round are disjoint and one launch applies all of them: the
-// workgroup of pair (p, q) owns columns p and q of A and of V, mixes the two
-// columns with its own rotation and then every row pair with that pair's
-// rotation.  The rotation angles of the next round are read from a small side
-// array that each owner fills with its new diagonal entry and the entry its
-// column holds in the row of its next partner, so every workgroup computes
-// bit-identical angles without reading columns another workgroup is writing.
+// Jacobi: a block method.  The indices form blocks of 32; the block pairs of a
+// round follow the round-robin (circle) schedule, so their rotations are
+// disjoint.  Per round, each pair's 64 x 64 principal submatrix is diagonalised
+// in LDS by cyclic Jacobi (rotations accumulated from the identity), then every
+// pair's columns of A and V are multiplied by its 64 x 64 rotation and its rows
+// of A by the transpose (two passes of 64-wide tile products).  A sweep thus
+// passes over A and V n/32 times instead of n times.
 //
 // Woodbury Newton: with W the likelihood curvature (Q_l = diag(W)) and
 // S = diag(sqrt(W)), the symmetric form of Eq. (woodeqn) is
@@ -41,33 +40,32 @@ namespace inla {
 Ctx *handle_ctx(inla_handle *h);
 
 // ------------------------------------------------------------------ Jacobi
-constexpr int JAC_MAX_N = 4096;      // two columns of the working matrix fit the 64 KiB of LDS
+constexpr int JB = 32;               // block width of the block Jacobi method
+constexpr int JP = 2 * JB;           // block-pair width (the inner eigenproblem's order)
+constexpr int JAC_MAX_N = 16384;
 constexpr int JAC_MAX_SWEEPS = 40;
+constexpr int JAC_INNER_SWEEPS = 30;
 constexpr double JAC_RTOL_DEFAULT = 1e-9;
 constexpr int JAC_NORM_BLOCKS = 256;
 
 struct JacDesc {
   const double *Q;   // input, lower triangle read (ld ldq)
-  double *A, *V;     // ne x ne working matrix and eigenvectors (ld ne)
-  double *side;      // 2 slots x 2 x ne: [slot][0][k] = a_kk, [slot][1][k] = a_{partner(k), k}
+  double *A, *V;     // ne x ne working matrix and eigenvectors (ld ne), ne a multiple of JP
+  double *R;         // [nbk / 2][JP * JP] the round's pair rotations, column-major
+  double *lam;       // [nbk / 2][JP] the pairs' eigenvalues
   double *f;         // [ne] 1/lambda_k or 0
   double *part;      // [2 * JAC_NORM_BLOCKS] per-workgroup partial sums of squares
   double *norms;     // [4] off-diagonal sum of squares, sum of squares, max|lambda|, rank
   double *P;         // output Q^+ (ld ldp), full symmetric
-  int n, ne, ldq, ldp;
+  int n, ne, nbk, ldq, ldp;
 };
 
-// Round-robin schedule of ne (even) players, round r in [0, ne - 2]: slot 0
-// holds player 0, the other players rotate through slots 1 .. ne - 1; slots s
-// and ne - 1 - s play each other.
-__host__ __device__ __forceinline__ int rr_pos(int slot, int r, int ne) {
-  return slot == 0 ? 0 : 1 + (slot - 1 + r) % (ne - 1);
-}
-__host__ __device__ __forceinline__ int rr_slot(int k, int r, int ne) {
-  return k == 0 ? 0 : 1 + (k - 1 - r + (ne - 1)) % (ne - 1);
-}
-__host__ __device__ __forceinline__ int rr_partner(int k, int r, int ne) {
-  return rr_pos(ne - 1 - rr_slot(k, r, ne), r, ne);
+// Round-robin schedule of np (even) players, round r in [0, np - 2]: slot 0
+// holds player 0, the other players rotate through slots 1 .. np - 1; slots s
+// and np - 1 - s play each other.  Players are blocks of JB indices in the
+// outer iteration and single indices in the inner one.
+__host__ __device__ __forceinline__ int rr_pos(int slot, int r, int np) {
+  return slot == 0 ? 0 : 1 + (slot - 1 + r) % (np - 1);
 }
 
 // The rotation J = [c s; -s c] (rows and columns p, q) with (J^T A J)_pq = 0
@@ -84,8 +82,11 @@ __device__ __forceinline__ void jac_rot(double app, double aqq, double apq, doub
   s = t * c;
 }
 
-// A = Q (symmetric from its lower triangle, zero padded to ne), V = I, and the
-// side array of round 0.  Grid (ne / 256 row blocks, ne columns, B).
+// Global index of local index l (0 .. JP-1) of the pair of blocks (I, K).
+__device__ __forceinline__ int pair_idx(int l, int I, int K) { return l < JB ? I * JB + l : K * JB + (l - JB); }
+
+// A = Q (symmetric from its lower triangle, zero padded to ne), V = I.  Grid
+// (ne / 256 row blocks, ne columns, B).
 __global__ __launch_bounds__(256) void jacobi_init_kernel(const JacDesc *__restrict__ jd) {
   const JacDesc J = jd[blockIdx.z];
   const int c = blockIdx.y, i = blockIdx.x * 256 + threadIdx.x;
@@ -94,69 +95,178 @@ __global__ __launch_bounds__(256) void jacobi_init_kernel(const JacDesc *__restr
   if (i < J.n && c < J.n) a = i >= c ? J.Q[(size_t)c * J.ldq + i] : J.Q[(size_t)i * J.ldq + c];
   J.A[(size_t)c * J.ne + i] = a;
   J.V[(size_t)c * J.ne + i] = i == c ? 1.0 : 0.0;
-  if (i == c) J.side[c] = a;
-  if (i == rr_partner(c, 0, J.ne)) J.side[J.ne + c] = a;
 }
 
-// One round: A <- J^T A J and V <- V J for the ne / 2 disjoint rotations of
-// round r (global round counter; each matrix uses r mod (ne - 1) and the side
-// slot r mod 2).  Workgroup j owns the columns of pair j.  Grid (ne_max / 2, B),
-// dynamic LDS 2 * ne_max doubles.
-__global__ __launch_bounds__(256) void jacobi_round_kernel(const JacDesc *__restrict__ jd, int r) {
+// Inner eigenproblem of one block pair: the JP x JP principal submatrix S of A
+// on the pair's indices is diagonalised in LDS by cyclic Jacobi (round-robin
+// over its JP indices, rotations accumulated from the identity, so R stays
+// close to I, which the outer iteration's convergence needs), until its
+// off-diagonal part is at the rounding level.  Writes R (column-major) and the
+// diagonal.  Grid (nbk / 2 pairs, B).
+__global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__restrict__ jd, int r) {
   const JacDesc J = jd[blockIdx.y];
-  const int ne = J.ne, j = blockIdx.x;
-  if (j >= ne / 2) return;
-  const int rb = r % (ne - 1);
-  const double *sd_in = J.side + (size_t)(r & 1) * 2 * ne;
-  double *sd_out = J.side + (size_t)((r + 1) & 1) * 2 * ne;
-  const int p = rr_pos(j, rb, ne), q = rr_pos(ne - 1 - j, rb, ne);
-  double cj, sj;
-  jac_rot(sd_in[p], sd_in[q], sd_in[ne + p], cj, sj);
-  extern __shared__ double lds[];
-  double *cp = lds, *cq = lds + ne;
-  auto *Ap = gptr(J.A + (size_t)p * ne), *Aq = gptr(J.A + (size_t)q * ne);
-  for (int i = threadIdx.x; i < ne; i += 256) {
-    cp[i] = Ap[i];
-    cq[i] = Aq[i];
-  }
-  auto *Vp = gptr(J.V + (size_t)p * ne), *Vq = gptr(J.V + (size_t)q * ne);
-  for (int i = threadIdx.x; i < ne; i += 256) {
-    const double a = Vp[i], b = Vq[i];
-    Vp[i] = cj * a - sj * b;
-    Vq[i] = sj * a + cj * b;
+  const int j = blockIdx.x;
+  if (j >= J.nbk / 2) return;
+  const int rb = r % (J.nbk - 1);
+  const int I = rr_pos(j, rb, J.nbk), K = rr_pos(J.nbk - 1 - j, rb, J.nbk);
+  __shared__ double S[JP][JP + 1];    // S[row][col]
+  __shared__ double Rt[JP][JP + 1];   // Rt[col][row] = R(row, col)
+  __shared__ double cs[JP / 2], sn[JP / 2];
+  __shared__ int pp[JP / 2], qq[JP / 2];
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  const auto *A = gptr((const double *)J.A);
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int l = e % JP, m = e / JP;
+    S[l][m] = A[(size_t)pair_idx(m, I, K) * J.ne + pair_idx(l, I, K)];
+    Rt[m][l] = l == m ? 1.0 : 0.0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ne / 2; i += 256) {
-    const int P = rr_pos(i, rb, ne), Qr = rr_pos(ne - 1 - i, rb, ne);
-    double ci = cj, si = sj;
-    if (i != j) jac_rot(sd_in[P], sd_in[Qr], sd_in[ne + P], ci, si);
-    // columns: (A J) on rows P and Qr of the two owned columns
-    const double aPp = cp[P], aPq = cq[P], aQp = cp[Qr], aQq = cq[Qr];
-    const double bPp = cj * aPp - sj * aPq, bPq = sj * aPp + cj * aPq;
-    const double bQp = cj * aQp - sj * aQq, bQq = sj * aQp + cj * aQq;
-    // rows: J^T (A J) mixes rows P and Qr
-    double nPp = ci * bPp - si * bQp, nQp = si * bPp + ci * bQp;
-    double nPq = ci * bPq - si * bQq, nQq = si * bPq + ci * bQq;
-    if (i == j) {   // the annihilated entry of this pair's own 2 x 2 block
-      nQp = 0.0;
-      nPq = 0.0;
+  const double eps = 2.220446049250313e-16;
+  for (int sw = 0; sw < JAC_INNER_SWEEPS; ++sw) {
+    double off = 0.0, fro = 0.0;
+    for (int e = tid; e < JP * JP; e += 256) {
+      const int l = e % JP, m = e / JP;
+      const double v = S[l][m];
+      fro += v * v;
+      if (l != m) off += v * v;
     }
-    cp[P] = nPp;
-    cp[Qr] = nQp;
-    cq[P] = nPq;
-    cq[Qr] = nQq;
+    off = block_sum256(off, sh);
+    fro = block_sum256(fro, sh);
+    if (off <= 16.0 * eps * eps * fro) break;
+    for (int ri = 0; ri < JP - 1; ++ri) {
+      if (tid < JP / 2) {
+        const int p = rr_pos(tid, ri, JP), q = rr_pos(JP - 1 - tid, ri, JP);
+        double c, s;
+        jac_rot(S[p][p], S[q][q], S[q][p], c, s);
+        pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+      }
+      __syncthreads();
+      for (int e = tid; e < (JP / 2) * JP; e += 256) {   // columns p, q of S and of R
+        const int t = e / JP, i = e % JP, p = pp[t], q = qq[t];
+        const double c = cs[t], s = sn[t];
+        const double a = S[i][p], b = S[i][q];
+        S[i][p] = c * a - s * b;
+        S[i][q] = s * a + c * b;
+        const double ra = Rt[p][i], rbv = Rt[q][i];
+        Rt[p][i] = c * ra - s * rbv;
+        Rt[q][i] = s * ra + c * rbv;
+      }
+      __syncthreads();
+      for (int e = tid; e < (JP / 2) * JP; e += 256) {   // rows p, q of S
+        const int t = e / JP, i = e % JP, p = pp[t], q = qq[t];
+        const double c = cs[t], s = sn[t];
+        const double a = S[p][i], b = S[q][i];
+        S[p][i] = c * a - s * b;
+        S[q][i] = s * a + c * b;
+      }
+      __syncthreads();
+      if (tid < JP / 2) {
+        S[qq[tid]][pp[tid]] = 0.0;
+        S[pp[tid]][qq[tid]] = 0.0;
+      }
+      __syncthreads();
+    }
+  }
+  double *Rg = J.R + (size_t)j * JP * JP;
+  for (int e = tid; e < JP * JP; e += 256) Rg[e] = Rt[e / JP][e % JP];
+  if (tid < JP) J.lam[(size_t)j * JP + tid] = S[tid][tid];
+}
+
+// Columns of every pair: X[:, pair] <- X[:, pair] R for X = A (z even) and
+// X = V (z odd), one 64-row tile per workgroup.  Grid (ne / 64, nbk / 2, 2 B).
+__global__ __launch_bounds__(256) void jacobi_pair_cols_kernel(const JacDesc *__restrict__ jd, int r) {
+  const JacDesc J = jd[blockIdx.z >> 1];
+  double *X = (blockIdx.z & 1) ? J.V : J.A;
+  const int j = blockIdx.y, i0 = blockIdx.x * 64;
+  if (j >= J.nbk / 2 || i0 >= J.ne) return;
+  const int rb = r % (J.nbk - 1);
+  const int I = rr_pos(j, rb, J.nbk), K = rr_pos(J.nbk - 1 - j, rb, J.nbk);
+  __shared__ double Xt[64][JP + 1];   // Xt[row][l]
+  __shared__ double Rs[JP][JP + 1];   // Rs[l][m] = R(l, m)
+  const int tid = threadIdx.x;
+  const double *Rg = J.R + (size_t)j * JP * JP;
+  auto *Xg = gptr(X);
+  for (int e = tid; e < 64 * JP; e += 256) {
+    const int row = e % 64, l = e / 64;
+    Xt[row][l] = Xg[(size_t)pair_idx(l, I, K) * J.ne + i0 + row];
+    Rs[e % JP][e / JP] = Rg[e];
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < ne; i += 256) {
-    Ap[i] = cp[i];
-    Aq[i] = cq[i];
+  const int tr = tid & 15, tc = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int l = 0; l < JP; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = Xt[tr + 16 * u][l];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = Rs[l][tc + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
   }
-  if (threadIdx.x == 0) {
-    const int r1 = (r + 1) % (ne - 1);
-    sd_out[p] = cp[p];
-    sd_out[q] = cq[q];
-    sd_out[ne + p] = cp[rr_partner(p, r1, ne)];
-    sd_out[ne + q] = cq[rr_partner(q, r1, ne)];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const size_t col = (size_t)pair_idx(tc + 16 * v, I, K) * J.ne + i0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) Xg[col + tr + 16 * u] = acc[u][v];
+  }
+}
+
+// Rows of every pair: A[pair, :] <- R^T A[pair, :], one 64-column tile per
+// workgroup; where the tile's columns belong to the pair itself the block is
+// written as diag(lambda), its exact value up to the inner iteration's
+// rounding-level residual.  Grid (ne / 64, nbk / 2, B).
+__global__ __launch_bounds__(256) void jacobi_pair_rows_kernel(const JacDesc *__restrict__ jd, int r) {
+  const JacDesc J = jd[blockIdx.z];
+  const int j = blockIdx.y, c0 = blockIdx.x * 64;
+  if (j >= J.nbk / 2 || c0 >= J.ne) return;
+  const int rb = r % (J.nbk - 1);
+  const int I = rr_pos(j, rb, J.nbk), K = rr_pos(J.nbk - 1 - j, rb, J.nbk);
+  __shared__ double At[JP][64 + 1];   // At[l][col]
+  __shared__ double Rs[JP][JP + 1];   // Rs[l][m] = R(l, m)
+  const int tid = threadIdx.x;
+  const double *Rg = J.R + (size_t)j * JP * JP;
+  auto *Ag = gptr(J.A);
+  for (int e = tid; e < JP * 64; e += 256) {
+    const int l = e % JP, col = e / JP;
+    At[l][col] = Ag[(size_t)(c0 + col) * J.ne + pair_idx(l, I, K)];
+    Rs[e % JP][e / JP] = Rg[e];
+  }
+  __syncthreads();
+  const int tm = tid & 15, tcol = tid >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int l = 0; l < JP; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = Rs[l][tm + 16 * u];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = At[l][tcol + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+  }
+  const double *lam = J.lam + (size_t)j * JP;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int c = c0 + tcol + 16 * v;
+    const int cb = c / JB;
+    const bool own = cb == I || cb == K;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int m = tm + 16 * u, row = pair_idx(m, I, K);
+      Ag[(size_t)c * J.ne + row] = own ? (row == c ? lam[m] : 0.0) : acc[u][v];
+    }
   }
 }
 
@@ -280,27 +390,33 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
   std::vector<size_t> off(B);
   size_t total = 0;
   int ne_max = 0;
+  auto sizes = [&](int ne) {
+    const int nbk = ne / JB;
+    return 2 * a256(sizeof(double) * (size_t)ne * ne) + a256(sizeof(double) * (size_t)(nbk / 2) * JP * JP) +
+           a256(sizeof(double) * ((size_t)(nbk / 2) * JP + ne + 2 * JAC_NORM_BLOCKS)) + a256(sizeof(double) * 4);
+  };
   for (int b = 0; b < B; ++b) {
-    const int ne = n[b] + (n[b] & 1);
+    const int ne = round_up(n[b], JP);
     off[b] = total;
-    total += 2 * a256(sizeof(double) * (size_t)ne * ne) + a256(sizeof(double) * (5 * ne + 2 * JAC_NORM_BLOCKS)) +
-             a256(sizeof(double) * 4);
+    total += sizes(ne);
     ne_max = std::max(ne_max, ne);
   }
   if (!ctx.reserve(total)) return INLA_ERR_NOMEM;
   for (int b = 0; b < B; ++b) {
-    const int ne = n[b] + (n[b] & 1);
+    const int ne = round_up(n[b], JP);
     char *base = ctx.ws + off[b];
     JacDesc &J = hd[b];
-    J.Q = Q[b]; J.ldq = ldq[b]; J.P = P[b]; J.ldp = ldp[b]; J.n = n[b]; J.ne = ne;
+    J.Q = Q[b]; J.ldq = ldq[b]; J.P = P[b]; J.ldp = ldp[b]; J.n = n[b]; J.ne = ne; J.nbk = ne / JB;
     J.A = (double *)base;
     base += a256(sizeof(double) * (size_t)ne * ne);
     J.V = (double *)base;
     base += a256(sizeof(double) * (size_t)ne * ne);
-    J.side = (double *)base;
-    J.f = J.side + 4 * ne;
+    J.R = (double *)base;
+    base += a256(sizeof(double) * (size_t)(J.nbk / 2) * JP * JP);
+    J.lam = (double *)base;
+    J.f = J.lam + (size_t)(J.nbk / 2) * JP;
     J.part = J.f + ne;
-    base += a256(sizeof(double) * (5 * ne + 2 * JAC_NORM_BLOCKS));
+    base += a256(sizeof(double) * ((size_t)(J.nbk / 2) * JP + ne + 2 * JAC_NORM_BLOCKS));
     J.norms = (double *)base;
   }
   const JacDesc *dall = (const JacDesc *)ctx.upload(hd.data(), sizeof(JacDesc) * B);
@@ -312,19 +428,28 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
   for (int b = 0; b < B; ++b) { act[b] = b; sweeps[b] = 0; info[b] = INLA_INFO_OK; }
   std::vector<double> prev(B, std::numeric_limits<double>::infinity());
   std::vector<double> hn(4 * (size_t)B);
-  int r = 0;   // global round counter (keeps every matrix's schedule and side slot in step)
+  int r = 0;   // global round counter: every matrix takes its rounds in order (r mod (nbk - 1))
   for (int sw = 0; sw < JAC_MAX_SWEEPS && !act.empty(); ++sw) {
     std::vector<JacDesc> ha;
     int ne_act = 0;
     for (int b : act) { ha.push_back(hd[b]); ne_act = std::max(ne_act, hd[b].ne); }
     const JacDesc *da = (const JacDesc *)ctx.upload(ha.data(), sizeof(JacDesc) * ha.size());
     if (!da) return INLA_ERR_NOMEM;
-    const int nb = (int)ha.size();
-    const size_t lds = sizeof(double) * 2 * ne_act;
-    for (int k = 0; k < ne_act - 1; ++k, ++r) {
+    const int nb = (int)ha.size(), nbk = ne_act / JB, tiles = ne_act / 64;
+    // per round: columns of A and V (2 JP flops and 16 bytes per element each),
+    // then rows of A
+    const double round_flops = 6.0 * JP * (double)ne_act * ne_act * nb;
+    const double round_bytes = 48.0 * (double)ne_act * ne_act * nb;
+    for (int k = 0; k < nbk - 1; ++k, ++r) {
       const int rr = r;
-      ctx.launch(INLA_K_SOLVE, 6.0 * ne_act * ne_act * nb, 32.0 * ne_act * ne_act * nb, [&] {
-        hipLaunchKernelGGL(jacobi_round_kernel, dim3(ne_act / 2, nb), dim3(256), lds, ctx.stream, da, rr);
+      ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+        hipLaunchKernelGGL(jacobi_pair_eig_kernel, dim3(nbk / 2, nb), dim3(256), 0, ctx.stream, da, rr);
+      });
+      ctx.launch(INLA_K_SOLVE, round_flops * 2.0 / 3.0, round_bytes * 2.0 / 3.0, [&] {
+        hipLaunchKernelGGL(jacobi_pair_cols_kernel, dim3(tiles, nbk / 2, 2 * nb), dim3(256), 0, ctx.stream, da, rr);
+      });
+      ctx.launch(INLA_K_SOLVE, round_flops / 3.0, round_bytes / 3.0, [&] {
+        hipLaunchKernelGGL(jacobi_pair_rows_kernel, dim3(tiles, nbk / 2, nb), dim3(256), 0, ctx.stream, da, rr);
       });
     }
     ctx.launch(INLA_K_SOLVE, 0.0, 8.0 * ne_act * ne_act * nb, [&] {
@@ -346,15 +471,13 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
       if (!std::isfinite(off_) || !std::isfinite(fro)) { info[b] = INLA_INFO_NONFINITE; continue; }
       const double eps = std::numeric_limits<double>::epsilon();
       // converged: the off-diagonal part at the rounding level.  Clustered
-      // spectra pass through plateaus well above it (halving per sweep), so a
-      // sweep that no longer shrinks it ends the iteration only once it is
-      // already below 1e-14 of the matrix.
+      // spectra pass through plateaus well above it, so a sweep that no longer
+      // shrinks it ends the iteration only once it is already below 1e-14 of
+      // the matrix.
       const bool done = off_ <= 4.0 * eps * fro || (off_ <= 1e-14 * fro && off_ >= 0.9 * prev[b]);
       prev[b] = off_;
       if (!done) keep.push_back(b);
     }
-    // a matrix that keeps rotating resumes at round r, whose side slot its last
-    // round wrote
     act.swap(keep);
   }
   for (int b : act) info[b] = INLA_INFO_EIG_MAXIT;

@@ -138,7 +138,7 @@ def test_woodbury_warm_start_and_errors(lib):
     r3, _ = lib.woodbury_eval([dm], [float("nan")], P)
     assert r3[0]["info"] == -3
     with pytest.raises(LibraryError):
-        lib.pinv([dev(np.eye(4097))[:4097, :4097]])
+        lib.pinv([dev(np.zeros((0, 0)))])
 
 
 def test_woodbury_n3000(lib):
