@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__r
   }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
+  double prev = -1.0;
   for (int sw = 0; sw < JAC_INNER_SWEEPS; ++sw) {
     double off = 0.0, fro = 0.0;
     for (int e = tid; e < JP * JP; e += 256) {
@@ -133,7 +134,11 @@ __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__r
     }
     off = block_sum256(off, sh);
     fro = block_sum256(fro, sh);
-    if (off <= 16.0 * eps * eps * fro) break;
+    // converged, or settled on its rounding floor (a sweep that no longer
+    // shrinks the off-diagonal sum of squares fourfold once it is below 1e-24
+    // of the total)
+    if (off <= 16.0 * eps * eps * fro || (prev >= 0.0 && off <= 1e-24 * fro && off > 0.25 * prev)) break;
+    prev = off;
     for (int ri = 0; ri < JP - 1; ++ri) {
       if (tid < JP / 2) {
         const int p = rr_pos(tid, ri, JP), q = rr_pos(JP - 1 - tid, ri, JP);
@@ -153,17 +158,12 @@ __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__r
         Rt[q][i] = s * ra + c * rbv;
       }
       __syncthreads();
-      for (int e = tid; e < (JP / 2) * JP; e += 256) {   // rows p, q of S
+      for (int e = tid; e < (JP / 2) * JP; e += 256) {   // rows p, q of S; the pair's entry is annihilated
         const int t = e / JP, i = e % JP, p = pp[t], q = qq[t];
         const double c = cs[t], s = sn[t];
         const double a = S[p][i], b = S[q][i];
-        S[p][i] = c * a - s * b;
-        S[q][i] = s * a + c * b;
-      }
-      __syncthreads();
-      if (tid < JP / 2) {
-        S[qq[tid]][pp[tid]] = 0.0;
-        S[pp[tid]][qq[tid]] = 0.0;
+        S[p][i] = i == q ? 0.0 : c * a - s * b;
+        S[q][i] = i == p ? 0.0 : s * a + c * b;
       }
       __syncthreads();
     }
