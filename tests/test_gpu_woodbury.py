@@ -300,3 +300,31 @@ def test_type4_table3_first_size(lib):
     assert dx_ref <= tol_x and dx_krig <= tol_x
     assert abs(res[0]["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
     assert abs(res[0]["objective"] - rk[0]["objective"]) <= 1e-9 * abs(rk[0]["objective"])
+
+
+def test_woodbury_mixed_batch(lib):
+    """One call holding an A = I model and two general-A models of different
+    sizes (uneven observation and latent spaces): each result against the
+    reference, and the variances of all three."""
+    from paper_2311_08050_amd.binding import DeviceModel
+    models = [synth.rw1_besag(13, 7, seed=90), synth.type4(12, 5, seed=91, graph="delaunay"),
+              synth.type4(20, 6, seed=92, graph="delaunay")]
+    thetas = [synth.rw1_besag_theta0(7) + np.array([0.1, 0.05]),
+              synth.type4_theta0() + np.array([0.1, 0.2, -0.1, 0.0]),
+              synth.type4_theta0() + np.array([-0.2, 0.1, 0.2, 0.0])]
+    lp = [thetas[0][1], thetas[1][3], thetas[2][3]]
+    P, ranks, _, info = lib.pinv([dev(WB.prior_precision(m, th)) for m, th in zip(models, thetas)])
+    assert np.all(info == 0)
+    dms = [DeviceModel(m) for m in models]
+    res, xs = lib.woodbury_eval(dms, lp, P)
+    var, vinfo = lib.woodbury_var(dms, lp, P, xs)
+    assert np.all(vinfo == 0)
+    for m, th, r, x, v, Pk in zip(models, thetas, res, xs, var, P):
+        ref = WB.laplace_eval(m, th)
+        say(f"mixed batch: n={m['n']} m={m.get('m') or m['n']} GPU {r['iters']} it {r['objective']:.10f}, "
+            f"reference {ref['iters']} it {ref['objective']:.10f}")
+        assert r["info"] == 0 and ref["info"] == 0
+        assert np.max(np.abs(x.cpu().numpy() - ref["x"])) <= 1e-9 * max(1.0, np.max(np.abs(ref["x"])))
+        assert abs(r["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
+        scale = np.max(np.diag(Pk.cpu().numpy()))
+        assert np.max(np.abs(v.cpu().numpy() - np.diag(ref["Sigma"]))) <= 1e-10 * scale
