@@ -429,6 +429,49 @@ int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, cons
 int inla_woodbury_var(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,
                       const double *const *x_mode, double *const *var, int32_t *info);
 
+/* A prior given through the Moore-Penrose inverses of its diagonal blocks, for
+ * Stage 1 on the Moore-Penrose route (section "Bypassing constraints
+ * complexity ..."): Q_prior(theta) = blockdiag_k(tau_k R_k), so
+ * Q_prior(theta)^+ = blockdiag_k(R_k^+ / tau_k) with tau_k = exp(theta[tau_index[k]]),
+ * or a fixed 1 / tau_k = fixed_scale[k] where tau_index[k] < 0.  The blocks
+ * tile [0, n) without gaps or overlaps (any order).  The likelihood parameter
+ * is theta[lik_index], or lik_value where lik_index < 0.  All arrays are host
+ * arrays; P[k] are device pointers to R_k^+ (column-major, ld[k] >= size[k]),
+ * read only. */
+typedef struct inla_pinv_prior {
+  int32_t n_blocks;
+  const int32_t *offset;
+  const int32_t *size;
+  const double *const *P;
+  const int32_t *ld;
+  const int32_t *tau_index;
+  const double *fixed_scale;
+  int32_t lik_index;
+  int32_t reserved;
+  double lik_value;
+} inla_pinv_prior;
+
+/* Q_prior(theta_b)^+ for B points (theta row-major, stride ldtheta), written
+ * full n x n (column-major, ld n) to the device arrays out[b].  Returns -3 for
+ * an invalid prior description (blocks not tiling [0, n), a null pointer, an
+ * index outside theta), -i for another invalid i-th argument. */
+int inla_pinv_prior_assemble(inla_handle *h, const inla_pinv_prior *prior, int32_t n, int32_t B, const double *theta,
+                             int32_t ldtheta, double *const *out);
+/* inla_theta_mode / inla_theta_hessian with every evaluation on the
+ * Moore-Penrose route: each batch of points gets Q_prior(theta)^+ from `prior`
+ * (device workspace of n^2 doubles per point) and is evaluated by
+ * inla_woodbury_eval.  model: prior INLA_PRIOR_PINV, k = 0 (its Qprior and ldq
+ * are ignored); t is the dimension of theta (every tau_index and lik_index
+ * below t).  Other arguments and results as for inla_theta_mode and
+ * inla_theta_hessian. */
+int inla_theta_mode_pinv(inla_handle *h, const inla_model *model, const inla_pinv_prior *prior, int32_t t,
+                         const double *theta0, const inla_theta_opts *opts, inla_log_prior_fn log_prior, void *user,
+                         double *theta_star, double *f_star, double *grad, int32_t *iters, int32_t *evals,
+                         int32_t *info);
+int inla_theta_hessian_pinv(inla_handle *h, const inla_model *model, const inla_pinv_prior *prior, int32_t t,
+                            const double *theta, double step, const inla_opts *opts, inla_log_prior_fn log_prior,
+                            void *user, double *neg_hess, double *log_post, int32_t *info);
+
 /* ------------------------------------------------------------ profiling */
 /* Kernel classes timed when profiling is on. */
 enum {

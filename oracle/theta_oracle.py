@@ -34,9 +34,11 @@ from . import inla_oracle as O
 OK, MAXIT, LINESEARCH, EVAL_FAILED = 0, 1, 2, 3
 
 
-def neg_log_post(model, theta, log_prior=None):
-    """f(theta) = -(log pi~(y | theta) + log pi(theta)); +inf if the evaluation fails."""
-    r = O.laplace_eval(model, np.asarray(theta, dtype=np.float64))
+def neg_log_post(model, theta, log_prior=None, laplace=None):
+    """f(theta) = -(log pi~(y | theta) + log pi(theta)); +inf if the evaluation
+    fails.  `laplace(model, theta)` evaluates log pi~(y | theta) (default: the
+    kriging route of ``inla_oracle``; the Moore-Penrose route passes its own)."""
+    r = (laplace or O.laplace_eval)(model, np.asarray(theta, dtype=np.float64))
     lp = 0.0 if log_prior is None else float(log_prior(np.asarray(theta)))
     if r["info"] != 0 or not np.isfinite(r["objective"]) or not np.isfinite(lp):
         return math.inf
@@ -53,10 +55,11 @@ def central_gradient(f, theta, h):
     return g
 
 
-def theta_mode(model, theta0, log_prior=None, h=1e-3, gtol=1e-3, ftol=1e-12, max_iter=100, max_step=1.0):
+def theta_mode(model, theta0, log_prior=None, h=1e-3, gtol=1e-3, ftol=1e-12, max_iter=100, max_step=1.0,
+               laplace=None):
     """BFGS minimisation of -log pi~(theta | y).  Returns a dict with theta,
     log_post (= log pi~ at theta), grad (of log pi~), iters, info."""
-    f = lambda th: neg_log_post(model, th, log_prior)   # noqa: E731
+    f = lambda th: neg_log_post(model, th, log_prior, laplace)   # noqa: E731
     th = np.asarray(theta0, dtype=np.float64).copy()
     t = len(th)
     fx = f(th)
@@ -115,10 +118,10 @@ def theta_mode(model, theta0, log_prior=None, h=1e-3, gtol=1e-3, ftol=1e-12, max
     return {"theta": th, "log_post": -fx, "grad": -g, "iters": it, "info": status}
 
 
-def neg_hessian(model, theta, log_prior=None, h=5e-3):
+def neg_hessian(model, theta, log_prior=None, h=5e-3, laplace=None):
     """-d^2 log pi~(theta | y) by central differences (diagonal three-point,
     off-diagonal four-point stencil)."""
-    f = lambda th: neg_log_post(model, th, log_prior)   # noqa: E731
+    f = lambda th: neg_log_post(model, th, log_prior, laplace)   # noqa: E731
     th = np.asarray(theta, dtype=np.float64)
     t = len(th)
     f0 = f(th)

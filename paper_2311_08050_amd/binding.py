@@ -38,6 +38,7 @@ EXPORTS = [
     "inla_set_graphs", "inla_set_lookahead", "inla_graph_stats",
     "inla_vb_mean", "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
     "inla_pinv", "inla_woodbury_eval", "inla_woodbury_var",
+    "inla_pinv_prior_assemble", "inla_theta_mode_pinv", "inla_theta_hessian_pinv",
 ]
 # Autotuner candidates (nb, tm) without lookahead, in the order inla_autotune
 # reports their times; the fastest is then timed with lookahead as well.
@@ -76,6 +77,34 @@ class Result(C.Structure):
 class ThetaOpts(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("reserved", C.c_int32), ("h", C.c_double), ("gtol", C.c_double),
                 ("ftol", C.c_double), ("max_step", C.c_double), ("eval", Opts)]
+
+
+class PinvPriorStruct(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("offset", C.POINTER(C.c_int32)), ("size", C.POINTER(C.c_int32)),
+                ("P", C.POINTER(C.c_void_p)), ("ld", C.POINTER(C.c_int32)), ("tau_index", C.POINTER(C.c_int32)),
+                ("fixed_scale", C.POINTER(C.c_double)), ("lik_index", C.c_int32), ("reserved", C.c_int32),
+                ("lik_value", C.c_double)]
+
+
+class PinvPrior:
+    """A prior given through its diagonal blocks' pseudo-inverses (inla_pinv_prior):
+    blocks is a list of dicts {"offset", "P" (square float64 device tensor R_k^+),
+    "tau_index" (theta component of log tau_k, or -1), "fixed_scale" (1 / tau_k
+    for tau_index -1)}; the likelihood parameter is theta[lik_index], or
+    lik_value for lik_index -1.  Keeps its arrays alive."""
+
+    def __init__(self, blocks, lik_index=-1, lik_value=0.0):
+        k = len(blocks)
+        self.tensors = [b["P"] for b in blocks]
+        self._off = (C.c_int32 * k)(*[int(b["offset"]) for b in blocks])
+        self._size = (C.c_int32 * k)(*[int(b["P"].shape[0]) for b in blocks])
+        self._ptr = (C.c_void_p * k)(*[b["P"].data_ptr() for b in blocks])
+        self._ld = (C.c_int32 * k)(*[int(b["P"].shape[0]) for b in blocks])
+        self._tau = (C.c_int32 * k)(*[int(b.get("tau_index", -1)) for b in blocks])
+        self._fix = (C.c_double * k)(*[float(b.get("fixed_scale", 0.0)) for b in blocks])
+        self.struct = PinvPriorStruct(n_blocks=k, offset=self._off, size=self._size, P=self._ptr, ld=self._ld,
+                                      tau_index=self._tau, fixed_scale=self._fix, lik_index=int(lik_index),
+                                      reserved=0, lik_value=float(lik_value))
 
 
 LOG_PRIOR_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_int32, C.c_void_p)
@@ -126,6 +155,12 @@ def load_library(path: str = LIBPATH):
                                     pi32, pi32, pi32]
     lib.inla_theta_hessian.argtypes = [P, C.POINTER(Model), i32, pd, C.c_double, C.POINTER(Opts), LOG_PRIOR_FN, P, pd,
                                        pd, pi32]
+    pp = C.POINTER(PinvPriorStruct)
+    lib.inla_pinv_prior_assemble.argtypes = [P, pp, i32, i32, pd, i32, C.POINTER(P)]
+    lib.inla_theta_mode_pinv.argtypes = [P, C.POINTER(Model), pp, i32, pd, C.POINTER(ThetaOpts), LOG_PRIOR_FN, P, pd,
+                                         pd, pd, pi32, pi32, pi32]
+    lib.inla_theta_hessian_pinv.argtypes = [P, C.POINTER(Model), pp, i32, pd, C.c_double, C.POINTER(Opts),
+                                            LOG_PRIOR_FN, P, pd, pd, pi32]
     lib.inla_ccd_design.argtypes = [i32, C.c_double, pi32, pd, pd]
     lib.inla_ccd_points.argtypes = [i32, pd, pd, C.c_double, pi32, pd, pd]
     lib.inla_ccd_weights.argtypes = [i32, pd, pd, pd]
@@ -365,6 +400,59 @@ class Library:
                                          self._prior(log_prior), None, H.ctypes.data_as(pd), C.byref(lp),
                                          C.byref(info))
         self._check(rc, "inla_theta_hessian")
+        return H, lp.value, info.value
+
+    @staticmethod
+    def _pinv_model_struct(dmodel):
+        s = Model.from_buffer_copy(dmodel.struct)
+        s.prior, s.k, s.C, s.e = 3, 0, None, None
+        return s
+
+    def pinv_prior_assemble(self, prior, n, thetas):
+        """Q_prior(theta_b)^+ (n x n device tensors) for the rows of thetas."""
+        th = np.ascontiguousarray(np.atleast_2d(np.asarray(thetas, dtype=np.float64)))
+        B = th.shape[0]
+        out = [self.torch.empty((n, n), dtype=self.torch.float64, device="cuda") for _ in range(B)]
+        ptrs = (C.c_void_p * B)(*[o.data_ptr() for o in out])
+        rc = self.lib.inla_pinv_prior_assemble(self.h, C.byref(prior.struct), n, B,
+                                               th.ctypes.data_as(C.POINTER(C.c_double)), th.shape[1], ptrs)
+        self._check(rc, "inla_pinv_prior_assemble")
+        return out
+
+    def theta_mode_pinv(self, dmodel, prior, theta0, log_prior=None, max_iter=0, h=0.0, gtol=0.0, ftol=0.0,
+                        max_step=0.0):
+        """inla_theta_mode on the Moore-Penrose route (inla_theta_mode_pinv)."""
+        th0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        t = len(th0)
+        o = ThetaOpts(max_iter=max_iter, reserved=0, h=h, gtol=gtol, ftol=ftol, max_step=max_step,
+                      eval=Opts(prec=0, max_iter=0, tol=0.0, start=0, reserved=0))
+        cb = self._prior(log_prior)
+        out, grad = np.zeros(t), np.zeros(t)
+        fs = C.c_double()
+        it, ev, info = C.c_int32(), C.c_int32(), C.c_int32()
+        pd = C.POINTER(C.c_double)
+        ms = self._pinv_model_struct(dmodel)
+        rc = self.lib.inla_theta_mode_pinv(self.h, C.byref(ms), C.byref(prior.struct), t, th0.ctypes.data_as(pd),
+                                           C.byref(o), cb, None, out.ctypes.data_as(pd), C.byref(fs),
+                                           grad.ctypes.data_as(pd), C.byref(it), C.byref(ev), C.byref(info))
+        self._check(rc, "inla_theta_mode_pinv")
+        return {"theta": out, "log_post": fs.value, "grad": grad, "iters": it.value, "evals": ev.value,
+                "info": info.value}
+
+    def theta_hessian_pinv(self, dmodel, prior, theta, step=0.0, log_prior=None):
+        """(negative Hessian, log pi~ at theta, info) on the Moore-Penrose route."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        t = len(th)
+        H = np.zeros((t, t))
+        lp = C.c_double()
+        info = C.c_int32()
+        o = Opts(prec=0, max_iter=0, tol=0.0, start=0, reserved=0)
+        pd = C.POINTER(C.c_double)
+        ms = self._pinv_model_struct(dmodel)
+        rc = self.lib.inla_theta_hessian_pinv(self.h, C.byref(ms), C.byref(prior.struct), t, th.ctypes.data_as(pd),
+                                              step, C.byref(o), self._prior(log_prior), None, H.ctypes.data_as(pd),
+                                              C.byref(lp), C.byref(info))
+        self._check(rc, "inla_theta_hessian_pinv")
         return H, lp.value, info.value
 
     def ccd_points(self, theta_star, neg_hess, f0=1.1):

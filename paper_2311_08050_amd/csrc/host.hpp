@@ -132,6 +132,15 @@ int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, T
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+// The handle's context (C-ABI handles wrap one Ctx).
+Ctx *handle_ctx(inla_handle *h);
+// Block-structured pseudo-inverse priors (woodbury.hip): validation for order n
+// and theta dimension t (t < 0: unchecked), 0 or -3; and Q_prior(theta_b)^+ for B
+// points into the device arrays out[b] (n x n, ld n).
+int pinv_prior_check(const inla_pinv_prior *pp, int n, int t);
+int pinv_prior_assemble(Ctx &ctx, const inla_pinv_prior &pp, int n, int B, const double *theta, int ldtheta,
+                        double *const *out);
+
 // Small dense symmetric eigen-decomposition (host) and the Gauss-Hermite rule
 // built on it (nodes, then weights / sqrt(pi)).
 void sym_eigen(int t, std::vector<double> A, std::vector<double> &w, std::vector<double> &V);

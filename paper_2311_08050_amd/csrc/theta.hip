@@ -5,8 +5,10 @@
 // "Hyperparameter exploration"; appendix "Marginal posteriors of the
 // hyperparameters", Eq. (41) and the z-parameterisation that follows it).
 //
-// Host code only: every objective value comes from inla_laplace_eval, and every
-// gradient, line search and Hessian stencil is one batched call.
+// Host code only: every objective value comes from inla_laplace_eval (or, on the
+// Moore-Penrose route, from inla_woodbury_eval after Q_prior(theta)^+ is
+// assembled from the prior's block pseudo-inverses), and every gradient, line
+// search and Hessian stencil is one batched call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -15,6 +17,7 @@
 #include <vector>
 
 #include "../../include/inla_dense.h"
+#include "host.hpp"
 
 namespace inla {
 hipStream_t handle_stream(inla_handle *h);
@@ -35,12 +38,32 @@ struct Evaluator {
   int cap = 0;
   bool have_centre = false;
   int evals = 0;
+  // Moore-Penrose route: the prior's block pseudo-inverses, and device room for
+  // Q_prior(theta)^+ of each point of a batch ([qcap][n][n])
+  const inla_pinv_prior *pp = nullptr;
+  double *qbuf = nullptr;
+  int qcap = 0;
 
   ~Evaluator() {
-    if (xbuf) {
-      (void)hipStreamSynchronize(inla::handle_stream(h));
-      (void)hipFree(xbuf);
+    if (xbuf || qbuf) (void)hipStreamSynchronize(inla::handle_stream(h));
+    if (xbuf) (void)hipFree(xbuf);
+    if (qbuf) (void)hipFree(qbuf);
+  }
+  int ensure_q(int B) {
+    if (B <= qcap) return INLA_OK;
+    if (qbuf) {
+      if (hipStreamSynchronize(inla::handle_stream(h)) != hipSuccess) return INLA_ERR_HIP;
+      (void)hipFree(qbuf);
+      qbuf = nullptr;
+      qcap = 0;
     }
+    if (hipMalloc(&qbuf, sizeof(double) * (size_t)B * n * n) != hipSuccess) {
+      (void)hipGetLastError();
+      qbuf = nullptr;
+      return INLA_ERR_NOMEM;
+    }
+    qcap = B;
+    return INLA_OK;
   }
   double *centre() { return xbuf + (size_t)cap * n; }
   int ensure(int B) {
@@ -78,7 +101,21 @@ struct Evaluator {
     std::vector<inla_result> r(B);
     inla_opts o = eo;
     o.start = have_centre ? 1 : 0;
-    rc = inla_laplace_eval(h, B, ms.data(), th, t, xs.data(), &o, r.data());
+    if (pp) {
+      if ((rc = ensure_q(B))) return rc;
+      std::vector<double *> qs(B);
+      std::vector<double> lik(B);
+      for (int b = 0; b < B; ++b) {
+        qs[b] = qbuf + (size_t)b * n * n;
+        ms[b].Qprior = qs[b];
+        ms[b].ldq = n;
+        lik[b] = pp->lik_index >= 0 ? th[(size_t)b * t + pp->lik_index] : pp->lik_value;
+      }
+      if ((rc = inla::pinv_prior_assemble(*inla::handle_ctx(h), *pp, n, B, th, t, qs.data()))) return rc;
+      rc = inla_woodbury_eval(h, B, ms.data(), lik.data(), 1, xs.data(), &o, r.data());
+    } else {
+      rc = inla_laplace_eval(h, B, ms.data(), th, t, xs.data(), &o, r.data());
+    }
     if (rc) return rc;
     for (int b = 0; b < B; ++b) {
       const double prior = lp ? lp(th + (size_t)b * t, t, user) : 0.0;
@@ -187,25 +224,16 @@ std::vector<double> gauss_hermite(int d) {
 
 using inla::sym_eigen;
 
-extern "C" {
+namespace {
 
-int inla_theta_mode(inla_handle *h, const inla_model *model, int32_t t, const double *theta0,
-                    const inla_theta_opts *opts, inla_log_prior_fn log_prior, void *user, double *theta_star,
-                    double *f_star, double *grad, int32_t *iters, int32_t *evals, int32_t *info) {
-  if (!h) return -1;
-  if (!model) return -2;
-  if (t != n_prior_params(model->prior) + 1) return -3;
-  if (!theta0) return -4;
-  if (!theta_star) return -8;
-  for (int i = 0; i < t; ++i)
-    if (!std::isfinite(theta0[i])) return -4;
+// BFGS for the mode of log pi~(theta | y) with the evaluator's route.
+int theta_mode_run(Evaluator &ev, int32_t t, const double *theta0, const inla_theta_opts *opts, double *theta_star,
+                   double *f_star, double *grad, int32_t *iters, int32_t *evals, int32_t *info) {
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 100;
   const double hd = (opts && opts->h > 0) ? opts->h : 1e-3;
   const double gtol = (opts && opts->gtol > 0) ? opts->gtol : 1e-3;
   const double ftol = (opts && opts->ftol > 0) ? opts->ftol : 1e-12;
   const double max_step = (opts && opts->max_step > 0) ? opts->max_step : 1.0;
-  Evaluator ev{h, model, t, model->n, opts ? opts->eval : inla_opts{}, log_prior, user};
-  ev.eo.start = 0;
   int status = INLA_THETA_MAXIT, it = 0;
   std::vector<double> th(theta0, theta0 + t), g, gn, Hi((size_t)t * t, 0.0);
   double f = 0.0;
@@ -311,17 +339,9 @@ int inla_theta_mode(inla_handle *h, const inla_model *model, int32_t t, const do
   return INLA_OK;
 }
 
-int inla_theta_hessian(inla_handle *h, const inla_model *model, int32_t t, const double *theta, double step,
-                       const inla_opts *opts, inla_log_prior_fn log_prior, void *user, double *neg_hess,
-                       double *log_post, int32_t *info) {
-  if (!h) return -1;
-  if (!model) return -2;
-  if (t != n_prior_params(model->prior) + 1) return -3;
-  if (!theta) return -4;
-  if (!(step > 0)) step = 5e-3;
-  if (!neg_hess) return -9;
-  Evaluator ev{h, model, t, model->n, opts ? *opts : inla_opts{}, log_prior, user};
-  ev.eo.start = 0;
+// Central-difference negative Hessian of log pi~(theta | y) with the evaluator's route.
+int theta_hessian_run(Evaluator &ev, int32_t t, const double *theta, double step, double *neg_hess, double *log_post,
+                      int32_t *info) {
   double f0 = 0.0;
   int rc = ev.eval(1, theta, &f0);
   if (rc) return rc;
@@ -364,6 +384,75 @@ int inla_theta_hessian(inla_handle *h, const inla_model *model, int32_t t, const
     }
   if (log_post) *log_post = -f0;
   return INLA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int inla_theta_mode(inla_handle *h, const inla_model *model, int32_t t, const double *theta0,
+                    const inla_theta_opts *opts, inla_log_prior_fn log_prior, void *user, double *theta_star,
+                    double *f_star, double *grad, int32_t *iters, int32_t *evals, int32_t *info) {
+  if (!h) return -1;
+  if (!model) return -2;
+  if (t != n_prior_params(model->prior) + 1) return -3;
+  if (!theta0) return -4;
+  if (!theta_star) return -8;
+  for (int i = 0; i < t; ++i)
+    if (!std::isfinite(theta0[i])) return -4;
+  Evaluator ev{h, model, t, model->n, opts ? opts->eval : inla_opts{}, log_prior, user};
+  ev.eo.start = 0;
+  return theta_mode_run(ev, t, theta0, opts, theta_star, f_star, grad, iters, evals, info);
+}
+
+static bool pinv_model_ok(const inla_model *m) { return m->prior == INLA_PRIOR_PINV && m->k == 0 && m->n >= 1; }
+
+int inla_theta_mode_pinv(inla_handle *h, const inla_model *model, const inla_pinv_prior *prior, int32_t t,
+                         const double *theta0, const inla_theta_opts *opts, inla_log_prior_fn log_prior, void *user,
+                         double *theta_star, double *f_star, double *grad, int32_t *iters, int32_t *evals,
+                         int32_t *info) {
+  if (!h) return -1;
+  if (!model || !pinv_model_ok(model)) return -2;
+  if (t < 1) return -4;
+  if (inla::pinv_prior_check(prior, model->n, t)) return -3;
+  if (!theta0) return -5;
+  if (!theta_star) return -9;
+  for (int i = 0; i < t; ++i)
+    if (!std::isfinite(theta0[i])) return -5;
+  Evaluator ev{h, model, t, model->n, opts ? opts->eval : inla_opts{}, log_prior, user};
+  ev.eo.start = 0;
+  ev.pp = prior;
+  return theta_mode_run(ev, t, theta0, opts, theta_star, f_star, grad, iters, evals, info);
+}
+
+int inla_theta_hessian(inla_handle *h, const inla_model *model, int32_t t, const double *theta, double step,
+                       const inla_opts *opts, inla_log_prior_fn log_prior, void *user, double *neg_hess,
+                       double *log_post, int32_t *info) {
+  if (!h) return -1;
+  if (!model) return -2;
+  if (t != n_prior_params(model->prior) + 1) return -3;
+  if (!theta) return -4;
+  if (!(step > 0)) step = 5e-3;
+  if (!neg_hess) return -9;
+  Evaluator ev{h, model, t, model->n, opts ? *opts : inla_opts{}, log_prior, user};
+  ev.eo.start = 0;
+  return theta_hessian_run(ev, t, theta, step, neg_hess, log_post, info);
+}
+
+int inla_theta_hessian_pinv(inla_handle *h, const inla_model *model, const inla_pinv_prior *prior, int32_t t,
+                            const double *theta, double step, const inla_opts *opts, inla_log_prior_fn log_prior,
+                            void *user, double *neg_hess, double *log_post, int32_t *info) {
+  if (!h) return -1;
+  if (!model || !pinv_model_ok(model)) return -2;
+  if (t < 1) return -4;
+  if (inla::pinv_prior_check(prior, model->n, t)) return -3;
+  if (!theta) return -5;
+  if (!(step > 0)) step = 5e-3;
+  if (!neg_hess) return -10;
+  Evaluator ev{h, model, t, model->n, opts ? *opts : inla_opts{}, log_prior, user};
+  ev.eo.start = 0;
+  ev.pp = prior;
+  return theta_hessian_run(ev, t, theta, step, neg_hess, log_post, info);
 }
 
 int inla_ccd_design(int32_t t, double f0, int32_t *n_points, double *z, double *delta) {

@@ -25,6 +25,7 @@
 // diag(Sigma*) factor M once more with the n border rows Q^+ S.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <limits>
 #include <vector>
@@ -1114,6 +1115,74 @@ static int woodbury_var(Ctx &ctx, int B, const inla_model *models, const double 
   return ctx.check();
 }
 
+// ------------------------------------------------------------------ block-structured Q^+(theta)
+struct PinvBlock {
+  const double *P;
+  int off, size, ld, pad_;
+};
+
+// out_b = blockdiag_k(scale[b][k] P_k), full n x n (ld n).  Grid (n / 256, n, B).
+__global__ __launch_bounds__(256) void pinv_prior_kernel(const PinvBlock *__restrict__ blk, int nblk,
+                                                         const double *__restrict__ scale, int n,
+                                                         double *const *__restrict__ out) {
+  const int j = blockIdx.y, b = blockIdx.z, i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n || j >= n) return;
+  double v = 0.0;
+  for (int k = 0; k < nblk; ++k) {
+    const PinvBlock &B = blk[k];
+    if (j >= B.off && j < B.off + B.size) {
+      if (i >= B.off && i < B.off + B.size)
+        v = scale[(size_t)b * nblk + k] * B.P[(size_t)(j - B.off) * B.ld + (i - B.off)];
+      break;
+    }
+  }
+  out[b][(size_t)j * n + i] = v;
+}
+
+// 0 if the description is valid for order n and theta dimension t (t < 0: not
+// checked), else -3.
+int pinv_prior_check(const inla_pinv_prior *pp, int n, int t) {
+  if (!pp || pp->n_blocks < 1 || !pp->offset || !pp->size || !pp->P || !pp->ld || !pp->tau_index) return -3;
+  std::vector<std::pair<int, int>> iv;
+  for (int k = 0; k < pp->n_blocks; ++k) {
+    if (pp->size[k] < 1 || pp->offset[k] < 0 || !pp->P[k] || pp->ld[k] < pp->size[k]) return -3;
+    if (pp->tau_index[k] < 0 && (!pp->fixed_scale || !std::isfinite(pp->fixed_scale[k]))) return -3;
+    if (t >= 0 && pp->tau_index[k] >= t) return -3;
+    iv.push_back({pp->offset[k], pp->size[k]});
+  }
+  std::sort(iv.begin(), iv.end());
+  int pos = 0;
+  for (auto &q : iv) {
+    if (q.first != pos) return -3;
+    pos += q.second;
+  }
+  if (pos != n) return -3;
+  if (t >= 0 && pp->lik_index >= t) return -3;
+  if (pp->lik_index < 0 && !std::isfinite(pp->lik_value)) return -3;
+  return 0;
+}
+
+int pinv_prior_assemble(Ctx &ctx, const inla_pinv_prior &pp, int n, int B, const double *theta, int ldtheta,
+                        double *const *out) {
+  const int nb = pp.n_blocks;
+  std::vector<PinvBlock> hb(nb);
+  for (int k = 0; k < nb; ++k) hb[k] = PinvBlock{pp.P[k], pp.offset[k], pp.size[k], pp.ld[k], 0};
+  std::vector<double> sc((size_t)B * nb);
+  for (int b = 0; b < B; ++b)
+    for (int k = 0; k < nb; ++k)
+      sc[(size_t)b * nb + k] = pp.tau_index[k] >= 0 ? std::exp(-theta[(size_t)b * ldtheta + pp.tau_index[k]])
+                                                    : pp.fixed_scale[k];
+  const PinvBlock *db = (const PinvBlock *)ctx.upload(hb.data(), sizeof(PinvBlock) * nb);
+  const double *ds = (const double *)ctx.upload(sc.data(), sizeof(double) * sc.size());
+  double *const *dout = (double *const *)ctx.upload(out, sizeof(double *) * B);
+  if (!db || !ds || !dout) return INLA_ERR_NOMEM;
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 8.0 * n * (double)n * B, [&] {
+    hipLaunchKernelGGL(pinv_prior_kernel, dim3((n + 255) / 256, n, B), dim3(256), 0, ctx.stream, db, nb, ds, n,
+                       dout);
+  });
+  return ctx.check();
+}
+
 }  // namespace inla
 
 extern "C" {
@@ -1163,6 +1232,21 @@ int inla_woodbury_var(inla_handle *h, int32_t B, const inla_model *models, const
   for (int b = 0; b < B; ++b)
     if (!wb_design_ok(models[b])) return -3;
   return woodbury_var(*handle_ctx(h), B, models, theta, ldtheta, x_mode, var, info);
+}
+
+int inla_pinv_prior_assemble(inla_handle *h, const inla_pinv_prior *prior, int32_t n, int32_t B, const double *theta,
+                             int32_t ldtheta, double *const *out) {
+  using namespace inla;
+  if (!h) return -1;
+  if (n < 1) return -3;
+  if (B < 0) return -4;
+  if (!theta || ldtheta < 1) return -5;
+  if (pinv_prior_check(prior, n, ldtheta)) return -2;
+  if (B == 0) return INLA_OK;
+  if (!out) return -7;
+  for (int b = 0; b < B; ++b)
+    if (!out[b]) return -7;
+  return pinv_prior_assemble(*handle_ctx(h), *prior, n, B, theta, ldtheta, out);
 }
 
 int inla_woodbury_eval(inla_handle *h, int32_t B, const inla_model *models, const double *theta, int32_t ldtheta,

@@ -48,7 +48,8 @@ def test_struct_layouts(tmp_path):
 
     from paper_2311_08050_amd import binding
     pairs = [("inla_model", binding.Model), ("inla_opts", binding.Opts), ("inla_result", binding.Result),
-             ("inla_kstats", binding.KStats), ("inla_theta_opts", binding.ThetaOpts)]
+             ("inla_kstats", binding.KStats), ("inla_theta_opts", binding.ThetaOpts),
+             ("inla_pinv_prior", binding.PinvPriorStruct)]
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
     for cname, cls in pairs:
         lines.append(f'  printf("%zu\\n", sizeof({cname}));')
