@@ -239,6 +239,7 @@ def run_extras(lib, binding, synth, dms, thetas, xs):
     log(f"stage 1 at n=3000: {t1 - t0:.2f} s ({g['iters']} iterations), Hessian + CCD {t2 - t1:.2f} s")
     out["moore_penrose_n3000"] = run_moore_penrose(lib, binding, synth)
     out["table3_type4"] = run_table3(lib, binding, synth)
+    out["stage1_type4_moore_penrose"] = run_stage1_type4(lib, binding, synth)
     return out
 
 
@@ -377,6 +378,52 @@ def run_table3(lib, binding, synth, B=8, sizes=((200, 5), (400, 5), (800, 5))):
                         "N(theta0, 0.3^2 I) per size", "rows": out, "precision": "fp64"}
 
 
+def run_stage1_type4(lib, binding, synth, n_s=200, n_t=5):
+    """Stage 1 and the CCD exploration on the Moore-Penrose route for the Type IV
+    model at the simulation table's first size (s = 1207, k = 406 implicit
+    constraints): block pseudo-inverses of the three structures (one batched
+    call), BFGS mode and Hessian of log pi~(theta | y) over theta = (log tau_time,
+    log tau_space, log tau_interaction) with a N(theta0, I) log prior, the CCD
+    points, their Woodbury evaluations and weights.  FP64."""
+    import numpy as np
+    import torch
+    m = synth.type4(n_s, n_t, seed=90 + n_s)
+    th0 = synth.type4_theta0()[:3]
+    blocks, _, _ = type4_inputs(m, np.r_[th0, 0.0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P, _, sweeps, pinfo = lib.pinv([torch.as_tensor(b).cuda() for b in blocks])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    one = torch.ones((1, 1), dtype=torch.float64, device="cuda")
+    c = m["fixed_precision"]
+    prior = binding.PinvPrior([{"offset": 0, "P": one, "tau_index": -1, "fixed_scale": 1.0 / c},
+                               {"offset": 1, "P": one, "tau_index": -1, "fixed_scale": 1.0 / c},
+                               {"offset": 2, "P": P[0], "tau_index": 0},
+                               {"offset": 2 + n_t, "P": P[1], "tau_index": 1},
+                               {"offset": 2 + n_t + n_s, "P": P[2], "tau_index": 2}], lik_index=-1, lik_value=0.0)
+    dm = binding.DeviceModel(m)
+    lp = lambda th: -0.5 * float(np.sum((np.asarray(th) - th0) ** 2))   # noqa: E731
+    g = lib.theta_mode_pinv(dm, prior, th0 + np.array([0.3, -0.3, 0.3]), log_prior=lp)
+    t2 = time.perf_counter()
+    H, lpost, hinfo = lib.theta_hessian_pinv(dm, prior, g["theta"], log_prior=lp)
+    pts, delta = lib.ccd_points(g["theta"], H)
+    Ps = lib.pinv_prior_assemble(prior, m["n"], pts)
+    res, _ = lib.woodbury_eval([dm] * len(pts), np.zeros(len(pts)), Ps)
+    w = lib.ccd_weights(delta, [q["objective"] + lp(p) for q, p in zip(res, pts)])
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    out = {"workload": f"Type IV Poisson model, s={m['n']} effects, k={n_t + 2 * n_s + 1} implicit constraints, "
+                       "t=3, N(theta0, I) log prior, Moore-Penrose route",
+           "pinv_blocks_s": t1 - t0, "pinv_sweeps": [int(v) for v in sweeps], "mode_s": t2 - t1,
+           "bfgs_iterations": g["iters"], "evaluations": g["evals"], "theta_evals_per_s": g["evals"] / (t2 - t1),
+           "hessian_and_ccd_s": t3 - t2, "ccd_points": len(pts), "weights_sum": float(np.sum(w)),
+           "theta_star": [float(v) for v in g["theta"]], "info": [g["info"], hinfo] + [q["info"] for q in res]}
+    log(f"stage 1 on the Moore-Penrose route (s={m['n']}): pinv {t1 - t0:.2f} s, mode {t2 - t1:.2f} s "
+        f"({g['iters']} iterations, {g['evals']} evaluations), Hessian + {len(pts)} CCD points {t3 - t2:.2f} s")
+    return out
+
+
 def run_moore_penrose(lib, binding, synth, B=9):
     """The paper's comparison of its Moore-Penrose route with kriging, on one
     posterior: the intrinsic RW1 x Besag Poisson model at n = 3000 (100 regions
@@ -484,7 +531,8 @@ def main():
     if args.moore_penrose_only:
         lib = binding.Library()
         print(json.dumps({"moore_penrose_n3000": run_moore_penrose(lib, binding, synth),
-                          "table3_type4": run_table3(lib, binding, synth)}), flush=True)
+                          "table3_type4": run_table3(lib, binding, synth),
+                          "stage1_type4_moore_penrose": run_stage1_type4(lib, binding, synth)}), flush=True)
         return
     if args.calibrate_copy:
         nbytes = 1 << 30
