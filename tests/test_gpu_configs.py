@@ -205,3 +205,49 @@ def test_warm_start_configuration_n4096(lib):
     ref = O.laplace_eval(model, test[0])
     assert np.max(np.abs(xw[0].cpu().numpy() - ref["x"])) / max(1.0, np.max(np.abs(ref["x"]))) <= RTOL
     assert rel(rw[0]["objective"], ref["objective"]) <= LOGDET_RTOL
+
+
+def test_headline_configuration_n8192(lib):
+    """The headline launch: n = 8192 (128 regions x 64 times, k = 191), 64 theta
+    ~ N(theta0, 0.5^2 I), FP32 factorisations started from a learned warm start
+    (a small network trained here on 256 solved modes), the untuned default
+    configuration.  All 64 theta: status, iterations, the Kronecker closed form
+    of log|Q_prior|, C x* = e, and agreement with the FP64 path (mode 1e-9,
+    log|Q*| and objective 2e-6); theta 0 also against the oracle."""
+    from paper_2311_08050_amd import warmstart
+    from paper_2311_08050_amd.binding import DeviceModel
+    model, thetas = synth.headline(B=64)
+    dm = DeviceModel(model)
+    th0 = synth.kron_theta0(64)
+    scale = np.full(4, 0.5)
+    say("headline: training a small warm-start network on 256 modes")
+    train = synth.normal_batch(th0, 256, 0.5, seed=91)
+    mlp, info = warmstart.train(lib, dm, train, th0, scale, hidden=128, epochs=80, batch=64, lr=2e-3, prec="fp32")
+    say(f"headline: trained (loss {info['loss_last']:.2e}); FP32 warm-start evaluation of 64 theta")
+    xw = mlp.predict_modes(thetas, th0, scale)
+    t0 = time.perf_counter()
+    r32, x32 = lib.laplace_eval([dm] * 64, thetas, x=xw, start=1, prec="fp32")
+    lib.torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r64, x64 = lib.laplace_eval([dm] * 64, thetas, prec="fp64")
+    lib.torch.cuda.synchronize()
+    say(f"headline: fp32+warm {t1 - t0:.2f} s, iterations {np.mean([r['iters'] for r in r32]):.2f}; "
+        f"fp64 {time.perf_counter() - t1:.2f} s, iterations {np.mean([r['iters'] for r in r64]):.2f}")
+    C = model["C"]
+    for b in range(64):
+        a, f = r32[b], r64[b]
+        assert a["info"] == 0 and f["info"] == 0, (b, a["info"], f["info"])
+        assert a["iters"] <= f["iters"] + 1   # a warm start that fails is redone from zero
+        ld = kron_logdet_closed_form(model, thetas[b])
+        assert rel(f["logdet_qprior"], ld) <= 1e-9 and rel(a["logdet_qprior"], ld) <= 1e-9
+        xa, xf = x32[b].cpu().numpy(), x64[b].cpu().numpy()
+        assert np.max(np.abs(xa - xf)) <= RTOL * max(1.0, np.max(np.abs(xf)))
+        assert np.max(np.abs(C @ xa)) <= 1e-10 * max(1.0, np.max(np.abs(xa)))
+        assert rel(a["logdet_qstar"], f["logdet_qstar"]) <= LOGDET_RTOL
+        assert rel(a["objective"], f["objective"]) <= LOGDET_RTOL
+    say("headline: oracle on theta 0 (about a minute on the host)")
+    ref = O.laplace_eval(model, thetas[0])
+    assert ref["info"] == 0
+    assert np.max(np.abs(x64[0].cpu().numpy() - ref["x"])) <= RTOL * max(1.0, np.max(np.abs(ref["x"])))
+    assert rel(r64[0]["objective"], ref["objective"]) <= RTOL
+    assert rel(r32[0]["objective"], ref["objective"]) <= LOGDET_RTOL
