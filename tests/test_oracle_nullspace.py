@@ -20,9 +20,11 @@ det(N^T Q N) = det(Q) det(C Q^{-1} C^T) / det(C C^T) and
 (x - mu_c)^T Q (x - mu_c) = x^T Q x - e^T (C Q^{-1} C^T)^{-1} e on {C x = e},
 this equals the kriging form term by term, so a dropped or mis-signed term of the
 oracle's objective (the e-term, either Schur log-determinant), a transposed
-design matrix or a wrong Poisson weight makes the two disagree.  The prior
-precision, the likelihood and every determinant are written here from their
-definitions, not taken from the oracle.
+design matrix or a wrong Poisson weight makes the two disagree.  The posterior
+covariance of the Gaussian approximation on the surface is N H^{-1} N^T (H the
+Hessian in z), which pins the oracle's kriging-corrected marginal variances.
+The prior precision, the likelihood and every determinant are written here from
+their definitions, not taken from the oracle.
 """
 import math
 
@@ -91,7 +93,9 @@ def nullspace_laplace(Q, A, y, E, offset, C, e):
     assert sp > 0 and sh > 0
     gmax = float(np.max(np.abs(grad(z))))
     obj = ll - 0.5 * dz @ P @ dz + 0.5 * ldP - 0.5 * ldH
-    return xp + N @ z, obj, gmax
+    # posterior covariance of the Gaussian approximation on the surface: N H^{-1} N^T
+    var = np.einsum("ij,ji->i", N, np.linalg.solve(hess(z), N.T))
+    return xp + N @ z, obj, gmax, var
 
 
 def _kron_case(n_s, n_t, seed, e_scale, constrained=True):
@@ -122,7 +126,7 @@ def test_laplace_objective_equals_nullspace_route(case):
     y = np.asarray(m["y"], dtype=np.float64)
     nobs = y.shape[0]
     E = np.ones(nobs) if m.get("E") is None else np.asarray(m["E"], dtype=np.float64)
-    x_ns, obj_ns, gmax = nullspace_laplace(Q, A, y, E, off, m.get("C"), m.get("e"))
+    x_ns, obj_ns, gmax, var_ns = nullspace_laplace(Q, A, y, E, off, m.get("C"), m.get("e"))
     assert gmax <= 1e-9 * max(1.0, float(np.max(np.abs(y))))
     r = O.laplace_eval(m, th)
     assert r["info"] == O.INFO_OK
@@ -130,3 +134,7 @@ def test_laplace_objective_equals_nullspace_route(case):
     assert abs(r["objective"] - obj_ns) <= 1e-9 * abs(obj_ns)
     if m.get("C") is not None:
         assert np.max(np.abs(m["C"] @ x_ns - m["e"])) <= 1e-10 * max(1.0, float(np.max(np.abs(x_ns))))
+    # marginal variances: the oracle's kriging-corrected diagonal equals the
+    # diagonal of the surface covariance N H^{-1} N^T at the mode
+    v = O.marginal_var(m, th, r["x"])
+    assert np.max(np.abs(v - var_ns)) <= 1e-9 * float(np.max(var_ns))
