@@ -253,6 +253,14 @@ class Library:
         if rc != 0:
             raise LibraryError(f"{what} returned {rc}")
 
+    def set_stream(self, stream=None):
+        """Rebind the handle to ``stream`` (a torch.cuda.Stream of the same
+        device; None: torch's current stream).  The library first waits for the
+        work it queued on the previous stream; ordering of the caller's own work
+        across the two streams stays the caller's (``wait_stream``)."""
+        s = self.torch.cuda.current_stream() if stream is None else stream
+        self._check(self.lib.inla_set_stream(self.h, C.c_void_p(s.cuda_stream)), "inla_set_stream")
+
     # ------------------------------------------------------------- entry points
     def logdet(self, mats, prec="fp64"):
         """log|Q_b| for a list of square float64 device tensors (C-order symmetric
