@@ -82,3 +82,38 @@ def test_no_oracle_in_product_path():
             if fn.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "from oracle" not in text, fn
+
+
+def _zero_args(params):
+    """NULL for every pointer (and callback), zero for every scalar, typed from
+    the declaration's parameter list."""
+    out = []
+    for p in [q.strip() for q in params.split(",") if q.strip() and q.strip() != "void"]:
+        if "*" in p or p.split()[0].endswith("_fn"):
+            out.append(ctypes.c_void_p(None))
+        elif "double" in p:
+            out.append(ctypes.c_double(0.0))
+        elif "float" in p:
+            out.append(ctypes.c_float(0.0))
+        elif "int64_t" in p:
+            out.append(ctypes.c_int64(0))
+        else:
+            out.append(ctypes.c_int32(0))
+    return out
+
+
+def test_null_first_argument_is_an_error_not_a_crash(libpath):
+    """Every int-returning entry point called with a NULL handle (or network,
+    or output handle) and zero sizes returns -1 without touching a device; the
+    two destroy calls accept NULL and return 0."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    lib = ctypes.CDLL(libpath)
+    seen = 0
+    for m in re.finditer(r"\n\s*int\s+(inla_[a-z0-9_]+)\s*\(([^;{]*?)\)\s*;", src):
+        name, params = m.group(1), " ".join(m.group(2).split())
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        want = 0 if name in ("inla_destroy", "inla_mlp_destroy") else -1
+        assert f(*_zero_args(params)) == want, name
+        seen += 1
+    assert seen == len(declared_functions()) - 1   # all but inla_version
