@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void border_gemv_kernel(const ThetaDesc *__res
   const ThetaDesc t = td[blockIdx.y];
   const int a = blockIdx.x * 64 + (threadIdx.x & 63), w = threadIdx.x >> 6;
   __shared__ double part[4][64];
-  if (blockIdx.x * 64 >= t.k_pad) return;
+  if ((int)blockIdx.x * 64 >= t.k_pad) return;
   const int np = t.n_pad;
   double s = 0.0;
   if (a < t.k) {

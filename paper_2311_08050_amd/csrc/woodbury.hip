@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void wb_lik_kernel(const WbDesc *__restrict__ 
 __global__ __launch_bounds__(256) void wb_symv_part_kernel(const WbDesc *__restrict__ wd, int src, int scaled) {
   const WbDesc D = wd[blockIdx.z];
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x * 256 >= D.n_pad) return;
+  if ((int)blockIdx.x * 256 >= D.n_pad) return;
   const int cs = (D.n + WB_CH - 1) / WB_CH;
   const int j0 = blockIdx.y * cs, j1 = min(D.n, j0 + cs);
   const double *v = wb_vec(D, src);
@@ -738,7 +738,7 @@ __global__ __launch_bounds__(256) void wb_update_kernel(const WbDesc *__restrict
 __global__ __launch_bounds__(256) void wb_xl_part_kernel(const WbDesc *__restrict__ wd) {
   const WbDesc D = wd[blockIdx.z];
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (!D.general || blockIdx.x * 256 >= D.n_lat_pad) return;
+  if (!D.general || (int)blockIdx.x * 256 >= D.n_lat_pad) return;
   const int cs = (D.n + WB_CH - 1) / WB_CH;
   const int i0 = blockIdx.y * cs, i1 = min(D.n, i0 + cs);
   double acc = 0.0;
