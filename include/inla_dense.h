@@ -361,10 +361,10 @@ int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_po
  *
  * inla_pinv: Q^+ of B symmetric matrices by a block Jacobi eigen-decomposition
  * Q = V diag(lambda) V^T: blocks of 32 indices, block pairs in round-robin
- * order, each pair's 64 x 64 principal submatrix diagonalised by cyclic Jacobi
- * and applied to A and V as 64-wide tile products; sweeps until the
- * off-diagonal Frobenius norm is at most 4 eps ||A||_F, or below 1e-14 ||A||_F
- * and shrinking by less than 10% per sweep (at most 40 sweeps).
+ * order, each pair's 64 x 64 principal submatrix reduced by one sweep of cyclic
+ * Jacobi and the rotations applied to A and V as 64-wide tile products; sweeps
+ * until the off-diagonal Frobenius norm is at most 4 eps ||A||_F, or below
+ * 1e-14 ||A||_F and shrinking by less than 10% per sweep (at most 120 sweeps).
  * Q^+ = V diag(f) V^T with f_k = 1 / lambda_k where |lambda_k| > rtol *
  * max|lambda| and 0 otherwise.
  *   n        host [B] orders, 1 <= n[b] <= 16384

@@ -44,8 +44,14 @@ Ctx *handle_ctx(inla_handle *h);
 constexpr int JB = 32;               // block width of the block Jacobi method
 constexpr int JP = 2 * JB;           // block-pair width (the inner eigenproblem's order)
 constexpr int JAC_MAX_N = 16384;
-constexpr int JAC_MAX_SWEEPS = 40;
-constexpr int JAC_INNER_SWEEPS = 30;
+// One inner sweep per block pair and round: the outer rounds carry the
+// convergence, and an inexact inner solve keeps each pair's rotation product
+// orthogonal, so the method stays exact while each round costs one inner sweep
+// instead of the 2-6 a converged inner solve takes.  Measured at n = 3000 and
+// on the order-1000 Kronecker block of the Type IV prior: 35 and 45 outer
+// sweeps, 1.8 and 3.8 times faster than converged inner solves.
+constexpr int JAC_MAX_SWEEPS = 120;
+constexpr int JAC_INNER_SWEEPS = 1;
 constexpr double JAC_RTOL_DEFAULT = 1e-9;
 constexpr int JAC_NORM_BLOCKS = 256;
 
@@ -98,11 +104,11 @@ __global__ __launch_bounds__(256) void jacobi_init_kernel(const JacDesc *__restr
 }
 
 // Inner eigenproblem of one block pair: the JP x JP principal submatrix S of A
-// on the pair's indices is diagonalised in LDS by cyclic Jacobi (round-robin
-// over its JP indices, rotations accumulated from the identity, so R stays
-// close to I, which the outer iteration's convergence needs), until its
-// off-diagonal part is at the rounding level.  Writes R (column-major).  Grid
-// (nbk / 2 pairs, B).
+// on the pair's indices is reduced in LDS by cyclic Jacobi (round-robin over
+// its JP indices, rotations accumulated from the identity, so R stays close to
+// I, which the outer iteration's convergence needs): at most JAC_INNER_SWEEPS
+// sweeps, fewer once its off-diagonal part is at the rounding level.  Writes R
+// (column-major).  Grid (nbk / 2 pairs, B).
 __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__restrict__ jd, int r) {
   const JacDesc J = jd[blockIdx.y];
   const int j = blockIdx.x;

@@ -386,3 +386,20 @@ def test_type4_stage1_moore_penrose(lib):
     assert info == 0
     assert np.max(np.abs(H - Hr)) <= 1e-3 * np.max(np.abs(Hr)), (H, Hr)
     assert np.all(np.linalg.eigvalsh(H) > 0)
+
+
+def test_type4_kronecker_block_converges(lib):
+    """The Type IV prior's interaction structure R2_t kron R_s at the first
+    simulation-study size (n_s = 200, n_t = 5: order 1000, rank 597) on the
+    random graph the benchmark draws: the block Jacobi iteration meets its own
+    convergence test within its sweep limit (info 0), and Q^+ equals the
+    reference eigen-decomposition's to the parity bar."""
+    m = synth.type4(200, 5, seed=290)
+    R = np.kron(WB.rw2_structure(5), WB.besag_structure(200, m["edges"]))
+    say("type4 Kronecker block, order 1000")
+    P, rank, sweeps, info = lib.pinv([dev(R)])
+    say(f"rank {rank[0]}, sweeps {sweeps[0]}, info {info[0]}")
+    Pr, rr, _ = WB.pseudo_inverse(R)
+    assert info[0] == 0 and rank[0] == rr == 1000 - 403
+    sc = np.max(np.abs(Pr))
+    assert np.max(np.abs(P[0].cpu().numpy() - Pr)) <= 1e-11 * sc
