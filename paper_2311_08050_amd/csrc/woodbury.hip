@@ -219,29 +219,39 @@ __global__ __launch_bounds__(256) void jacobi_pair_cols_kernel(const JacDesc *__
     Rs[e % JP][e / JP] = Rg[e];
   }
   __syncthreads();
-  const int tr = tid & 15, tc = tid >> 4;
-  double acc[4][4];
+  // 64 x 64 x 64 product on FP64 MFMA: wave w owns the 32 x 32 quadrant
+  // (rows wr.., columns wc..) as 2 x 2 blocks of 16 x 16.  Operands are
+  // swapped as in the factorisation's trailing update, so lane l's four
+  // results are output row li of columns g + 4v and each store covers whole
+  // 128-byte column segments.
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, g = lane >> 4;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  d4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int l = 0; l < JP; ++l) {
-    double a[4], b[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JP; k0 += 4) {
+    const int k = k0 + g;
+    double x[2], q[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = Xt[tr + 16 * u][l];
+    for (int a = 0; a < 2; ++a) x[a] = Xt[wr + 16 * a + li][k];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = Rs[l][tc + 16 * v];
+    for (int b = 0; b < 2; ++b) q[b] = Rs[k][wc + 16 * b + li];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[b], x[a], acc[a][b], 0, 0, 0);
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const size_t col = (size_t)pair_idx(tc + 16 * v, I, K) * J.ne + i0;
+  for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) Xg[col + tr + 16 * u] = acc[u][v];
-  }
+    for (int v = 0; v < 4; ++v) {
+      const size_t col = (size_t)pair_idx(wc + 16 * b + g + 4 * v, I, K) * J.ne + i0;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) Xg[col + wr + 16 * a + li] = acc[a][b][v];
+    }
 }
 
 // Rows of every pair: A[pair, :] <- R^T A[pair, :], one 64-column tile per
@@ -266,29 +276,37 @@ __global__ __launch_bounds__(256) void jacobi_pair_rows_kernel(const JacDesc *__
     Rs[e % JP][e / JP] = Rg[e];
   }
   __syncthreads();
-  const int tm = tid & 15, tcol = tid >> 4;
-  double acc[4][4];
+  // R^T At on FP64 MFMA, laid out as in the column pass: lane l's four
+  // results are pair row wr + 16 a + li of columns g + 4v (16 consecutive pair
+  // rows lie in one 32-row block, so each store covers 128-byte segments).
+  const int lane = tid & 63, w = tid >> 6, li = lane & 15, g = lane >> 4;
+  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+  d4 acc[2][2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int l = 0; l < JP; ++l) {
-    double a[4], b[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < JP; k0 += 4) {
+    const int k = k0 + g;
+    double p[2], q[2];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = Rs[l][tm + 16 * u];
+    for (int a = 0; a < 2; ++a) p[a] = Rs[k][wr + 16 * a + li];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = At[l][tcol + 16 * v];
+    for (int b = 0; b < 2; ++b) q[b] = At[k][wc + 16 * b + li];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(q[b], p[a], acc[a][b], 0, 0, 0);
   }
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int c = c0 + tcol + 16 * v;
+  for (int b = 0; b < 2; ++b)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) Ag[(size_t)c * J.ne + pair_idx(tm + 16 * u, I, K)] = acc[u][v];
-  }
+    for (int v = 0; v < 4; ++v) {
+      const size_t col = (size_t)(c0 + wc + 16 * b + g + 4 * v) * J.ne;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) Ag[col + pair_idx(wr + 16 * a + li, I, K)] = acc[a][b][v];
+    }
 }
 
 // Sums of squares of the off-diagonal and of all entries: workgroup g sums
