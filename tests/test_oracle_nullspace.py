@@ -138,3 +138,23 @@ def test_laplace_objective_equals_nullspace_route(case):
     # diagonal of the surface covariance N H^{-1} N^T at the mode
     v = O.marginal_var(m, th, r["x"])
     assert np.max(np.abs(v - var_ns)) <= 1e-9 * float(np.max(var_ns))
+
+
+@pytest.mark.slow
+def test_laplace_objective_equals_nullspace_route_at_n3000():
+    """The same pin at the n = 3000 configuration's shape (100 regions x 30
+    times, k = 129 sum-to-zero rows): objective, mode and marginal variances of
+    the oracle against the constraint-surface route (z of dimension 2871)."""
+    m = synth.kron_poisson(100, 30, seed=2)
+    th = synth.kron_theta0(30) + np.array([0.1, -0.1, 0.2, 0.05])
+    Q = kron_prior(m, th)
+    y, E = np.asarray(m["y"], dtype=np.float64), np.asarray(m["E"], dtype=np.float64)
+    x_ns, obj_ns, gmax, var_ns = nullspace_laplace(Q, None, y, E, float(th[3]), m["C"], m["e"])
+    assert gmax <= 1e-9 * max(1.0, float(np.max(np.abs(y))))
+    r = O.laplace_eval(m, th)
+    assert r["info"] == O.INFO_OK
+    assert np.max(np.abs(r["x"] - x_ns)) <= 1e-8 * max(1.0, float(np.max(np.abs(x_ns))))
+    assert abs(r["objective"] - obj_ns) <= 1e-9 * abs(obj_ns)
+    assert np.max(np.abs(m["C"] @ x_ns - m["e"])) <= 1e-10 * max(1.0, float(np.max(np.abs(x_ns))))
+    v = O.marginal_var(m, th, r["x"])
+    assert np.max(np.abs(v - var_ns)) <= 1e-9 * float(np.max(var_ns))
