@@ -54,6 +54,32 @@ def stationarity_residual(model, th, x, Qp=None):
     return np.max(np.abs(v - model["C"].T @ lam)) / max(1.0, np.max(np.abs(Qp @ x)))
 
 
+def golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)) as f:
+        return json.load(f)
+
+
+def check_mixed_vs_golden(r, x, g, what):
+    """A mixed-precision evaluation against the stored FP64 oracle values: the
+    mode (refined in FP64) at the FP64 bar, the FP64 prior pass at the FP64
+    bar, log|Q*|, log|S| and the objective at the mixed-precision bounds; the
+    absolute objective error is printed next to the relative one."""
+    idx = np.array(g["index"])
+    err_x = np.max(np.abs(x[idx] - np.array(g["x"]))) / max(1.0, g["x_absmax"])
+    d_obj = abs(r["objective"] - g["objective"])
+    say(f"{what} vs oracle (n={g['n']}): mode {err_x:.2e}, log|Q*| {rel(r['logdet_qstar'], g['logdet_qstar']):.2e}, "
+        f"log|S| {rel(r['logdet_s'], g['logdet_s']):.2e}, objective {rel(r['objective'], g['objective']):.2e} "
+        f"relative, {d_obj:.2e} absolute")
+    assert err_x <= RTOL
+    for key in ("logdet_qprior", "logdet_sprior", "ese"):
+        assert rel(r[key], g[key]) <= RTOL, (what, key)
+    assert rel(r["logdet_qstar"], g["logdet_qstar"]) <= LOGDET_RTOL
+    assert rel(r["logdet_s"], g["logdet_s"]) <= 1e-5
+    assert rel(r["objective"], g["objective"]) <= LOGDET_RTOL
+
+
 @pytest.mark.timeout(600)
 def test_uneven_batch_configuration(lib):
     from paper_2311_08050_amd.binding import DeviceModel
@@ -109,6 +135,23 @@ def test_n16384_fp64_and_mixed(lib):
     assert np.max(np.abs(model["C"] @ x64)) <= 1e-10
     say("n=16384: stationarity on the CPU")
     assert stationarity_residual(model, th0, x64) <= 1e-9
+    # the FP64 oracle's values at theta0, stored by tests/golden/make_full_size.py
+    g = golden("kron16384_theta0.json")
+    assert np.array_equal(np.array(g["theta"]), th0)
+    idx = np.array(g["index"])
+    gx = np.array(g["x"])
+    assert abs(r64["iters"] - g["iters"]) <= 1
+    for key in ("objective", "logdet_qprior", "logdet_sprior", "ese", "logdet_qstar", "logdet_s", "xqx", "loglik"):
+        assert rel(r64[key], g[key]) <= RTOL, (key, r64[key], g[key])
+    assert np.max(np.abs(x64[idx] - gx)) <= RTOL * max(1.0, g["x_absmax"])
+    say("n=16384: marginal variances at the FP64 mode against the stored oracle values")
+    import torch
+    var, vinfo = lib.marginal_var([dm], th0[None, :], [torch.tensor(x64).cuda()])
+    assert vinfo[0] == 0
+    verr = np.max(np.abs(var[0].cpu().numpy()[idx] - np.array(g["var"])) / np.array(g["var"]))
+    say(f"n=16384 marginal variances: max relative error {verr:.2e}")
+    assert verr <= RTOL
+    del var
     say("n=16384: mixed precision (FP32 factorisations, FP64 refinement)")
     r32, x32 = lib.laplace_eval([dm], th0[None, :], prec="fp32")
     r32, x32 = r32[0], x32[0].cpu().numpy()
@@ -119,6 +162,7 @@ def test_n16384_fp64_and_mixed(lib):
     assert mode_err <= RTOL
     assert rel(r32["logdet_qstar"], r64["logdet_qstar"]) <= LOGDET_RTOL
     assert rel(r32["objective"], r64["objective"]) <= LOGDET_RTOL
+    check_mixed_vs_golden(r32, x32, g, "fp32")
     say("n=16384: BF16 trailing operands on the unrefined Newton steps")
     rbf, xbf = lib.laplace_eval([dm], th0[None, :], prec="bf16")
     rbf, xbf = rbf[0], xbf[0].cpu().numpy()
@@ -129,6 +173,7 @@ def test_n16384_fp64_and_mixed(lib):
     assert mode_err <= RTOL
     assert rel(rbf["logdet_qstar"], r64["logdet_qstar"]) <= LOGDET_RTOL
     assert rel(rbf["objective"], r64["objective"]) <= LOGDET_RTOL
+    check_mixed_vs_golden(rbf, xbf, g, "bf16")
     # log|Q*| at the mode from a single factorisation in each precision (BF16:
     # trailing operands BF16 throughout), against the FP64 factorisation
     import torch

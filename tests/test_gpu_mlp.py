@@ -89,6 +89,36 @@ def test_adam_step_matches_reference(net):
     m.set_params(torch.tensor(p.astype(np.float32)))
 
 
+def test_adam_sequence_matches_reference(net):
+    """Six Adam steps in a row (moment accumulation and bias correction from step
+    2 on) against the FP64 reference run on the same batch from the same
+    parameters.  On parameters whose gradient stays well above the FP32
+    gradient error at every step, the total move agrees to 1e-4 of the largest
+    possible move (steps x lr) plus the FP32 storage rounding of the parameters."""
+    import torch
+    m, p, u, t, (I, H, O) = net
+    steps, lr = 6, 1e-3
+    say("mlp adam, six steps")
+    m.set_params(torch.tensor(p.astype(np.float32)))
+    U, T = torch.tensor(u).cuda(), torch.tensor(t).cuda()
+    for _ in range(steps):
+        m.train_step(U, T, lr)
+    new = m.get_params().cpu().numpy().astype(np.float64)
+    ref, mom, vel = p.copy(), np.zeros_like(p), np.zeros_like(p)
+    big = np.ones(p.size, dtype=bool)
+    for s in range(1, steps + 1):
+        _, g = M.grad(ref, u.astype(np.float64), t, I, H, O)
+        big &= np.abs(g) >= 1e-3 * np.max(np.abs(g))
+        ref, mom, vel = M.adam(ref, g, mom, vel, s, lr)
+    assert big.sum() > 0.5 * p.size
+    move, ref_move = new - p, ref - p
+    tol = 1e-4 * steps * lr + steps * np.finfo(np.float32).eps * np.max(np.abs(p))
+    err = np.max(np.abs(move[big] - ref_move[big]))
+    say(f"six Adam steps: max |GPU - reference| move {err:.2e} (bound {tol:.2e})")
+    assert err <= tol
+    m.set_params(torch.tensor(p.astype(np.float32)))
+
+
 def test_trained_warm_start_saves_newton_iterations(lib):
     import torch
     from paper_2311_08050_amd import warmstart

@@ -168,6 +168,15 @@ def test_woodbury_n3000(lib):
     assert all(q["info"] == 0 for q in res)
     assert np.max(np.abs(x - ref["x"])) <= 1e-9 * max(1.0, np.max(np.abs(ref["x"])))
     assert abs(r["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
+    # marginal variances diag(Sigma*) at full size (M of order 3000 factored with
+    # 3000 border rows: six 512-wide panels) against the reference covariance
+    var, vinfo = lib.woodbury_var([dm] * 3, [th[1] for th in thetas], Ps, xs)
+    assert np.all(vinfo == 0)
+    vr = np.diag(ref["Sigma"])
+    scale = np.max(np.diag(Ps[1].cpu().numpy()))
+    err = np.max(np.abs(var[1].cpu().numpy() - vr))
+    say(f"n=3000 Woodbury variances: max |GPU - reference| {err:.2e} (Q+ diagonal up to {scale:.3f})")
+    assert err <= 1e-10 * scale
     # the GPU pseudo-inverse itself, sampled columns
     Pr, _, _ = WB.pseudo_inverse(R)
     cols = np.random.default_rng(0).choice(3000, 16, replace=False)
@@ -300,6 +309,21 @@ def test_type4_table3_first_size(lib):
     assert dx_ref <= tol_x and dx_krig <= tol_x
     assert abs(res[0]["objective"] - ref["objective"]) <= 1e-9 * abs(ref["objective"])
     assert abs(res[0]["objective"] - rk[0]["objective"]) <= 1e-9 * abs(rk[0]["objective"])
+    # marginal variances at this size (M of order 1000 with 1207 border rows)
+    # against the reference covariance and the GPU kriging route's variances
+    var, vinfo = lib.woodbury_var([dm], [th[3]], P, xs)
+    vk, kinfo = lib.marginal_var([dk], np.array([[th[3]]]), xs)
+    assert vinfo[0] == 0 and kinfo[0] == 0
+    vg, vr = var[0].cpu().numpy(), np.diag(ref["Sigma"])
+    scale = np.max(np.diag(P[0].cpu().numpy()))
+    e_ref, e_krig = np.max(np.abs(vg - vr)), np.max(np.abs(vg - vk[0].cpu().numpy()))
+    say(f"table-3 size variances: max |GPU - reference| {e_ref:.2e}, |Woodbury - kriging| {e_krig:.2e} "
+        f"(Q+ diagonal up to {scale:.3g})")
+    assert np.all(vg > 0)
+    # the covariance form's rounding floor, about u cond(M), bounds the
+    # variances as it bounds the mode: max(1e-10, 4 u cond(M)) of the scale
+    tol_v = max(1e-10, 4 * np.finfo(float).eps * ev[-1] / ev[0])
+    assert e_ref <= tol_v * scale and e_krig <= tol_v * scale
 
 
 def test_woodbury_mixed_batch(lib):
@@ -355,7 +379,7 @@ def test_type4_stage1_moore_penrose(lib):
     pseudo-inverses, the BFGS mode and the finite-difference Hessian of
     log pi~(theta | y) against the reference's BFGS and Hessian driven by its
     own Woodbury evaluation.  Tolerances: objective values agree to ~1e-11
-    relative (the covariance form's floor, R29), so the modes agree far inside
+    relative (the covariance form's rounding floor), so the modes agree far inside
     the gradient tolerance (1e-5 here) and the Hessians (h = 5e-3 divides the
     objective's differences by h^2) to 1e-3 of their largest entry."""
     from oracle import theta_oracle as T
