@@ -86,7 +86,11 @@ enum {
  *        with FP64 residuals until the correction is below 1e-13 relative, and
  *        only a refined step can end the iteration.  The last Newton factor
  *        gives log|Q*|.  A theta whose refinement does not converge within its
- *        budget is re-evaluated in FP64 and flagged in inla_result.fallback.
+ *        budget, whose FP32 (or BF16-operand) factorisation of Q* meets a
+ *        non-positive pivot, or whose kriging system built from that factor is
+ *        numerically singular, is re-evaluated in FP64 and flagged in
+ *        inla_result.fallback (bit 0); its info then comes from the FP64
+ *        evaluation.
  *  BF16: as FP32, but the factorisations of the unrefined Newton steps round
  *        the panel operands of the trailing update of Q* to BF16 (FP32 storage,
  *        FP32 accumulation; the border rows keep FP32 operands), and each such

@@ -900,6 +900,14 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       const int *inf = &b.hinfo[4 * i];
       const double *dr = &b.hdres[DRES_COUNT * i];
       res[i].iters = it;
+      // A low-precision factor that meets a non-positive pivot, or whose kriging
+      // system comes out numerically singular, says nothing about Q* itself:
+      // the prior pass (FP64) has already checked C's rank, and Q* may be
+      // positive definite in FP64 while its FP32 factorisation breaks down
+      // (condition number beyond 1 / u_32).  Such a theta is re-evaluated in
+      // FP64.  The failed factor's NaNs also reach the iterate, so this test
+      // comes before the non-finite one.
+      if (mixed && (inf[F_BIG] || inf[F_SMALL] || dr[DRES_RANK] != 0.0)) { failed[i] = 1; redo.push_back(i); continue; }
       if (dr[DRES_NONFINITE] != 0.0) { res[i].info = INLA_INFO_NONFINITE; failed[i] = 1; continue; }
       if (inf[F_BIG]) { res[i].info = inf[F_BIG]; failed[i] = 1; continue; }
       if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; failed[i] = 1; continue; }

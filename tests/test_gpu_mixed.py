@@ -135,3 +135,48 @@ def test_logdet_precisions_on_posterior_precision(lib):
         ld, inf = lib.logdet([torch.tensor(Q).cuda()], prec=prec)
         say(f"logdet {prec}: relative error {abs(ld[0] - ld_ref) / abs(ld_ref):.2e}")
         assert inf[0] == 0 and abs(ld[0] - ld_ref) <= tol * abs(ld_ref), (prec, ld[0], ld_ref)
+
+
+def ill_conditioned_model(n=300, seed=11):
+    """Poisson model with a dense prior whose eigenvalues run geometrically from
+    1 down to 1e-10 (condition 1e10): positive definite in FP64 (u_64 cond ~
+    1e-6), far beyond FP32 (u_32 cond ~ 6e2), so an FP32 Cholesky of Q* meets a
+    non-positive pivot (LAPACK's spotrf fails at pivot 216 on it).  y = 0 and an
+    exposure of 1e-17 keep W = E e^x ~ 1e-17, so Q* ~ Q_prior, and the mode of
+    order 1e-7, where FP64 Newton converges in two steps (the oracle's too)."""
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    Q = (U * np.logspace(0.0, -10.0, n)) @ U.T
+    Q = 0.5 * (Q + Q.T)
+    return {"n": n, "lik": "poisson", "prior": "dense", "y": np.zeros(n), "E": np.full(n, 1e-17), "A": None,
+            "C": None, "e": None, "coords": None, "n_s": n, "n_t": 1, "Qprior": Q}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_low_precision_breakdown_is_redone_in_fp64(lib, prec):
+    """A Q* that is positive definite in FP64 but whose low-precision factor
+    breaks down is re-evaluated in FP64 (fallback bit 0, info 0) and matches the
+    FP64 path; a well-conditioned theta of the same batch stays mixed.  From a
+    warm start the same holds: the FP64 re-evaluation, not a zero-start retry in
+    the failing precision."""
+    import torch
+    bad = ill_conditioned_model()
+    good = synth.kron_poisson(13, 7, seed=5)
+    th_bad, th_good = np.array([0.0, 0, 0, 0]), synth.kron_theta0(7)
+    dms = dev_models([bad, good])
+    ths = np.stack([th_bad, th_good])
+    say(f"{prec} breakdown on an FP64-definite Q* (cond 1e10)")
+    r64, x64 = lib.laplace_eval(dms, ths, prec="fp64")
+    assert r64[0]["info"] == 0 and r64[1]["info"] == 0, (r64[0]["info"], r64[1]["info"])
+    for start in (0, 1):
+        xs = [torch.zeros(bad["n"], dtype=torch.float64, device="cuda"),
+              torch.zeros(good["n"], dtype=torch.float64, device="cuda")]
+        r, xs = lib.laplace_eval(dms, ths, x=xs, start=start, prec=prec)
+        assert r[0]["info"] == 0 and r[0]["fallback"] & 1 and not r[0]["fallback"] & 2, (start, r[0])
+        assert abs(r[0]["objective"] - r64[0]["objective"]) <= 1e-12 * max(1.0, abs(r64[0]["objective"]))
+        assert torch.equal(xs[0], x64[0])
+        assert r[1]["info"] == 0 and r[1]["fallback"] == 0
+        assert rel(r[1]["objective"], r64[1]["objective"]) <= LOGDET_RTOL
+    ref = O.laplace_eval(bad, th_bad)
+    assert ref["info"] == 0
+    assert np.max(np.abs(x64[0].cpu().numpy() - ref["x"])) <= MODE_RTOL * max(1.0, np.max(np.abs(ref["x"])))
