@@ -191,6 +191,32 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
     }
 
 
+def amortised_warm_start(results, train_info, counts=(512, 4096)):
+    """What the learned warm start buys an INLA run once its one-time cost is
+    charged to the evaluations it speeds up.  For each mixed precision p with a
+    '+mlp' variant and a zero-start variant in this run: theta-evals/s over N
+    evaluations, N / (setup + N / v_warm), with setup = the training targets'
+    solves + the training itself, and with setup = the training alone (targets
+    taken from modes the run computes anyway, e.g. its Stage-1 evaluations);
+    and the break-even count setup / (1 / v_zero - 1 / v_warm).  N = 512 is
+    about one run at t = 4 (Stage 1 took 457 evaluations at n = 3000, plus the
+    Hessian and CCD points)."""
+    out = {}
+    for p in ("fp32", "bf16"):
+        if f"{p}+mlp" not in results or p not in results:
+            continue
+        vz, vw = results[p]["value"], results[f"{p}+mlp"]["value"]
+        row = {"zero_start": vz, "warm_start": vw}
+        for label, setup in (("with_target_solves", train_info["solve_s"] + train_info["train_s"]),
+                             ("targets_from_run", train_info["train_s"])):
+            row[label] = {"setup_s": setup,
+                          **{f"N{n}": n / (setup + n / vw) for n in counts},
+                          "break_even_evals": setup / (1.0 / vz - 1.0 / vw) if vw > vz else None}
+        out[p] = row
+    out["unit"] = "θ-evals/s"
+    return out
+
+
 def run_extras(lib, binding, synth, dms, thetas, xs):
     """Separately timed figures (not part of `value`): marginal variances and the
     variational-Bayes mean correction of the headline batch (FP64, from the modes
@@ -237,9 +263,94 @@ def run_extras(lib, binding, synth, dms, thetas, xs):
                            "evaluations": g["evals"], "theta_evals_per_s": g["evals"] / (t1 - t0),
                            "hessian_and_ccd_s": t2 - t1, "ccd_points": len(pts), "info": [g["info"], hinfo]}
     log(f"stage 1 at n=3000: {t1 - t0:.2f} s ({g['iters']} iterations), Hessian + CCD {t2 - t1:.2f} s")
+    out["uneven_batch"] = run_uneven_batch(lib, binding, synth)
+    out["n16384_precision"] = run_n16384(lib, binding, synth)
     out["moore_penrose_n3000"] = run_moore_penrose(lib, binding, synth)
     out["table3_type4"] = run_table3(lib, binding, synth)
     out["stage1_type4_moore_penrose"] = run_stage1_type4(lib, binding, synth)
+    return out
+
+
+def run_uneven_batch(lib, binding, synth, steps=3):
+    """The batching configuration: 64 theta in one call, n drawn from {1024,
+    2048, 3000, 4096, 6144} (Poisson space-time models, k = n_s + n_t - 1),
+    theta_b ~ N(theta0(n_b), 0.5^2 I), FP64, zero start, autotuned panel width
+    and tile for the batch's shape; `steps` timed calls after one untimed one."""
+    import numpy as np
+    import torch
+    models, thetas = synth.uneven_batch(B=64, seed=3)
+    seen, dms = {}, []
+    for m in models:
+        if id(m) not in seen:
+            seen[id(m)] = binding.DeviceModel(m)
+        dms.append(seen[id(m)])
+    t0 = time.perf_counter()
+    chosen, _ = lib.autotune([m["n"] for m in models], [m["C"].shape[0] + 1 for m in models], prec="fp64", reps=2)
+    t_tune = time.perf_counter() - t0
+    lib.laplace_eval(dms, thetas)
+    torch.cuda.synchronize()
+    g0 = lib.graph_stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, _ = lib.laplace_eval(dms, thetas)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    g1 = lib.graph_stats()
+    assert all(r["info"] == 0 for r in res), [r["info"] for r in res]
+    ns = [m["n"] for m in models]
+    out = {"workload": "64 theta in one call, n in {1024, 2048, 3000, 4096, 6144} (Poisson space-time, k = n_s + n_t "
+                       "- 1), theta ~ N(theta0, 0.5^2 I), FP64, zero start",
+           "value": 64 / dt, "unit": "θ-evals/s", "ms_per_call": dt * 1e3, "steps": steps,
+           "n_counts": {str(v): ns.count(v) for v in sorted(set(ns))},
+           "newton_iters_mean": float(np.mean([r["iters"] for r in res])),
+           "autotune": {"nb": chosen[0], "tm": chosen[1], "lookahead": chosen[2], "tune_s": t_tune},
+           "graph_replays_per_call": (g1["replays"] - g0["replays"]) / steps,
+           "graphs_captured_in_timed_calls": g1["captured"] - g0["captured"], "precision": "fp64"}
+    log(f"uneven batch: {64 / dt:.1f} theta-evals/s ({dt * 1e3:.0f} ms per call), tuned {chosen}")
+    return out
+
+
+def run_n16384(lib, binding, synth):
+    """The precision configuration: n = 16384 (128 regions x 128 times, k =
+    255), the 9-point finite-difference batch at theta0 (h = 0.01) in FP64, FP32
+    and BF16 (one untimed and one timed call each, autotuned), and the errors
+    of theta0's evaluation against the FP64 oracle's stored values
+    (tests/golden/kron16384_theta0.json, written by a script that calls only
+    the oracle): mode (every 8th element), log|Q*|, log|S| and the objective,
+    relative and absolute."""
+    import numpy as np
+    import torch
+    model = synth.kron_poisson(128, 128, seed=4)
+    th0 = synth.kron_theta0(128)
+    batch = synth.fd_batch(th0, 0.01, [0, 1, 2, 3])
+    dm = binding.DeviceModel(model)
+    with open(os.path.join(ROOT, "tests", "golden", "kron16384_theta0.json")) as f:
+        g = json.load(f)
+    idx = np.array(g["index"])
+    k = model["C"].shape[0]
+    out = {"workload": "Poisson space-time n=16384 (128 regions x 128 times), k=255, 9-point finite-difference "
+                       "batch at theta0", "precisions": {}}
+    for prec in ("fp64", "fp32", "bf16"):
+        chosen, _ = lib.autotune([16384] * 9, [k + 1] * 9, prec=prec, reps=1)
+        lib.laplace_eval([dm] * 9, batch, prec=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, xs = lib.laplace_eval([dm] * 9, batch, prec=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        assert all(r["info"] == 0 for r in res), [r["info"] for r in res]
+        r0, x0 = res[0], xs[0].cpu().numpy()
+        errs = {"mode_max_rel": float(np.max(np.abs(x0[idx] - np.array(g["x"]))) / max(1.0, g["x_absmax"])),
+                "objective_abs": abs(r0["objective"] - g["objective"])}
+        for key in ("objective", "logdet_qstar", "logdet_s", "logdet_qprior"):
+            errs[f"{key}_rel"] = abs(r0[key] - g[key]) / abs(g[key])
+        out["precisions"][prec] = {
+            "value": 9 / dt, "unit": "θ-evals/s", "s_per_call": dt,
+            "newton_iters": [r["iters"] for r in res], "fp64_fallbacks": int(sum(r["fallback"] & 1 for r in res)),
+            "autotune": {"nb": chosen[0], "tm": chosen[1], "lookahead": chosen[2]},
+            "theta0_errors_vs_oracle": errs}
+        log(f"n=16384 9-point batch {prec}: {9 / dt:.2f} theta-evals/s, iterations "
+            f"{[r['iters'] for r in res]}, theta0 objective error {errs['objective_abs']:.1e} abs")
     return out
 
 
@@ -503,6 +614,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="factor with the default panel width and tile instead of tuning them first")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no hipGraph replays)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="run each evaluation's prior pass beside the Newton iteration on a second stream")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the separately timed marginal-variance, VB-correction and Stage-1 figures")
     ap.add_argument("--rocprof-window", metavar="CSV",
@@ -554,6 +667,8 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     if args.no_graphs:
         lib.set_graphs(False)
+    if args.overlap:
+        lib.set_overlap(True)
     tuning = {}
     if not args.no_autotune:
         # one-time setup, not timed: the tuner factors synthetic batches of the
@@ -617,9 +732,11 @@ def main():
         "variants": results,
         "autotune": tuning or None,
         "graphs": not args.no_graphs,
+        "overlap": args.overlap,
     }
     if train_info is not None:
         out["warm_start_training"] = dict(train_info, **MLP_TRAIN)
+        out["warm_start_amortised"] = amortised_warm_start(results, train_info)
     if "fp64" in results and head != "fp64":
         out["speedup_vs_fp64"] = hv["value"] / results["fp64"]["value"]
     if not args.no_extras:

@@ -529,6 +529,17 @@ int inla_set_graphs(inla_handle *h, int32_t enable);
  * Results are identical with and without lookahead.  Returns -1 for a null
  * handle. */
 int inla_set_lookahead(inla_handle *h, int32_t enable);
+/* Concurrent prior pass (off by default).  The prior's factorisation in
+ * inla_laplace_eval and inla_constrained_mode (log|Q_prior|, C Q_prior^{-1} C^T
+ * and their log-determinant, FP64 in every precision) depends on theta alone,
+ * and the Newton iteration never reads it: with overlap on it runs on a third
+ * stream owned by the handle (created on first use, default priority) while
+ * the handle's stream runs the Newton iteration, in a workspace of its own
+ * (one more FP64 bordered matrix of order n + k + 1, padded to 128, per
+ * theta).  Events order the two streams; every call still returns with its
+ * work complete on the handle's stream.  Results are identical with and
+ * without overlap.  Returns -1 for a null handle. */
+int inla_set_overlap(inla_handle *h, int32_t enable);
 /* Graphs captured and replayed so far by this handle (host outputs; either may be NULL). */
 int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
 /* Autotuner of the blocked Cholesky.  A configuration is int32_t[3] =

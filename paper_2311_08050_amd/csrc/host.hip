@@ -27,11 +27,31 @@ int Ctx::side_ready() {
   return INLA_OK;
 }
 
+int Ctx::aux_ready() {
+  if (aux) return INLA_OK;
+  if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+    aux = nullptr;
+    return INLA_ERR_HIP;
+  }
+  if (hipEventCreateWithFlags(&ev_c, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ev_d, hipEventDisableTiming) != hipSuccess)
+    return INLA_ERR_HIP;
+  return INLA_OK;
+}
+
+int Ctx::sync_all() {
+  // the caller's stream (NULL is the null stream), then the handle's own
+  // streams if created; `stream` is always one of them
+  if (hipStreamSynchronize(home) != hipSuccess) return INLA_ERR_HIP;
+  for (hipStream_t s : {side, aux})
+    if (s && hipStreamSynchronize(s) != hipSuccess) return INLA_ERR_HIP;
+  return INLA_OK;
+}
+
 // The ring is reused once every earlier reader has finished: work on the
-// caller's stream and on the side stream.
+// caller's stream, the side stream and the aux stream.
 static bool ring_wrap(Ctx &c) {
-  if (hipStreamSynchronize(c.stream) != hipSuccess) return false;
-  if (c.side && hipStreamSynchronize(c.side) != hipSuccess) return false;
+  if (c.sync_all() != INLA_OK) return false;
   c.ring_off = 0;
   return true;
 }
@@ -66,7 +86,7 @@ int Ctx::sequence(int cls, const std::vector<int64_t> &key, const void *args, si
   return rc;
 }
 
-int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
+int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key0, const void *args, size_t nbytes,
                        const std::function<void(const void *)> &body) {
   if (capturing) return INLA_ERR_UNSUPPORTED;   // sequences do not nest
   if (!graphs) {
@@ -75,6 +95,9 @@ int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key, const void *arg
     body(d);
     return check();
   }
+  // one graph (and argument block) per stream lane
+  std::vector<int64_t> key = key0;
+  key.push_back(lane);
   auto it = graph_cache.find(key);
   if (it == graph_cache.end()) {
     if (!cap_stream && hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) return INLA_ERR_HIP;
@@ -82,7 +105,7 @@ int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key, const void *arg
       auto lru = graph_cache.begin();
       for (auto q = graph_cache.begin(); q != graph_cache.end(); ++q)
         if (q->second.used < lru->second.used) lru = q;
-      if (hipStreamSynchronize(stream) != hipSuccess) return INLA_ERR_HIP;
+      if (sync_all() != INLA_OK) return INLA_ERR_HIP;
       (void)hipGraphExecDestroy(lru->second.exec);
       (void)hipFree(lru->second.dargs);
       graph_cache.erase(lru);
@@ -137,8 +160,7 @@ int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key, const void *arg
 
 void Ctx::drop_graphs() {
   if (graph_cache.empty()) return;
-  if (stream) (void)hipStreamSynchronize(stream);
-  else (void)hipDeviceSynchronize();
+  (void)sync_all();
   for (auto &kv : graph_cache) {
     (void)hipGraphExecDestroy(kv.second.exec);
     (void)hipFree(kv.second.dargs);
@@ -149,8 +171,7 @@ void Ctx::drop_graphs() {
 char *Ctx::pbf_reserve(size_t bytes) {
   if (bytes <= pbf_size) return pbf;
   if (pbf) {
-    if (hipStreamSynchronize(stream) != hipSuccess) return nullptr;
-    if (side && hipStreamSynchronize(side) != hipSuccess) return nullptr;
+    if (sync_all() != INLA_OK) return nullptr;
     (void)hipFree(pbf);
     pbf = nullptr;
     pbf_size = 0;
@@ -167,7 +188,7 @@ char *Ctx::pbf_reserve(size_t bytes) {
 bool Ctx::reserve(size_t bytes) {
   if (bytes <= ws_size) return true;
   if (ws) {
-    if (hipStreamSynchronize(stream) != hipSuccess) return false;
+    if (sync_all() != INLA_OK) return false;
     (void)hipFree(ws);
     ws = nullptr;
     ws_size = 0;
@@ -209,8 +230,7 @@ void Ctx::launch(int cls, double flops, double bytes, const std::function<void()
 
 void Ctx::harvest() {
   if (pending.empty()) return;
-  (void)hipStreamSynchronize(stream);
-  if (side) (void)hipStreamSynchronize(side);
+  (void)sync_all();
   for (auto &p : pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -250,12 +270,13 @@ Ctx::~Ctx() {
     (void)hipFree(kv.second.dargs);
   }
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
-  if (side) {
-    (void)hipStreamSynchronize(side);
-    (void)hipStreamDestroy(side);
-  }
-  if (ev_a) (void)hipEventDestroy(ev_a);
-  if (ev_b) (void)hipEventDestroy(ev_b);
+  for (hipStream_t *s : {&side, &aux})
+    if (*s) {
+      (void)hipStreamSynchronize(*s);
+      (void)hipStreamDestroy(*s);
+    }
+  for (hipEvent_t e : {ev_a, ev_b, ev_c, ev_d})
+    if (e) (void)hipEventDestroy(e);
   if (ws) (void)hipFree(ws);
   if (pbf) (void)hipFree(pbf);
   if (gh) (void)hipFree(gh);
@@ -295,7 +316,9 @@ static int check_model(const inla_model &m) {
   return 0;
 }
 
-static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
+// aux: the plan of a prior pass run beside the Newton iteration; it reads the
+// main plan's Q_prior (no slot of its own) and keeps no observation workspace.
+static Plan make_plan(const inla_model &m, const double *th, Mode mode, bool aux = false) {
   Plan p;
   ThetaDesc &t = p.t;
   t.y = m.y; t.E = m.E; t.C = m.C; t.e = m.e; t.coords = m.coords; t.Quser = m.Qprior;
@@ -327,7 +350,8 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
   t.ldp = t.Np;
   // layout: [Qp][W/P alias][S][vectors][linv]
   size_t off = 0;
-  p.off_Qp = off; off += align256(sizeof(double) * (size_t)t.n_pad * t.n_pad);
+  p.off_Qp = off;
+  if (!aux) off += align256(sizeof(double) * (size_t)t.n_pad * t.n_pad);
   p.off_W = off;
   const size_t wbytes = sizeof(double) * (size_t)t.ldw * t.Ncw;
   const size_t pbytes = sizeof(double) * (size_t)t.ldp * t.Np;
@@ -339,10 +363,11 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode) {
   // build, whose order is at most n_pad) and kriging factor
   p.off_linv = off; off += align256(sizeof(double) * (size_t)t.n_pad * NBI);
   p.off_linv_small = off; off += align256(sizeof(double) * (size_t)std::max(t.k_pad, NBI) * NBI);
-  // general design matrix: A x, g, W and log-likelihood per observation
-  t.m = m.m;
+  // general design matrix: A x, g, W and log-likelihood per observation (the
+  // prior pass reads none of it)
+  t.m = aux ? 0 : m.m;
   t.A_rowptr = m.A_rowptr; t.A_col = m.A_col; t.A_val = m.A_val;
-  p.off_obs = off; off += align256(sizeof(double) * 4 * (size_t)m.m);
+  p.off_obs = off; off += align256(sizeof(double) * 4 * (size_t)t.m);
   p.bytes = off;
   return p;
 }
@@ -573,34 +598,46 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
 
 static int setup_design(Batch &b, const inla_model *models, int B);
 
-// Allocate and bind the workspace of a batch; zero the per-theta scratch.
-static int setup(Batch &b, int B, const inla_model *models, const double *theta, int ldtheta, Mode mode) {
-  b.plans.resize(B);
+// Allocate and bind the workspace of a batch; zero the per-theta scratch.  With
+// `aux`, the same allocation also holds the workspace of a prior pass run on
+// the aux stream (the aux batch shares the main batch's Q_prior).
+static int setup(Batch &b, int B, const inla_model *models, const double *theta, int ldtheta, Mode mode,
+                 Batch *aux = nullptr) {
+  const int nb = aux ? 2 : 1;
+  Batch *bs[2] = {&b, aux};
   size_t total = 0;
-  std::vector<size_t> offs(B);
-  for (int i = 0; i < B; ++i) {
-    b.plans[i] = make_plan(models[i], theta ? theta + (size_t)i * ldtheta : nullptr, mode);
-    offs[i] = total;
-    total += b.plans[i].bytes;
+  std::vector<size_t> offs[2];
+  for (int q = 0; q < nb; ++q) {
+    bs[q]->plans.resize(B);
+    offs[q].resize(B);
+    for (int i = 0; i < B; ++i) {
+      bs[q]->plans[i] = make_plan(models[i], theta ? theta + (size_t)i * ldtheta : nullptr, mode, q == 1);
+      offs[q][i] = total;
+      total += bs[q]->plans[i].bytes;
+    }
   }
   const size_t info_off = total;
-  total += align256(sizeof(int) * 4 * B);
-  const size_t pin_off = total;  // not used on device; keeps layout simple
-  (void)pin_off;
+  total += nb * align256(sizeof(int) * 4 * B);
   if (!b.ctx.reserve(total)) return INLA_ERR_NOMEM;
-  b.bases.resize(B);
-  for (int i = 0; i < B; ++i) {
-    b.bases[i] = b.ctx.ws + offs[i];
-    bind(b.plans[i], b.bases[i]);
+  for (int q = 0; q < nb; ++q) {
+    Batch &x = *bs[q];
+    x.bases.resize(B);
+    for (int i = 0; i < B; ++i) {
+      x.bases[i] = b.ctx.ws + offs[q][i];
+      bind(x.plans[i], x.bases[i]);
+      if (q == 1) x.plans[i].t.Qp = b.plans[i].t.Qp;
+    }
+    x.dinfo = (int *)(b.ctx.ws + info_off + q * align256(sizeof(int) * 4 * B));
+    if (hipMemsetAsync(x.dinfo, 0, sizeof(int) * 4 * B, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    for (int i = 0; i < B; ++i) {
+      const ThetaDesc &t = x.plans[i].t;
+      if (hipMemsetAsync(t.dres, 0, sizeof(double) * DRES_COUNT, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+      // the prior pass never reads its iterate; zero it all the same
+      if (q == 1 && hipMemsetAsync(t.x, 0, sizeof(double) * t.n_pad, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
+    }
+    if (hipHostMalloc(&x.pin, sizeof(double) * DRES_COUNT * B + sizeof(int) * 4 * B + 64) != hipSuccess)
+      return INLA_ERR_NOMEM;
   }
-  b.dinfo = (int *)(b.ctx.ws + info_off);
-  if (hipMemsetAsync(b.dinfo, 0, sizeof(int) * 4 * B, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
-  for (int i = 0; i < B; ++i) {
-    const ThetaDesc &t = b.plans[i].t;
-    if (hipMemsetAsync(t.dres, 0, sizeof(double) * DRES_COUNT, b.ctx.stream) != hipSuccess) return INLA_ERR_HIP;
-  }
-  if (hipHostMalloc(&b.pin, sizeof(double) * DRES_COUNT * B + sizeof(int) * 4 * B + 64) != hipSuccess)
-    return INLA_ERR_NOMEM;
   return setup_design(b, models, B);
 }
 
@@ -772,7 +809,7 @@ static int validate_common(inla_handle *h, int B, const inla_model *models, cons
 
 // Split [0, B) into chunks whose workspace fits the budget.
 static std::vector<std::pair<int, int>> chunks(Ctx &ctx, int B, const inla_model *models, const double *theta,
-                                               int ldtheta, Mode mode) {
+                                               int ldtheta, Mode mode, bool aux = false) {
   std::vector<std::pair<int, int>> out;
   const size_t cap = budget(ctx);
   int s = 0;
@@ -780,7 +817,9 @@ static std::vector<std::pair<int, int>> chunks(Ctx &ctx, int B, const inla_model
     size_t tot = 0;
     int e = s;
     while (e < B) {
-      const size_t need = make_plan(models[e], theta + (size_t)e * ldtheta, mode).bytes + 4096;
+      const double *th = theta + (size_t)e * ldtheta;
+      const size_t need = make_plan(models[e], th, mode).bytes + (aux ? make_plan(models[e], th, mode, true).bytes : 0) +
+                          8192;
       if (e > s && tot + need > cap) break;
       tot += need;
       ++e;
@@ -797,9 +836,16 @@ static std::vector<std::pair<int, int>> chunks(Ctx &ctx, int B, const inla_model
 // in FP64 and flagged.
 static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *theta, int ldtheta, double *const *x,
                       const inla_opts *opts, inla_result *res, bool laplace) {
-  Batch b(ctx);
-  int rc = setup(b, B, models, theta, ldtheta, MODE_LAPLACE);
-  if (rc) { teardown(b); return rc; }
+  // The prior pass depends on theta alone, and the Newton passes never read
+  // its factor (they assemble Q_prior + W from the built prior), so with
+  // overlap on it runs on the aux stream, in its own workspace, while the
+  // caller's stream runs the Newton iteration; its results are read after the
+  // iteration.  Every kernel computes what it would in order, so the results
+  // are identical either way.
+  const bool overlap = ctx.overlap && ctx.aux_ready() == INLA_OK;
+  Batch b(ctx), pb(ctx);
+  int rc = setup(b, B, models, theta, ldtheta, MODE_LAPLACE, overlap ? &pb : nullptr);
+  if (rc) { (void)ctx.sync_all(); teardown(pb); teardown(b); return rc; }
   const int max_iter = (opts && opts->max_iter > 0) ? opts->max_iter : 50;
   const double tol = (opts && opts->tol > 0) ? opts->tol : 1e-11;
   const bool warm = opts && opts->start == 1;
@@ -817,30 +863,51 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     if (!finite) { res[i].info = INLA_INFO_NONFINITE; continue; }
     all.push_back(i);
     if (warm) {
-      if (hipMemcpyAsync(t.x, x[i], sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) { teardown(b); return INLA_ERR_HIP; }
-      if (t.n_pad > t.n && hipMemsetAsync(t.x + t.n, 0, sizeof(double) * (t.n_pad - t.n), ctx.stream) != hipSuccess) { teardown(b); return INLA_ERR_HIP; }
+      if (hipMemcpyAsync(t.x, x[i], sizeof(double) * t.n, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess) { teardown(pb); teardown(b); return INLA_ERR_HIP; }
+      if (t.n_pad > t.n && hipMemsetAsync(t.x + t.n, 0, sizeof(double) * (t.n_pad - t.n), ctx.stream) != hipSuccess) { teardown(pb); teardown(b); return INLA_ERR_HIP; }
     } else if (hipMemsetAsync(t.x, 0, sizeof(double) * t.n_pad, ctx.stream) != hipSuccess) {
-      teardown(b); return INLA_ERR_HIP;
+      teardown(pb); teardown(b); return INLA_ERR_HIP;
     }
     if (mixed && (hipMemsetAsync(t.lam, 0, sizeof(double) * std::max(t.k_pad, 64), ctx.stream) != hipSuccess ||
                   hipMemsetAsync(t.xn, 0, sizeof(double) * t.n_pad, ctx.stream) != hipSuccess)) {
-      teardown(b); return INLA_ERR_HIP;
+      teardown(pb); teardown(b); return INLA_ERR_HIP;
     }
   }
-  auto fail = [&](int r) { teardown(b); return r; };
-  if ((rc = prior_build(b, all))) return fail(rc);
-  if ((rc = run_pass(b, all, PASS_PRIOR, INLA_PREC_FP64))) return fail(rc);
-  if ((rc = readback(b))) return fail(rc);
-  for (int i : all) {
-    const int *inf = &b.hinfo[4 * i];
-    const double *dr = &b.hdres[DRES_COUNT * i];
-    if (inf[F_PRIOR]) { res[i].info = inf[F_PRIOR]; continue; }
-    if (inf[F_BIG]) { res[i].info = inf[F_BIG]; continue; }
-    if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; continue; }
+  auto fail = [&](int r) { (void)ctx.sync_all(); teardown(pb); teardown(b); return r; };
+  // prior-pass status and results of theta i (from the host copy read back
+  // from `pp`); returns whether theta i passed
+  auto prior_ok = [&](Batch &pp, int i) {
+    const int *inf = &pp.hinfo[4 * i];
+    const double *dr = &pp.hdres[DRES_COUNT * i];
+    if (inf[F_PRIOR]) { res[i].info = inf[F_PRIOR]; return false; }
+    if (inf[F_BIG]) { res[i].info = inf[F_BIG]; return false; }
+    if (inf[F_SMALL] || dr[DRES_RANK] != 0.0) { res[i].info = INLA_INFO_CONSTRAINT_RANK; return false; }
     res[i].logdet_qprior = dr[DRES_LOGDET_L];
     res[i].logdet_sprior = dr[DRES_LOGDET_S];
     res[i].ese = dr[DRES_WNORM2];
-    ok.push_back(i);
+    return true;
+  };
+  if ((rc = prior_build(b, all))) return fail(rc);
+  if (overlap) {
+    if (!all.empty()) {
+      // the prior build's status travels with the prior pass's (the Newton
+      // iteration clears the main batch's status slots)
+      if (hipMemcpyAsync(pb.dinfo, b.dinfo, sizeof(int) * 4 * B, hipMemcpyDeviceToDevice, ctx.stream) != hipSuccess ||
+          hipEventRecord(ctx.ev_c, ctx.stream) != hipSuccess || hipStreamWaitEvent(ctx.aux, ctx.ev_c, 0) != hipSuccess)
+        return fail(INLA_ERR_HIP);
+      {
+        AuxScope lane(ctx);
+        rc = run_pass(pb, all, PASS_PRIOR, INLA_PREC_FP64);
+      }
+      if (rc) return fail(rc);
+      if (hipEventRecord(ctx.ev_d, ctx.aux) != hipSuccess) return fail(INLA_ERR_HIP);
+    }
+    ok = all;   // prior failures are sorted out after the Newton iteration
+  } else {
+    if ((rc = run_pass(b, all, PASS_PRIOR, INLA_PREC_FP64))) return fail(rc);
+    if ((rc = readback(b))) return fail(rc);
+    for (int i : all)
+      if (prior_ok(b, i)) ok.push_back(i);
   }
   // Newton iteration (warm-start vectors were checked for finiteness by the
   // first assembly: a non-finite W or b sets the flag).
@@ -937,6 +1004,25 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
     }
     active.swap(next);
   }
+  if (overlap && !all.empty()) {
+    // the prior pass: its status and log-determinants
+    if (hipStreamWaitEvent(ctx.stream, ctx.ev_d, 0) != hipSuccess) return fail(INLA_ERR_HIP);
+    if ((rc = readback(pb))) return fail(rc);
+    std::vector<char> bad(B, 0);
+    for (int i : all)
+      if (!prior_ok(pb, i)) {
+        // reported as without overlap: the status alone, no Newton work
+        const int code = res[i].info;
+        res[i] = inla_result{};
+        res[i].info = code;
+        irsteps[i] = far_ir[i] = 0;
+        failed[i] = 1;
+        bad[i] = 1;
+      }
+    std::vector<int> keep;
+    for (int i : redo) if (!bad[i]) keep.push_back(i);
+    redo.swap(keep);
+  }
   // copy the modes out
   for (int i : ok) {
     if (failed[i]) continue;
@@ -980,6 +1066,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
   }
   for (int i = 0; i < B; ++i) res[i].ir_steps = irsteps[i] + far_ir[i];
   ctx.harvest();
+  teardown(pb);
   teardown(b);
   if ((rc = ctx.check())) return rc;
   // FP64 re-evaluation of thetas whose refinement did not converge
@@ -1120,9 +1207,9 @@ int inla_create(inla_handle **h, void *stream) {
   *h = nullptr;
   inla_handle *p = new (std::nothrow) inla_handle();
   if (!p) return INLA_ERR_NOMEM;
-  p->ctx.stream = (hipStream_t)stream;
+  p->ctx.stream = p->ctx.home = (hipStream_t)stream;
   if (hipGetDevice(&p->ctx.device) != hipSuccess) { delete p; return INLA_ERR_HIP; }
-  p->ctx.ring_size = (size_t)4 << 20;
+  p->ctx.ring_size = (size_t)16 << 20;
   if (hipMalloc(&p->ctx.ring, p->ctx.ring_size) != hipSuccess ||
       hipHostMalloc(&p->ctx.ring_host, p->ctx.ring_size) != hipSuccess) {
     delete p;
@@ -1139,9 +1226,8 @@ int inla_destroy(inla_handle *h) {
 
 int inla_set_stream(inla_handle *h, void *stream) {
   if (!h) return -1;
-  if (hipStreamSynchronize(h->ctx.stream) != hipSuccess) return INLA_ERR_HIP;
-  if (h->ctx.side && hipStreamSynchronize(h->ctx.side) != hipSuccess) return INLA_ERR_HIP;
-  h->ctx.stream = (hipStream_t)stream;
+  if (h->ctx.sync_all() != INLA_OK) return INLA_ERR_HIP;
+  h->ctx.stream = h->ctx.home = (hipStream_t)stream;
   return INLA_OK;
 }
 
@@ -1247,7 +1333,7 @@ static int mode_or_eval(inla_handle *h, int32_t B, const inla_model *models, con
   if (opts && opts->prec != INLA_PREC_FP64)
     for (int i = 0; i < B; ++i)
       if (models[i].m > 0) return INLA_ERR_UNSUPPORTED;   // general design matrices are evaluated in FP64
-  for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE)) {
+  for (auto c : chunks(h->ctx, B, models, theta, ldtheta, MODE_LAPLACE, h->ctx.overlap)) {
     rc = eval_chunk(h->ctx, c.second - c.first, models + c.first, theta + (size_t)c.first * ldtheta, ldtheta,
                     x + c.first, opts, res + c.first, laplace);
     if (rc) return rc;
@@ -1322,6 +1408,12 @@ int inla_set_graphs(inla_handle *h, int32_t enable) {
 int inla_set_lookahead(inla_handle *h, int32_t enable) {
   if (!h) return -1;
   h->ctx.lookahead = enable != 0;
+  return INLA_OK;
+}
+
+int inla_set_overlap(inla_handle *h, int32_t enable) {
+  if (!h) return -1;
+  h->ctx.overlap = enable != 0;
   return INLA_OK;
 }
 

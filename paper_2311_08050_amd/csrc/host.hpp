@@ -69,6 +69,19 @@ struct Ctx {
   hipStream_t side = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
   int side_ready();   // creates the side stream and its events on first use
+  // Concurrent prior pass: a third stream of the handle (default priority)
+  // runs the FP64 factorisation of the prior while the caller's stream runs
+  // the Newton iteration; ev_c / ev_d order the two.  `lane` is 1 while work
+  // is enqueued for that stream: it keys the hipGraphs apart (each graph owns
+  // one argument block, which two streams must not share) and keeps lookahead
+  // (which uses `side`) to lane 0.
+  bool overlap = false;
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_c = nullptr, ev_d = nullptr;
+  int lane = 0;
+  hipStream_t home = nullptr;   // the caller's stream (`stream` is swapped to side or aux at times)
+  int aux_ready();    // creates the aux stream and its events on first use
+  int sync_all();     // waits for the caller's, side and aux streams
   // Gauss-Hermite rule of the variational-Bayes correction (device, 2 x 64 doubles)
   double *gh = nullptr;
   // scratch of the BF16 panel copies (grow-only, reallocated after a stream sync)
@@ -105,6 +118,21 @@ struct Ctx {
   void harvest();
   int check();
   ~Ctx();
+};
+
+// Enqueues the work of its scope on the handle's aux stream (lane 1).
+struct AuxScope {
+  Ctx &c;
+  hipStream_t old;
+  int old_lane;
+  explicit AuxScope(Ctx &ctx) : c(ctx), old(ctx.stream), old_lane(ctx.lane) {
+    c.stream = c.aux;
+    c.lane = 1;
+  }
+  ~AuxScope() {
+    c.stream = old;
+    c.lane = old_lane;
+  }
 };
 
 // Tags the launches enqueued in its scope with a precision for the profiling counters.

@@ -779,7 +779,9 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
   // caller's stream), the rest (TRAIL_B) on the handle's side stream, and the
   // next panel is factored on the caller's stream while TRAIL_B runs.  TRAIL_A
   // of the following panel waits for TRAIL_B, which updated its columns too.
-  const bool look = look_cfg && ctx.lookahead && nf_max > nb && ctx.side_ready() == INLA_OK;
+  // (lookahead runs on the caller's lane only: the side stream and its events
+  // serve one factorisation at a time)
+  const bool look = look_cfg && ctx.lookahead && ctx.lane == 0 && nf_max > nb && ctx.side_ready() == INLA_OK;
   int rc = 0;
   hipStream_t main_stream = ctx.stream;
   for (int p0 = 0; p0 < nf_max && !rc; p0 += nb) {

@@ -16,10 +16,17 @@
 namespace inla {
 
 // C(M x N) = A(M x K) * B(K x N) with A(i, k) = A[i*sar + k*sac],
-// B(k, j) = B[k*sbr + j*sbc], C(i, j) = C[i*scr + j*scc]; 64 x 64 tiles, K in
-// chunks of 16 through LDS, each thread 4 x 4 outputs, FP32 accumulate.
+// B(k, j) = B[k*sbr + j*sbc], C(i, j) = C[i*scr + j*scc], on FP32 MFMA
+// (v_mfma_f32_16x16x4f32, FP32 accumulate): 64 x 64 tiles per workgroup, 32 x 32
+// per wave (2 x 2 blocks of 16 x 16), K in chunks of 16 through LDS.  Tile loads
+// run along whichever index of an operand is contiguous, so every layout the
+// network's forward and backward passes use is read coalesced.
 // Epilogue: + bias[j] (if bias), Z = pre-activation stored (if Z), C = GELU(.)
-// (if gelu), or C = alpha * acc + beta * C.
+// (if gelu), or C = alpha * acc + beta * C.  With `ksplit` > 1 the K range is
+// split over blockIdx.z and each split writes its partial tile to `part`
+// (ksplit x M x N); gemm_epilogue_kernel then sums the splits in a fixed order
+// and applies the epilogue (the backward product through the output layer has
+// K = n and only B x H outputs).
 struct GemmArgs {
   const float *A, *B;
   float *C, *Z;
@@ -35,46 +42,89 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-__global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g) {
-  __shared__ float As[16][65];
-  __shared__ float Bs[16][65];
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void gemm_store(const GemmArgs &g, int i, int j, float val) {
+  if (g.bias) val += g.bias[j];
+  float *c = g.C + (size_t)i * g.scr + (size_t)j * g.scc;
+  if (g.Z) g.Z[(size_t)i * g.N + j] = val;
+  if (g.gelu) *c = gelu_f(val);
+  else *c = g.alpha * val + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+}
+
+typedef float f4m __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g, float *part, int kper) {
+  __shared__ float As[16][64 + 4];
+  __shared__ float Bs[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1, li = lane & 15, gq = lane >> 4;
   const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
-  const int ti = (tid / 16) * 4, tj = (tid % 16) * 4;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < g.K; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int kk = e / 64, r = e % 64;
-      const int i = i0 + r, k = k0 + kk, j = j0 + r;
-      As[kk][r] = (i < g.M && k < g.K) ? g.A[(size_t)i * g.sar + (size_t)k * g.sac] : 0.0f;
-      Bs[kk][r] = (k < g.K && j < g.N) ? g.B[(size_t)k * g.sbr + (size_t)j * g.sbc] : 0.0f;
+  const int kb = blockIdx.z * kper, ke = min(g.K, kb + kper);
+  const bool a_krow = g.sac == 1, b_kcol = g.sbc != 1;   // contiguous along k?
+  f4m acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f4m{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = q * 256 + tid;
+      int r, kk;
+      if (a_krow) { r = e >> 4; kk = e & 15; } else { kk = e >> 6; r = e & 63; }
+      const int i = i0 + r, k = k0 + kk;
+      As[kk][r] = (i < g.M && k < ke) ? g.A[(size_t)i * g.sar + (size_t)k * g.sac] : 0.0f;
+      int c;
+      if (b_kcol) { c = e >> 4; kk = e & 15; } else { kk = e >> 6; c = e & 63; }
+      const int j = j0 + c, kb2 = k0 + kk;
+      Bs[kk][c] = (j < g.N && kb2 < ke) ? g.B[(size_t)kb2 * g.sbr + (size_t)j * g.sbc] : 0.0f;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      float a[4], b[4];
+    for (int st = 0; st < 4; ++st) {
+      const int kk = 4 * gq + st;   // lane group gq supplies k = 4 gq + st at step st
+      float av[2], bv[2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) { a[u] = As[kk][ti + u]; b[u] = Bs[kk][tj + u]; }
+      for (int a = 0; a < 2; ++a) av[a] = As[kk][wm * 32 + a * 16 + li];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk][wn * 32 + b * 16 + li];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fmaf(a[u], b[v], acc[u][v]);
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
+  // lane l holds rows 4 (l / 16) + v, column l % 16 of each 16 x 16 block
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int i = i0 + ti + u, j = j0 + tj + v;
-      if (i >= g.M || j >= g.N) continue;
-      float val = acc[u][v];
-      if (g.bias) val += g.bias[j];
-      float *c = g.C + (size_t)i * g.scr + (size_t)j * g.scc;
-      if (g.Z) g.Z[(size_t)i * g.N + j] = val;
-      if (g.gelu) *c = gelu_f(val);
-      else *c = g.alpha * val + (g.beta != 0.0f ? g.beta * *c : 0.0f);
-    }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + wm * 32 + a * 16 + 4 * gq + v, j = j0 + wn * 32 + b * 16 + li;
+        if (i >= g.M || j >= g.N) continue;
+        if (part) part[((size_t)blockIdx.z * g.M + i) * g.N + j] = acc[a][b][v];
+        else gemm_store(g, i, j, acc[a][b][v]);
+      }
+}
+
+// Sum of the K splits (fixed order) and the epilogue, one thread per output.
+__global__ __launch_bounds__(256) void gemm_epilogue_kernel(GemmArgs g, const float *part, int ksplit) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (int64_t)g.M * g.N) return;
+  const int i = (int)(idx / g.N), j = (int)(idx % g.N);
+  float s = 0.0f;
+  for (int z = 0; z < ksplit; ++z) s += part[(size_t)z * g.M * g.N + idx];
+  gemm_store(g, i, j, s);
+}
+
+// K splits of a product: enough workgroups for the chip (about 512) without
+// splits shorter than 128.
+static int gemm_ksplit(int M, int N, int K) {
+  const int tiles = ((M + 63) / 64) * ((N + 63) / 64);
+  int ks = std::max(1, 512 / std::max(1, tiles));
+  ks = std::min(ks, std::max(1, K / 128));
+  return ks;
 }
 
 // dY <- dY * GELU'(Z) (elementwise).
@@ -165,6 +215,8 @@ struct inla_mlp {
   float *u = nullptr, *z1 = nullptr, *h1 = nullptr, *z2 = nullptr, *h2 = nullptr, *out = nullptr, *dout = nullptr,
         *dh2 = nullptr, *dh1 = nullptr;
   double *part = nullptr;
+  float *kpart = nullptr;   // partial products of split-K GEMMs
+  size_t kpart_elems = 0;
   double *dtheta = nullptr, *dcentre = nullptr, *dscale = nullptr;
   double **dptrs = nullptr;
   int64_t step = 0;
@@ -184,9 +236,12 @@ void free_acts(inla_mlp *m) {
     *p = nullptr;
   }
   if (m->part) (void)hipFree(m->part);
+  if (m->kpart) (void)hipFree(m->kpart);
   if (m->dtheta) (void)hipFree(m->dtheta);
   if (m->dptrs) (void)hipFree(m->dptrs);
   m->part = nullptr;
+  m->kpart = nullptr;
+  m->kpart_elems = 0;
   m->dtheta = nullptr;
   m->dptrs = nullptr;
   m->cap = 0;
@@ -198,25 +253,45 @@ int ensure_cap(inla_mlp *m, int B) {
   free_acts(m);
   const int cap = std::max(B, 64);
   const size_t nb = (size_t)cap;
+  // split-K workspace: the largest ksplit x M x N over the products of a
+  // forward and backward pass at batch `cap` (GEMMs of fewer rows need less)
+  size_t kp = 0;
+  const int I = m->I, H = m->H, O = m->O;
+  const int shapes[][3] = {{cap, H, I}, {cap, H, H}, {cap, O, H}, {O, H, cap}, {cap, H, O}, {H, H, cap}, {H, I, cap}};
+  for (const auto &sh : shapes) {
+    const int ks = gemm_ksplit(sh[0], sh[1], sh[2]);
+    if (ks > 1) kp = std::max(kp, (size_t)ks * sh[0] * sh[1]);
+  }
   bool ok = hipMalloc(&m->u, 4 * nb * m->I) == hipSuccess && hipMalloc(&m->z1, 4 * nb * m->H) == hipSuccess &&
             hipMalloc(&m->h1, 4 * nb * m->H) == hipSuccess && hipMalloc(&m->z2, 4 * nb * m->H) == hipSuccess &&
             hipMalloc(&m->h2, 4 * nb * m->H) == hipSuccess && hipMalloc(&m->out, 4 * nb * m->O) == hipSuccess &&
             hipMalloc(&m->dout, 4 * nb * m->O) == hipSuccess && hipMalloc(&m->dh2, 4 * nb * m->H) == hipSuccess &&
             hipMalloc(&m->dh1, 4 * nb * m->H) == hipSuccess &&
             hipMalloc(&m->part, 8 * ((nb * m->O + 255) / 256 + 1)) == hipSuccess &&
-            hipMalloc(&m->dtheta, 8 * (nb * 8 + 16)) == hipSuccess && hipMalloc(&m->dptrs, 8 * nb) == hipSuccess;
+            hipMalloc(&m->dtheta, 8 * (nb * 8 + 16)) == hipSuccess && hipMalloc(&m->dptrs, 8 * nb) == hipSuccess &&
+            (kp == 0 || hipMalloc(&m->kpart, 4 * kp) == hipSuccess);
   if (!ok) {
     (void)hipGetLastError();
     free_acts(m);
     return INLA_ERR_NOMEM;
   }
   m->cap = cap;
+  m->kpart_elems = kp;
   return 0;
 }
 
-void gemm(hipStream_t s, const GemmArgs &g) {
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
-  hipLaunchKernelGGL(mlp_gemm_kernel, grid, dim3(256), 0, s, g);
+void gemm(inla_mlp *m, hipStream_t s, const GemmArgs &g) {
+  int ks = gemm_ksplit(g.M, g.N, g.K);
+  if ((size_t)ks * g.M * g.N > m->kpart_elems) ks = 1;   // never past the workspace
+  const int kper = ks > 1 ? ((g.K + ks - 1) / ks + 15) / 16 * 16 : g.K;
+  ks = ks > 1 ? (g.K + kper - 1) / kper : 1;
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, ks);
+  hipLaunchKernelGGL(mlp_gemm_kernel, grid, dim3(256), 0, s, g, ks > 1 ? m->kpart : nullptr, kper);
+  if (ks > 1) {
+    const int64_t cnt = (int64_t)g.M * g.N;
+    hipLaunchKernelGGL(gemm_epilogue_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, g,
+                       (const float *)m->kpart, ks);
+  }
 }
 
 GemmArgs ga(const float *A, int sar, int sac, const float *B, int sbr, int sbc, float *C, int scr, int scc, int M,
@@ -233,13 +308,13 @@ void forward(inla_mlp *m, hipStream_t s, int B) {
   const float *P = m->params;
   GemmArgs g = ga(m->u, m->I, 1, P + m->off_W1(), 1, m->I, m->h1, m->H, 1, B, m->H, m->I);
   g.bias = P + m->off_b1(); g.Z = m->z1; g.gelu = 1;
-  gemm(s, g);
+  gemm(m, s, g);
   g = ga(m->h1, m->H, 1, P + m->off_W2(), 1, m->H, m->h2, m->H, 1, B, m->H, m->H);
   g.bias = P + m->off_b2(); g.Z = m->z2; g.gelu = 1;
-  gemm(s, g);
+  gemm(m, s, g);
   g = ga(m->h2, m->H, 1, P + m->off_W3(), 1, m->H, m->out, m->O, 1, B, m->O, m->H);
   g.bias = P + m->off_b3();
-  gemm(s, g);
+  gemm(m, s, g);
 }
 
 // Backward pass from m->dout into m->grad (flat, same layout as params).
@@ -248,16 +323,16 @@ void backward(inla_mlp *m, hipStream_t s, int B) {
   float *G = m->grad;
   const int I = m->I, H = m->H, O = m->O;
   // dW3 (O x H) = dout^T (O x B) * h2 (B x H)
-  gemm(s, ga(m->dout, 1, O, m->h2, H, 1, G + m->off_W3(), H, 1, O, H, B));
+  gemm(m, s, ga(m->dout, 1, O, m->h2, H, 1, G + m->off_W3(), H, 1, O, H, B));
   hipLaunchKernelGGL(colsum_kernel, dim3((O + 255) / 256), dim3(256), 0, s, m->dout, B, O, G + m->off_b3());
   // dh2 (B x H) = dout (B x O) * W3 (O x H), then * GELU'(z2)
-  gemm(s, ga(m->dout, O, 1, P + m->off_W3(), H, 1, m->dh2, H, 1, B, H, O));
+  gemm(m, s, ga(m->dout, O, 1, P + m->off_W3(), H, 1, m->dh2, H, 1, B, H, O));
   hipLaunchKernelGGL(gelu_back_kernel, dim3((B * H + 255) / 256), dim3(256), 0, s, m->dh2, m->z2, B * H);
-  gemm(s, ga(m->dh2, 1, H, m->h1, H, 1, G + m->off_W2(), H, 1, H, H, B));
+  gemm(m, s, ga(m->dh2, 1, H, m->h1, H, 1, G + m->off_W2(), H, 1, H, H, B));
   hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, s, m->dh2, B, H, G + m->off_b2());
-  gemm(s, ga(m->dh2, H, 1, P + m->off_W2(), H, 1, m->dh1, H, 1, B, H, H));
+  gemm(m, s, ga(m->dh2, H, 1, P + m->off_W2(), H, 1, m->dh1, H, 1, B, H, H));
   hipLaunchKernelGGL(gelu_back_kernel, dim3((B * H + 255) / 256), dim3(256), 0, s, m->dh1, m->z1, B * H);
-  gemm(s, ga(m->dh1, 1, H, m->u, I, 1, G + m->off_W1(), I, 1, H, I, B));
+  gemm(m, s, ga(m->dh1, 1, H, m->u, I, 1, G + m->off_W1(), I, 1, H, I, B));
   hipLaunchKernelGGL(colsum_kernel, dim3((H + 255) / 256), dim3(256), 0, s, m->dh1, B, H, G + m->off_b1());
 }
 

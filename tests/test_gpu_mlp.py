@@ -90,32 +90,33 @@ def test_adam_step_matches_reference(net):
 
 
 def test_adam_sequence_matches_reference(net):
-    """Six Adam steps in a row (moment accumulation and bias correction from step
-    2 on) against the FP64 reference run on the same batch from the same
-    parameters.  On parameters whose gradient stays well above the FP32
-    gradient error at every step, the total move agrees to 1e-4 of the largest
-    possible move (steps x lr) plus the FP32 storage rounding of the parameters."""
+    """Six Adam steps in a row: moment accumulation and bias correction from
+    step 2 on.  Each GPU step is compared with the FP64 reference's Adam update
+    applied to the same parameters and the same gradient (the GPU's own, read
+    with inla_mlp_grad, which runs the kernels the step runs), with moments
+    accumulated in FP64 over the sequence; the bound is the FP32 rounding of
+    the parameters plus 1e-5 of a step."""
     import torch
     m, p, u, t, (I, H, O) = net
     steps, lr = 6, 1e-3
     say("mlp adam, six steps")
     m.set_params(torch.tensor(p.astype(np.float32)))
     U, T = torch.tensor(u).cuda(), torch.tensor(t).cuda()
-    for _ in range(steps):
-        m.train_step(U, T, lr)
-    new = m.get_params().cpu().numpy().astype(np.float64)
-    ref, mom, vel = p.copy(), np.zeros_like(p), np.zeros_like(p)
-    big = np.ones(p.size, dtype=bool)
+    cur = m.get_params().cpu().numpy().astype(np.float64)
+    mom, vel = np.zeros_like(cur), np.zeros_like(cur)
     for s in range(1, steps + 1):
-        _, g = M.grad(ref, u.astype(np.float64), t, I, H, O)
-        big &= np.abs(g) >= 1e-3 * np.max(np.abs(g))
-        ref, mom, vel = M.adam(ref, g, mom, vel, s, lr)
-    assert big.sum() > 0.5 * p.size
-    move, ref_move = new - p, ref - p
-    tol = 1e-4 * steps * lr + steps * np.finfo(np.float32).eps * np.max(np.abs(p))
-    err = np.max(np.abs(move[big] - ref_move[big]))
-    say(f"six Adam steps: max |GPU - reference| move {err:.2e} (bound {tol:.2e})")
-    assert err <= tol
+        _, g = m.grad(U, T)
+        g = g.cpu().numpy().astype(np.float64)
+        m.train_step(U, T, lr)
+        new = m.get_params().cpu().numpy().astype(np.float64)
+        ref, mom, vel = M.adam(cur, g, mom, vel, s, lr)
+        err = np.max(np.abs(new - ref))
+        tol = 2 * np.finfo(np.float32).eps * np.max(np.abs(cur)) + 1e-5 * lr
+        assert err <= tol, (s, err, tol)
+        if s == steps:
+            say(f"step {s}: max |GPU - reference| {err:.2e} (bound {tol:.2e}), "
+                f"max |move / lr| {np.max(np.abs(new - cur)) / lr:.3f}")
+        cur = new
     m.set_params(torch.tensor(p.astype(np.float32)))
 
 
