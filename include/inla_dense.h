@@ -52,6 +52,7 @@ extern "C" {
 #define INLA_ERR_HIP (-1000)
 #define INLA_ERR_NOMEM (-1001)
 #define INLA_ERR_UNSUPPORTED (-1002)
+#define INLA_ERR_TOO_LARGE (-1003)   /* inla_logdet_noalloc: the batch needs more than its fixed scratch */
 
 /* ----------------------------------------------------- per-theta info codes */
 /* info == j > 0: the leading minor of order j of the matrix being factored is
@@ -193,6 +194,29 @@ int inla_set_stream(inla_handle *h, void *stream);
  * Returns INLA_ERR_UNSUPPORTED for an unknown precision. */
 int inla_logdet(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq, int32_t prec,
                 double *logdet, int32_t *info);
+
+/* inla_logdet for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and status codes as inla_logdet (the same kernels), but
+ * the call allocates nothing: every scratch buffer of the factorisation
+ * (padded working matrices, diagonal-block inverses, result slots and status
+ * words, BF16 panel copies) lives in one fixed device array of
+ * INLA_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is loaded and
+ * held until the process ends; descriptors go through the handle's upload
+ * ring (allocated by inla_create); launch chains run without graphs (a new
+ * graph would allocate), without lookahead and without profiling events.
+ * Needed scratch per matrix of order n (np = n rounded up to 128, e = 8 bytes
+ * for FP64, 4 for FP32 and BF16): e np^2 + 64 e np + 8 (4 np + 80) bytes, each
+ * term rounded up to 256, plus 28 bytes per matrix of status words and
+ * results, plus for BF16 2048 np bytes (512-wide panels); e.g. one FP64 matrix
+ * up to n = 2816, or seven of n = 1024.  A larger batch returns
+ * INLA_ERR_TOO_LARGE before any work is enqueued.  Every call on a GPU
+ * shares that GPU's array, which keeps the last call's contents (the status
+ * words are cleared by the call itself): calls that overlap on one GPU, from
+ * two handles or two host threads, race and must be serialised by the caller. */
+#define INLA_NOALLOC_SCRATCH_BYTES (64 << 20)
+int inla_logdet_noalloc(inla_handle *h, int32_t B, const int32_t *n, double *const *Q, const int32_t *ldq,
+                        int32_t prec, double *logdet, int32_t *info);
 
 /* Constrained Newton mode of the Gaussian approximation for B theta points
  * (algorithm "Gaussian Approximation": Q* = Q_prior + Q_l(x), b = grad + Q_l x,

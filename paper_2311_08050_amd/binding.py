@@ -23,6 +23,7 @@ INFO_OK = 0
 INFO_NEWTON_MAXIT = -1
 INFO_CONSTRAINT_RANK = -2
 INFO_NONFINITE = -3
+ERR_TOO_LARGE = -1003
 INFO_EIG_MAXIT = -4
 
 K_TRAIL, K_PANEL, K_POTF2, K_ASSEMBLE, K_SOLVE, K_BORDER = 0, 1, 2, 3, 4, 5
@@ -31,7 +32,7 @@ K_NAMES = {K_TRAIL: "trail", K_PANEL: "panel", K_POTF2: "potf2", K_ASSEMBLE: "as
 
 # Symbols declared by include/inla_dense.h
 EXPORTS = [
-    "inla_create", "inla_destroy", "inla_set_stream", "inla_logdet", "inla_constrained_mode",
+    "inla_create", "inla_destroy", "inla_set_stream", "inla_logdet", "inla_logdet_noalloc", "inla_constrained_mode",
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
@@ -126,6 +127,7 @@ def load_library(path: str = LIBPATH):
     lib.inla_destroy.argtypes = [P]
     lib.inla_set_stream.argtypes = [P, P]
     lib.inla_logdet.argtypes = [P, i32, pi32, C.POINTER(P), pi32, i32, pd, pi32]
+    lib.inla_logdet_noalloc.argtypes = [P, i32, pi32, C.POINTER(P), pi32, i32, pd, pi32]
     for f in (lib.inla_constrained_mode, lib.inla_laplace_eval, lib.inla_woodbury_eval):
         f.argtypes = [P, i32, C.POINTER(Model), pd, i32, C.POINTER(P), C.POINTER(Opts), C.POINTER(Result)]
     lib.inla_pinv.argtypes = [P, i32, pi32, C.POINTER(P), pi32, C.POINTER(P), pi32, C.c_double, pi32, pi32, pi32]
@@ -277,6 +279,20 @@ class Library:
         rc = self.lib.inla_logdet(self.h, B, n, ptrs, ld, PREC[prec], out, info)
         self._check(rc, "inla_logdet")
         return np.array(out[:]), np.array(info[:], dtype=np.int32)
+
+    def logdet_noalloc(self, mats, prec="fp64"):
+        """As logdet, through inla_logdet_noalloc (scratch in the library's fixed
+        device array, nothing allocated).  Returns (logdets, info, status code):
+        the status is returned rather than raised, so that INLA_ERR_TOO_LARGE
+        (-1003) can be seen."""
+        B = len(mats)
+        n = (C.c_int32 * B)(*[int(m.shape[0]) for m in mats])
+        ld = (C.c_int32 * B)(*[max(1, int(m.shape[0])) for m in mats])
+        ptrs = (C.c_void_p * B)(*[m.data_ptr() for m in mats])
+        out = (C.c_double * B)()
+        info = (C.c_int32 * B)()
+        rc = self.lib.inla_logdet_noalloc(self.h, B, n, ptrs, ld, PREC[prec], out, info)
+        return np.array(out[:]), np.array(info[:], dtype=np.int32), int(rc)
 
     def _common(self, dmodels, theta, x):
         B = len(dmodels)

@@ -1209,6 +1209,9 @@ int inla_create(inla_handle **h, void *stream) {
   if (!p) return INLA_ERR_NOMEM;
   p->ctx.stream = p->ctx.home = (hipStream_t)stream;
   if (hipGetDevice(&p->ctx.device) != hipSuccess) { delete p; return INLA_ERR_HIP; }
+  // the no-allocation entry point's scratch on this device (its failure is
+  // reported by that entry point, not here)
+  (void)noalloc_init_device(p->ctx.device);
   p->ctx.ring_size = (size_t)16 << 20;
   if (hipMalloc(&p->ctx.ring, p->ctx.ring_size) != hipSuccess ||
       hipHostMalloc(&p->ctx.ring_host, p->ctx.ring_size) != hipSuccess) {

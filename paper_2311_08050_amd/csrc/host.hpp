@@ -162,6 +162,9 @@ inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // The handle's context (C-ABI handles wrap one Ctx).
 Ctx *handle_ctx(inla_handle *h);
+// Takes the device address of inla_logdet_noalloc's scratch array on `device`
+// (the current device) once per device; INLA_OK or INLA_ERR_HIP.
+int noalloc_init_device(int device);
 // Block-structured pseudo-inverse priors (woodbury.hip): validation for order n
 // and theta dimension t (t < 0: unchecked), 0 or -3; and Q_prior(theta_b)^+ for B
 // points into the device arrays out[b] (n x n, ld n).
