@@ -32,11 +32,15 @@ def solve_modes(lib, dmodel, thetas, prec="fp32", batch=64):
 
 
 def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, lr=1e-3, seed=0, prec="fp32",
-          lr_final=0.01):
+          lr_final=0.01, normalise=True):
     """Solve the training points, fit the network, return (mlp, info dict).
 
     Adam with a cosine learning-rate decay from `lr` to `lr_final * lr`; the
-    training set is visited in a fresh random order every epoch (seeded)."""
+    training set is visited in a fresh random order every epoch (seeded).
+    With `normalise` the network is fitted to the modes centred on their mean
+    and divided by their standard deviation, and the two are folded into the
+    last layer afterwards (W3 <- s W3, b3 <- s b3 + mean), so that it predicts
+    modes directly."""
     import math
 
     import torch
@@ -46,6 +50,11 @@ def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, 
     t0 = time.perf_counter()
     X, iters = solve_modes(lib, dmodel, thetas, prec=prec)
     t_solve = time.perf_counter() - t0
+    mean, sd = None, 1.0
+    if normalise:
+        mean = X.mean(0)
+        sd = float((X - mean).std()) or 1.0
+        X = (X - mean) / sd
     U = torch.tensor(((np.asarray(thetas) - centre) / scale).astype(np.float32), device="cuda")
     mlp = Mlp(lib, U.shape[1], hidden, dmodel.n, seed=seed)
     N = len(thetas)
@@ -63,6 +72,17 @@ def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, 
             tot += mlp.train_step(Us[s:s + batch], Xs[s:s + batch], step_lr)
             k += 1
         losses.append(tot / per_epoch)
+    if normalise:
+        # fold the target normalisation into the output layer (flat layout
+        # W1, b1, W2, b2, W3 (O x H), b3 (O))
+        I, H, O = mlp.dims
+        p = mlp.get_params().double()
+        o_w3 = H * I + H + H * H + H
+        o_b3 = o_w3 + O * H
+        p[o_w3:o_b3] *= sd
+        p[o_b3:] = p[o_b3:] * sd + mean
+        mlp.set_params(p.float())
     t_train = time.perf_counter() - t1
     return mlp, {"solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
-                 "zero_start_iters_mean": float(np.mean(iters)), "n_train": N, "epochs": epochs}
+                 "zero_start_iters_mean": float(np.mean(iters)), "n_train": N, "epochs": epochs,
+                 "target_scale": sd}
