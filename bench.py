@@ -764,6 +764,7 @@ def main():
             r0 = r0[0]
             errs[v] = {
                 "objective_rel": abs(r0["objective"] - ref["objective"]) / abs(ref["objective"]),
+                "objective_abs": abs(r0["objective"] - ref["objective"]),
                 "logdet_qstar_rel": abs(r0["logdet_qstar"] - ref["logdet_qstar"]) / abs(ref["logdet_qstar"]),
                 "logdet_s_rel": abs(r0["logdet_s"] - ref["logdet_s"]) / abs(ref["logdet_s"]),
                 "mode_max_abs": float(np.max(np.abs(x0[0].cpu().numpy() - ref["x"]))),

@@ -74,6 +74,9 @@ struct ThetaDesc {
   double *dres;    // [16] per-theta device results (see DRES_*)
   void *linv;      // inverses of the big factor's 64 x 64 diagonal blocks (factor storage type)
   double *u;       // forward-solve output / refinement correction [n_pad]
+  double *symv;    // partial sums of Q_prior v from its lower triangle: P
+                   // ((n_pad / 64) x n_pad, block column J's part of row i at
+                   // J n_pad + i), then D [n_pad] (the transposed part)
   double *out;     // caller's output vector (mode or variances), device
   // variational-Bayes mean correction: with vb_var set, the likelihood terms
   // are expectations over eta ~ N(eta(x), vb_var[i]) by ngh-point Gauss-Hermite

@@ -288,7 +288,8 @@ Ctx::~Ctx() {
 // Per-theta workspace plan.
 struct Plan {
   ThetaDesc t{};
-  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, off_linv_small = 0, off_obs = 0, bytes = 0;
+  size_t off_Qp = 0, off_W = 0, off_S = 0, off_vec = 0, off_linv = 0, off_linv_small = 0, off_obs = 0, off_symv = 0,
+         bytes = 0;
   int ns_real = 0;
   bool needs_prior_build = false;
 };
@@ -368,6 +369,9 @@ static Plan make_plan(const inla_model &m, const double *th, Mode mode, bool aux
   t.m = aux ? 0 : m.m;
   t.A_rowptr = m.A_rowptr; t.A_col = m.A_col; t.A_val = m.A_val;
   p.off_obs = off; off += align256(sizeof(double) * 4 * (size_t)t.m);
+  // Q_prior v partial sums (residuals and objective terms of the Newton passes)
+  p.off_symv = off;
+  if (!aux && mode == MODE_LAPLACE) off += align256(sizeof(double) * (size_t)(t.n_pad / 64 + 1) * t.n_pad);
   p.bytes = off;
   return p;
 }
@@ -390,6 +394,7 @@ static void bind(Plan &p, char *base) {
   t.part = v; v += 2 * t.ldw;
   t.dres = v;
   t.linv = (void *)(base + p.off_linv);
+  t.symv = (double *)(base + p.off_symv);
   if (t.m > 0) {
     double *o = (double *)(base + p.off_obs);
     t.obs_ax = o; t.obs_g = o + t.m; t.obs_W = o + 2 * (size_t)t.m; t.obs_ll = o + 3 * (size_t)t.m;
@@ -567,7 +572,7 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
     double rb = 0, tb = 0;
     for (int i : act) {
       const ThetaDesc &t = b.plans[i].t;
-      rb += 8.0 * (double)t.n * t.n;
+      rb += 8.0 * 0.5 * (double)t.n * (t.n + 1.0);   // the lower triangle of Q_prior
       tb += esz * (double)t.n * t.n;
     }
     const int npm = max_over(b, act, &ThetaDesc::n_pad), kpm = max_over(b, act, &ThetaDesc::k_pad);
@@ -1041,7 +1046,7 @@ static int eval_chunk(Ctx &ctx, int B, const inla_model *models, const double *t
       ThetaDesc *d = upload_td(b, fin);
       if (!fin.empty() && !d) return fail(INLA_ERR_NOMEM);
       double by = 0;
-      for (int i : fin) by += 8.0 * b.plans[i].t.n * (double)b.plans[i].t.n;
+      for (int i : fin) by += 8.0 * 0.5 * b.plans[i].t.n * (b.plans[i].t.n + 1.0);
       launch_objective_terms(ctx, d, (int)fin.size(), max_over(b, fin, &ThetaDesc::n_pad), by);
       launch_finish(ctx, d, (int)fin.size(), ref_prec);
     } else if ((rc = run_pass(b, fin, PASS_FINAL, prec))) {

@@ -187,19 +187,36 @@ __global__ __launch_bounds__(256) void assemble_kernel(const ThetaDesc *__restri
   const double *q = t.Qp + (size_t)c * t.ldqp;
   const int kc_pad = round_up_dev(k, PADN);
   double xq = 0.0;
-  for (int r = c + threadIdx.x; r < N; r += 256) {
-    double v;
-    if (r < np) {
-      const double qv = q[r];
-      v = qv + (r == c ? W : 0.0);
-      if (want_xqx && r < n) xq += (r == c ? 1.0 : 2.0) * qv * t.x[r];
-    } else {
-      const int a = r - np;
-      if (a < k) v = (c < n) ? t.C[(size_t)a * n + c] : 0.0;
-      else if (border == BORDER_CB) v = (a == k) ? bc : 0.0;
-      else v = (a - kc_pad == c) ? 1.0 : 0.0;
+  // Four rows per thread and pass, their loads issued before any store (the
+  // stores to the working matrix may alias the prior for the compiler, which
+  // would otherwise keep one load in flight per thread).  Each thread still
+  // visits its rows in increasing order, so the x^T Q x partial sums keep
+  // their order.
+  constexpr int U = 4;
+  for (int rb = c + threadIdx.x; rb < N; rb += 256 * U) {
+    double qv[U], xr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + 256 * u;
+      qv[u] = r < np ? q[r] : 0.0;
+      xr[u] = (want_xqx && r < n) ? t.x[r] : 0.0;
     }
-    col[r] = (T)v;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int r = rb + 256 * u;
+      if (r >= N) break;
+      double v;
+      if (r < np) {
+        v = qv[u] + (r == c ? W : 0.0);
+        if (want_xqx && r < n) xq += (r == c ? 1.0 : 2.0) * qv[u] * xr[u];
+      } else {
+        const int a = r - np;
+        if (a < k) v = (c < n) ? t.C[(size_t)a * n + c] : 0.0;
+        else if (border == BORDER_CB) v = (a == k) ? bc : 0.0;
+        else v = (a - kc_pad == c) ? 1.0 : 0.0;
+      }
+      col[r] = (T)v;
+    }
   }
   if (want_xqx) {
     xq = block_sum256(xq, sh);
@@ -250,76 +267,102 @@ __global__ __launch_bounds__(256) void kriging_build_kernel(const ThetaDesc *__r
   }
 }
 
-// FP64 residual of the constrained Newton system at the refined iterate xn:
-//   r1 = b - (Q_prior + diag W) xn - C^T lambda,   b = g(x) + W(x) x
-// with g, W at the linearisation point x.  Q_prior is stored symmetric, so the
-// product reads whole columns.  One wave per 16 rows; the result goes to t.z.
-__global__ __launch_bounds__(256) void kkt_residual_kernel(const ThetaDesc *__restrict__ td) {
+// y = Q_prior v from the lower triangle of Q_prior alone (half the bytes of a
+// whole-column product; the consumers below finish it).  Block (J, theta) takes
+// the 64 columns [64 J, 64 J + 64) and walks the 64-row tiles at and below the
+// diagonal through LDS: row r of a tile receives sum_{c in J, c <= r} Q_rc v_c,
+// written to P[J][r]; column c receives sum_{r > c} Q_rc v_r, summed over the
+// tiles in registers and written to D[c].  Then (Q v)_i = D[i] + sum over
+// J <= i / 64 of P[J][i], in that order (no atomics: fixed summation order).
+// src 0: v = xn (refinement residuals); 1: v = x (objective terms).
+__global__ __launch_bounds__(256) void symv_lower_part_kernel(const ThetaDesc *__restrict__ td, int src) {
   const ThetaDesc t = td[blockIdx.y];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * 64 + w * 16;
-  if (i0 >= t.n_pad) return;
-  const int n = t.n, k = t.k;
-  double acc[16];
+  const int J = blockIdx.x, c0 = J * 64, np = t.n_pad, n = t.n;
+  if (c0 >= np) return;
+  const double *v = src ? t.x : t.xn;
+  __shared__ double T[64][65];
+  __shared__ double vc[64], vr[64];
+  __shared__ double red[4][64];
+  const int tid = threadIdx.x, lo = tid & 63, part = tid >> 6;
+  double *P = t.symv;
+  double *D = t.symv + (size_t)(np / 64) * np;
+  if (tid < 64) vc[tid] = c0 + tid < n ? v[c0 + tid] : 0.0;
+  const double *Qc = t.Qp + (size_t)c0 * t.ldqp;
+  double dot = 0.0;
+  for (int r0 = c0; r0 < np; r0 += 64) {
+    __syncthreads();   // the previous tile and its row sums are consumed
+    double buf[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  const double *Q0 = t.Qp + (size_t)i0 * t.ldqp;
-  for (int j = lane; j < n; j += 64) {
-    const double xj = t.xn[j];
+    for (int q = 0; q < 16; ++q) buf[q] = Qc[(size_t)(part + 4 * q) * t.ldqp + r0 + lo];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] += Q0[(size_t)q * t.ldqp + j] * xj;
-  }
-  for (int q = 0; q < 16; ++q) {
-    const int i = i0 + q;
-    double ct = 0.0;
-    if (i < n)
-      for (int a = lane; a < k; a += 64) ct += t.C[(size_t)a * n + i] * t.lam[a];
-    const double s = wave_sum(acc[q] + ct);
-    if (lane == 0) {
-      double r = 0.0;
-      if (i < n) {
-        double g, W, ll;
-        lik_point(t, i, t.x[i], g, W, ll);
-        r = (g + W * t.x[i]) - W * t.xn[i] - s;
-      }
-      t.z[i] = r;
+    for (int q = 0; q < 16; ++q) T[lo][part + 4 * q] = buf[q];
+    if (tid < 64) vr[tid] = r0 + tid < n ? v[r0 + tid] : 0.0;
+    __syncthreads();
+    const bool diag = r0 == c0;
+    double rs = 0.0;   // row lo, columns 16 part .. 16 part + 15
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int c = 16 * part + q;
+      if (!diag || c <= lo) rs += T[lo][c] * vc[c];
     }
+    red[part][lo] = rs;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {   // column lo, rows 16 part .. 16 part + 15
+      const int r = 16 * part + q;
+      if (!diag || r > lo) dot += T[r][lo] * vr[r];
+    }
+    __syncthreads();
+    if (tid < 64) P[(size_t)J * np + r0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
   }
+  __syncthreads();
+  red[part][lo] = dot;
+  __syncthreads();
+  if (tid < 64) D[c0 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
 }
 
-// Objective terms at the mode without re-assembling: x^T Q_prior x (symmetric
-// Q_prior, whole-column products) and log pi(y | eta) into the per-column partial
-// sums read by the finish kernel.  Used when the last Newton factorisation is
-// reused for log|Q*|.
+// (Q_prior v)_i from the partial sums of symv_lower_part_kernel.
+__device__ __forceinline__ double symv_row(const ThetaDesc &t, int i) {
+  const int np = t.n_pad;
+  double y = t.symv[(size_t)(np / 64) * np + i];
+  for (int J = 0; J <= i / 64; ++J) y += t.symv[(size_t)J * np + i];
+  return y;
+}
+
+// FP64 residual of the constrained Newton system at the refined iterate xn:
+//   r1 = b - (Q_prior + diag W) xn - C^T lambda,   b = g(x) + W(x) x
+// with g, W at the linearisation point x and Q_prior xn from the lower-triangle
+// partial sums; one thread per row, the result to t.z.
+__global__ __launch_bounds__(256) void kkt_residual_kernel(const ThetaDesc *__restrict__ td) {
+  const ThetaDesc t = td[blockIdx.y];
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.n_pad) return;
+  double r = 0.0;
+  if (i < t.n) {
+    double s = symv_row(t, i);
+    for (int a = 0; a < t.k; ++a) s += t.C[(size_t)a * t.n + i] * t.lam[a];
+    double g, W, ll;
+    lik_point(t, i, t.x[i], g, W, ll);
+    r = (g + W * t.x[i]) - W * t.xn[i] - s;
+  }
+  t.z[i] = r;
+}
+
+// Objective terms at the mode without re-assembling: x^T Q_prior x (from the
+// lower-triangle partial sums of Q_prior x) and log pi(y | eta) into the
+// per-column partial sums read by the finish kernel.  Used when the last Newton
+// factorisation is reused for log|Q*|.
 __global__ __launch_bounds__(256) void objective_terms_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i0 = blockIdx.x * 64 + w * 16;
-  if (i0 >= t.n_pad) return;
-  const int n = t.n;
-  double acc[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  const double *Q0 = t.Qp + (size_t)i0 * t.ldqp;
-  for (int j = lane; j < n; j += 64) {
-    const double xj = t.x[j];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] += Q0[(size_t)q * t.ldqp + j] * xj;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= t.n_pad) return;
+  double ll = 0.0, xq = 0.0;
+  if (i < t.n) {
+    double g, W;
+    lik_point(t, i, t.x[i], g, W, ll);
+    xq = t.x[i] * symv_row(t, i);
   }
-  for (int q = 0; q < 16; ++q) {
-    const int i = i0 + q;
-    const double s = wave_sum(acc[q]);
-    if (lane == 0) {
-      double ll = 0.0, xq = 0.0;
-      if (i < n) {
-        double g, W;
-        lik_point(t, i, t.x[i], g, W, ll);
-        xq = t.x[i] * s;
-      }
-      t.part[i] = ll;
-      t.part[t.ldw + i] = xq;
-    }
-  }
+  t.part[i] = ll;
+  t.part[t.ldw + i] = xq;
 }
 
 // r2 = e - C xn, one wave per constraint row (zero on padded rows).
@@ -376,13 +419,19 @@ void launch_kriging_build(Ctx &ctx, const ThetaDesc *dtd, int B, int kp_max, int
 void launch_objective_terms(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, double bytes) {
   if (B <= 0 || np_max <= 0) return;
   ctx.launch(INLA_K_ASSEMBLE, 0.0, bytes, [&] {
-    hipLaunchKernelGGL(objective_terms_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd);
+    hipLaunchKernelGGL(symv_lower_part_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd, 1);
+  });
+  ctx.launch(INLA_K_ASSEMBLE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(objective_terms_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dtd);
   });
 }
 void launch_kkt_residual(Ctx &ctx, const ThetaDesc *dtd, int B, int np_max, int kp_max, double bytes) {
   if (B <= 0 || np_max <= 0) return;
   ctx.launch(INLA_K_SOLVE, 0.0, bytes, [&] {
-    hipLaunchKernelGGL(kkt_residual_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd);
+    hipLaunchKernelGGL(symv_lower_part_kernel, dim3(np_max / 64, B), dim3(256), 0, ctx.stream, dtd, 0);
+  });
+  ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {
+    hipLaunchKernelGGL(kkt_residual_kernel, dim3((np_max + 255) / 256, B), dim3(256), 0, ctx.stream, dtd);
   });
   if (kp_max > 0)
     ctx.launch(INLA_K_SOLVE, 0.0, 0.0, [&] {

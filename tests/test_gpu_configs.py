@@ -24,6 +24,13 @@ from paper_2311_08050_amd import synth
 pytestmark = pytest.mark.gpu
 RTOL = 1e-9
 LOGDET_RTOL = 2e-6   # mixed precision (FP32 factor) bound on log-determinants and the objective
+# Absolute bound on the mixed-precision objective, per latent element: the FP32
+# factor's n pivots each carry a relative error of order kappa(Q*) u_32, whose
+# sum enters log|Q*|; measured about 1.6e-7 n at n = 8192 and 0.9e-7 n at
+# n = 16384 (relative to the oracle), stated here with margin.  Objective
+# differences over finite-difference steps h need |error| << h |d objective /
+# d theta|, so a gradient step of h = 1e-3 wants the FP64 path.
+OBJ_ABS_PER_N = 3e-7
 
 
 def say(msg):
@@ -78,6 +85,7 @@ def check_mixed_vs_golden(r, x, g, what):
     assert rel(r["logdet_qstar"], g["logdet_qstar"]) <= LOGDET_RTOL
     assert rel(r["logdet_s"], g["logdet_s"]) <= 1e-5
     assert rel(r["objective"], g["objective"]) <= LOGDET_RTOL
+    assert d_obj <= OBJ_ABS_PER_N * g["n"], (what, d_obj)
 
 
 @pytest.mark.timeout(600)
@@ -258,7 +266,8 @@ def test_headline_configuration_n8192(lib):
     (a small network trained here on 256 solved modes), the untuned default
     configuration.  All 64 theta: status, iterations, the Kronecker closed form
     of log|Q_prior|, C x* = e, and agreement with the FP64 path (mode 1e-9,
-    log|Q*| and objective 2e-6); theta 0 also against the oracle."""
+    log|Q*| and objective 2e-6 relative and 3e-7 n absolute); theta 0 also
+    against the oracle's stored values."""
     from paper_2311_08050_amd import warmstart
     from paper_2311_08050_amd.binding import DeviceModel
     model, thetas = synth.headline(B=64)
@@ -290,9 +299,11 @@ def test_headline_configuration_n8192(lib):
         assert np.max(np.abs(C @ xa)) <= 1e-10 * max(1.0, np.max(np.abs(xa)))
         assert rel(a["logdet_qstar"], f["logdet_qstar"]) <= LOGDET_RTOL
         assert rel(a["objective"], f["objective"]) <= LOGDET_RTOL
-    say("headline: oracle on theta 0 (about a minute on the host)")
-    ref = O.laplace_eval(model, thetas[0])
-    assert ref["info"] == 0
-    assert np.max(np.abs(x64[0].cpu().numpy() - ref["x"])) <= RTOL * max(1.0, np.max(np.abs(ref["x"])))
-    assert rel(r64[0]["objective"], ref["objective"]) <= RTOL
-    assert rel(r32[0]["objective"], ref["objective"]) <= LOGDET_RTOL
+        assert abs(a["objective"] - f["objective"]) <= OBJ_ABS_PER_N * model["n"]
+    say("headline: theta 0 against the oracle's stored values")
+    g = golden("kron8192_theta0.json")
+    assert np.array_equal(np.array(g["theta"]), thetas[0])
+    idx = np.array(g["index"])
+    assert np.max(np.abs(x64[0].cpu().numpy()[idx] - np.array(g["x"]))) <= RTOL * max(1.0, g["x_absmax"])
+    assert rel(r64[0]["objective"], g["objective"]) <= RTOL
+    check_mixed_vs_golden(r32[0], x32[0].cpu().numpy(), g, "fp32 from the warm start")
