@@ -45,8 +45,9 @@ __global__ __launch_bounds__(256) void expcov_bordered_kernel(const ThetaDesc *_
 //   KRON:   Q[t1 n_s + s1, t2 n_s + s2] = tau (R_t[t1,t2] Sigma_s^{-1}[s1,s2] + delta [i == j]),
 //           R_t the unscaled first-order random walk (tridiagonal 1,2,..,2,1 / -1);
 //   DENSE:  copy of the caller's matrix (its lower triangle).
-// Both triangles are written (the FP64 residual reads whole columns); identity
-// on padded diagonal entries; one workgroup per column.
+// Only the lower triangle (rows r >= c of column c) is written: the assembly
+// and the lower-triangle products read no more.  Identity on padded diagonal
+// entries; one workgroup per column.
 __global__ __launch_bounds__(256) void prior_assemble_kernel(const ThetaDesc *__restrict__ td) {
   const ThetaDesc t = td[blockIdx.y];
   const int c = blockIdx.x;
@@ -54,25 +55,19 @@ __global__ __launch_bounds__(256) void prior_assemble_kernel(const ThetaDesc *__
   double *col = t.Qp + (size_t)c * t.ldqp;
   const int n = t.n;
   if (c >= n) {
-    for (int r = threadIdx.x; r < t.n_pad; r += 256) col[r] = (r == c) ? 1.0 : 0.0;
+    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = (r == c) ? 1.0 : 0.0;
     return;
   }
   if (t.prior == PRIOR_DENSE) {
-    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
-      const int a = r > c ? r : c, b = r > c ? c : r;
-      col[r] = r < n ? t.Quser[(size_t)b * t.ldquser + a] : 0.0;
-    }
+    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = r < n ? t.Quser[(size_t)c * t.ldquser + r] : 0.0;
   } else if (t.prior == PRIOR_EXPCOV) {
     const double *Sn = t.P + (size_t)t.ns_pad * t.ldp + t.ns_pad;  // -Sigma^{-1}, lower
-    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
-      const int a = r > c ? r : c, b = r > c ? c : r;
-      col[r] = r < n ? -t.tau * Sn[(size_t)b * t.ldp + a] : 0.0;
-    }
+    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) col[r] = r < n ? -t.tau * Sn[(size_t)c * t.ldp + r] : 0.0;
   } else {
     const int ns = t.n_s, nt = t.n_t;
     const int t2 = c / ns, s2 = c % ns;
     const double *Sn = t.P + (size_t)t.ns_pad * t.ldp + t.ns_pad;  // -Sigma_s^{-1}, lower
-    for (int r = threadIdx.x; r < t.n_pad; r += 256) {
+    for (int r = c + threadIdx.x; r < t.n_pad; r += 256) {
       double v = 0.0;
       if (r < n) {
         const int t1 = r / ns, s1 = r % ns;
