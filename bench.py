@@ -51,12 +51,15 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profile(kernel_source, summary_md, kernel_instance):
+def traffic_from_profile(kernel_source, summary_md, kernel_instance, alg_bytes_per_launch=None):
     """HBM bytes per launch of the trailing-update kernel from the committed
-    counter summary (its `kernel_instance:`, `kernel_source_sha256:` and
-    `traffic_bytes_per_launch:` lines), or None if the summary is missing, was
-    taken on a different kernel source or on another instance (tile size) than
-    the one this run timed."""
+    counter summary (its `kernel_instance:`, `kernel_source_sha256:`,
+    `traffic_bytes_per_launch:` and, if present, `traffic_alg_ratio:` lines),
+    or None if the summary is missing, was taken on a different kernel source
+    or on another instance (tile size) than the one this run timed.  With a
+    ratio and this run's algorithmic bytes per launch the figure is their
+    product (the counters may come from another launch mix of the same
+    kernel), else the summary's bytes per launch."""
     import hashlib
     try:
         with open(summary_md) as f:
@@ -74,6 +77,8 @@ def traffic_from_profile(kernel_source, summary_md, kernel_instance):
     if fields.get("kernel_source_sha256") != digest or fields.get("kernel_instance") != kernel_instance:
         return None
     try:
+        if alg_bytes_per_launch and "traffic_alg_ratio" in fields:
+            return float(fields["traffic_alg_ratio"]) * float(alg_bytes_per_launch)
         return float(fields["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
@@ -704,11 +709,16 @@ def main():
     head = variants[-1]
     hv = results[head]
     for v in variants:
-        pv = results[v]["roofline"]["precision"]
-        results[v]["roofline"]["traffic"] = traffic_from_profile(
-            os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"),
-            os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64.md"),
-            results[v]["roofline"]["kernel"].split(" ")[0])
+        roof = results[v]["roofline"]
+        pv = roof["precision"]
+        summary = os.path.join(ROOT, "profiles", f"trail_update_{pv}_n8192_b64.md")
+        roof["traffic"] = traffic_from_profile(
+            os.path.join(ROOT, "paper_2311_08050_amd", "csrc", "k_factor.hip"), summary,
+            roof["kernel"].split(" ")[0], roof["alg_bytes_per_launch"])
+        if roof["traffic"] is not None:
+            roof["traffic_basis"] = (f"HBM bytes per launch = this run's algorithmic bytes per launch x the ratio of "
+                                     f"FETCH_SIZE + WRITE_SIZE (copy-calibrated) to algorithmic bytes in "
+                                     f"profiles/{os.path.basename(summary)}")
     out = {
         "metric": METRIC,
         "value": hv["value"],

@@ -33,6 +33,19 @@ def test_traffic_read_when_source_and_instance_match(tmp_path, source):
     assert bench.traffic_from_profile(str(src), str(md), KERNEL) == 1.5e10
 
 
+def test_traffic_from_ratio_scales_this_runs_algorithmic_bytes(tmp_path, source):
+    src, sha = source
+    md = tmp_path / "summary.md"
+    _summary(md, sha)
+    with open(md, "a") as f:
+        f.write("- traffic_alg_ratio: 1.25\n")
+    assert bench.traffic_from_profile(str(src), str(md), KERNEL, 4.0e9) == 5.0e9
+    # without this run's algorithmic bytes the summary's own figure is used
+    assert bench.traffic_from_profile(str(src), str(md), KERNEL) == 1.5e10
+    src.write_text("// kernel source, edited\n")
+    assert bench.traffic_from_profile(str(src), str(md), KERNEL, 4.0e9) is None
+
+
 def test_traffic_null_after_a_source_change(tmp_path, source):
     src, sha = source
     md = tmp_path / "summary.md"
