@@ -3,9 +3,11 @@
 Workload: the n = 8192 Poisson space x time interaction model (128 regions x 64
 times, Q_prior = tau (R_t kron Sigma_s(rho)^{-1} + delta I), k = 191 independent
 sum-to-zero constraints), a batch of 64 theta ~ N(theta0, 0.5^2 I).  One step =
-one inla_laplace_eval over the batch (prior build, prior pass, Newton iterations
-with kriging, final pass at the mode, objective).  Inputs are synthetic
-(seeded) and resident in HBM before the timed region.
+one inla_laplace_eval over the batch (prior build, FP64 prior pass, Newton
+iterations with kriging, final pass at the mode, objective; the prior pass runs
+beside the Newton iterations on a second stream of the handle unless
+--no-overlap).  Inputs are synthetic (seeded) and resident in HBM before the
+timed region.
 
 Variants (each timed separately, same batch):
   fp64        FP64 everywhere, Newton from x = 0
@@ -619,8 +621,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="factor with the default panel width and tile instead of tuning them first")
     ap.add_argument("--no-graphs", action="store_true", help="launch every kernel directly (no hipGraph replays)")
-    ap.add_argument("--overlap", action="store_true",
-                    help="run each evaluation's prior pass beside the Newton iteration on a second stream")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run each evaluation's FP64 prior pass in order instead of beside the Newton iteration "
+                         "(inla_set_overlap; on by default here: +3.5%% at the headline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the separately timed marginal-variance, VB-correction and Stage-1 figures")
     ap.add_argument("--rocprof-window", metavar="CSV",
@@ -672,8 +675,7 @@ def main():
     variants = [v.strip() for v in args.variants.split(",") if v.strip()]
     if args.no_graphs:
         lib.set_graphs(False)
-    if args.overlap:
-        lib.set_overlap(True)
+    lib.set_overlap(not args.no_overlap)
     tuning = {}
     if not args.no_autotune:
         # one-time setup, not timed: the tuner factors synthetic batches of the
@@ -742,7 +744,7 @@ def main():
         "variants": results,
         "autotune": tuning or None,
         "graphs": not args.no_graphs,
-        "overlap": args.overlap,
+        "overlap": not args.no_overlap,
     }
     if train_info is not None:
         out["warm_start_training"] = dict(train_info, **MLP_TRAIN)

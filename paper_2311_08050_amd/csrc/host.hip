@@ -15,27 +15,36 @@ namespace inla {
 // ------------------------------------------------------------------ Ctx
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// The optional streams (side: lookahead; aux: concurrent prior pass) are
+// created on first use.  A failure leaves the feature off for the call and
+// clears the runtime's error state, so that it is not reported by a later check.
 int Ctx::side_ready() {
-  if (side) return INLA_OK;
-  if (hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+  if (side && ev_a && ev_b) return INLA_OK;
+  if (!side && hipStreamCreateWithFlags(&side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
     side = nullptr;
     return INLA_ERR_HIP;
   }
-  if (hipEventCreateWithFlags(&ev_a, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ev_b, hipEventDisableTiming) != hipSuccess)
+  if ((!ev_a && hipEventCreateWithFlags(&ev_a, hipEventDisableTiming) != hipSuccess) ||
+      (!ev_b && hipEventCreateWithFlags(&ev_b, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipGetLastError();
     return INLA_ERR_HIP;
+  }
   return INLA_OK;
 }
 
 int Ctx::aux_ready() {
-  if (aux) return INLA_OK;
-  if (hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+  if (aux && ev_c && ev_d) return INLA_OK;
+  if (!aux && hipStreamCreateWithFlags(&aux, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
     aux = nullptr;
     return INLA_ERR_HIP;
   }
-  if (hipEventCreateWithFlags(&ev_c, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&ev_d, hipEventDisableTiming) != hipSuccess)
+  if ((!ev_c && hipEventCreateWithFlags(&ev_c, hipEventDisableTiming) != hipSuccess) ||
+      (!ev_d && hipEventCreateWithFlags(&ev_d, hipEventDisableTiming) != hipSuccess)) {
+    (void)hipGetLastError();
     return INLA_ERR_HIP;
+  }
   return INLA_OK;
 }
 
