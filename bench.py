@@ -46,7 +46,7 @@ def trail_kernel_name(precision, tile):
     if precision == "bf16":
         return "trail_bf16_kernel<128,128>"
     return f"trail_update_kernel<{TYPE_NAME[precision]},{tile},{tile}>"
-MLP_TRAIN = {"n_train": 2048, "epochs": 1600, "hidden": 256, "lr": 2e-3, "lr_final": 0.01, "seed": 91}
+MLP_TRAIN = {"n_train": 2048, "epochs": 3200, "hidden": 256, "lr": 2e-3, "lr_final": 0.01, "seed": 91}
 
 
 def log(msg):

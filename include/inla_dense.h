@@ -280,7 +280,9 @@ int inla_mlp_forward(inla_mlp *m, int32_t B, const float *x, float *y);
  * NULL); *loss (host) receives the loss if loss is not NULL. */
 int inla_mlp_grad(inla_mlp *m, int32_t B, const float *x, const double *target, float *grad, double *loss);
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on the
- * mean-squared-error loss of a batch; *loss (host) receives the loss before the step. */
+ * mean-squared-error loss of a batch; *loss (host) receives the loss before the
+ * step.  With loss NULL the call only enqueues the step on the handle's stream
+ * and returns without waiting for the device. */
 int inla_mlp_train_step(inla_mlp *m, int32_t B, const float *x, const double *target, float lr, double *loss);
 /* Warm starts for inla_laplace_eval: theta (host, B x ldtheta, ldtheta <= 8)
  * normalised with centre[I], scale[I] (host), predicted modes written as FP64

@@ -618,12 +618,14 @@ class Mlp:
                                               C.byref(loss)), "inla_mlp_grad")
         return loss.value, g
 
-    def train_step(self, x, target, lr=1e-3):
-        """x: float32 (B x I) device tensor, target: float64 (B x O) device tensor."""
+    def train_step(self, x, target, lr=1e-3, want_loss=True):
+        """x: float32 (B x I) device tensor, target: float64 (B x O) device tensor.
+        Returns the batch loss before the step, or None with want_loss=False
+        (then the call does not wait for the device)."""
         loss = C.c_double()
         Library._check(self.lib.inla_mlp_train_step(self.m, x.shape[0], x.data_ptr(), target.data_ptr(), lr,
-                                                    C.byref(loss)), "inla_mlp_train_step")
-        return loss.value
+                                                    C.byref(loss) if want_loss else None), "inla_mlp_train_step")
+        return loss.value if want_loss else None
 
     def predict_modes(self, theta, centre, scale, x=None):
         theta = np.ascontiguousarray(np.atleast_2d(np.asarray(theta, dtype=np.float64)))

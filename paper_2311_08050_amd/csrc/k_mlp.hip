@@ -134,12 +134,20 @@ __global__ void gelu_back_kernel(float *dY, const float *Z, int count) {
 }
 
 // Column sums of a (rows x cols) row-major matrix into out[cols] (bias
-// gradients), fixed order.
+// gradients), rows added in increasing order; eight rows' loads are issued
+// ahead of their additions.
 __global__ void colsum_kernel(const float *X, int rows, int cols, float *out) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= cols) return;
   float s = 0.0f;
-  for (int r = 0; r < rows; ++r) s += X[(size_t)r * cols + j];
+  for (int r0 = 0; r0 < rows; r0 += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = r0 + u < rows ? X[(size_t)(r0 + u) * cols + j] : 0.0f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (r0 + u < rows) s += v[u];
+  }
   out[j] = s;
 }
 

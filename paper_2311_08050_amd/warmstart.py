@@ -66,12 +66,12 @@ def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, 
     for ep in range(epochs):
         perm = torch.as_tensor(rng.permutation(N), device="cuda")
         Us, Xs = U.index_select(0, perm), X.index_select(0, perm)
-        tot = 0.0
+        last = N - batch   # the epoch's last batch reports its loss; the others do not wait for the device
         for s in range(0, N - batch + 1, batch):
             step_lr = lr * (lr_final + (1.0 - lr_final) * 0.5 * (1.0 + math.cos(math.pi * k / total)))
-            tot += mlp.train_step(Us[s:s + batch], Xs[s:s + batch], step_lr)
+            loss = mlp.train_step(Us[s:s + batch], Xs[s:s + batch], step_lr, want_loss=(s + batch > last))
             k += 1
-        losses.append(tot / per_epoch)
+        losses.append(loss)
     if normalise:
         # fold the target normalisation into the output layer (flat layout
         # W1, b1, W2, b2, W3 (O x H), b3 (O))
@@ -83,6 +83,7 @@ def train(lib, dmodel, thetas, centre, scale, hidden=256, epochs=200, batch=64, 
         p[o_b3:] = p[o_b3:] * sd + mean
         mlp.set_params(p.float())
     t_train = time.perf_counter() - t1
+    # losses: the last batch's mean squared error (before its step) in the first and last epoch
     return mlp, {"solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
                  "zero_start_iters_mean": float(np.mean(iters)), "n_train": N, "epochs": epochs,
                  "target_scale": sd}
