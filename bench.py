@@ -710,6 +710,17 @@ def main():
         results[v] = run_variant(lib, binding, dms, thetas, xs, v, args.steps, args.warmup, warm)
     head = variants[-1]
     hv = results[head]
+    in_order = None
+    if not args.no_overlap:
+        # the headline variant once more with the prior pass in order: the
+        # trailing kernel's own rate, which the concurrent prior pass stretches
+        lib.set_overlap(False)
+        w = max(3, args.steps // 4)
+        r = run_variant(lib, binding, dms, thetas, xs, head, w, 1, warm)
+        lib.set_overlap(True)
+        in_order = {"value": r["value"], "ms_per_step": r["ms_per_step"], "steps": w,
+                    "roofline": {k: r["roofline"][k] for k in ("achieved", "peak", "unit", "frac", "launches",
+                                                               "avg_launch_ms")}}
     for v in variants:
         roof = results[v]["roofline"]
         pv = roof["precision"]
@@ -741,6 +752,7 @@ def main():
             "n": n, "k": k, "batch": args.batch, "variant": head,
         },
         "roofline": hv["roofline"],
+        "headline_prior_pass_in_order": in_order,
         "variants": results,
         "autotune": tuning or None,
         "graphs": not args.no_graphs,
