@@ -46,7 +46,7 @@ def trail_kernel_name(precision, tile):
     if precision == "bf16":
         return "trail_bf16_kernel<128,128>"
     return f"trail_update_kernel<{TYPE_NAME[precision]},{tile},{tile}>"
-MLP_TRAIN = {"n_train": 2048, "epochs": 3200, "hidden": 256, "lr": 2e-3, "lr_final": 0.01, "seed": 91}
+MLP_TRAIN = {"n_train": 2048, "epochs": 6400, "batch": 256, "hidden": 256, "lr": 4e-3, "lr_final": 0.01, "seed": 91}
 
 
 def log(msg):
@@ -700,8 +700,9 @@ def main():
                 train = synth.normal_batch(centre, MLP_TRAIN["n_train"], 0.5, seed=MLP_TRAIN["seed"])
                 log(f"training the warm start on {len(train)} theta (fp32 solves)")
                 trained["net"] = warmstart.train(lib, dm, train, centre, scale, hidden=MLP_TRAIN["hidden"],
-                                                 epochs=MLP_TRAIN["epochs"], lr=MLP_TRAIN["lr"], prec="fp32",
-                                                 seed=MLP_TRAIN["seed"], lr_final=MLP_TRAIN["lr_final"])
+                                                 epochs=MLP_TRAIN["epochs"], batch=MLP_TRAIN["batch"],
+                                                 lr=MLP_TRAIN["lr"], prec="fp32", seed=MLP_TRAIN["seed"],
+                                                 lr_final=MLP_TRAIN["lr_final"])
                 log(f"warm start trained: {trained['net'][1]}")
             mlp, train_info = trained["net"]
             # a warm start that needs more iterations than the zero-start median is
