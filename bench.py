@@ -720,6 +720,7 @@ def main():
         r = run_variant(lib, binding, dms, thetas, xs, head, w, 1, warm)
         lib.set_overlap(True)
         in_order = {"value": r["value"], "ms_per_step": r["ms_per_step"], "steps": w,
+                    "newton_iters": r["newton_iters"], "kernel_time_ms": r["kernel_time_ms"],
                     "roofline": {k: r["roofline"][k] for k in ("achieved", "peak", "unit", "frac", "launches",
                                                                "avg_launch_ms")}}
     for v in variants:
