@@ -1,4 +1,4 @@
-// Bordered, batched, right-looking blocked Cholesky for gfx950.
+// Bordered, batched, blocked Cholesky for gfx950.
 //
 // Dense Cholesky is the step the paper names as the bottleneck of every
 // hyperparameter evaluation (section "Implementation of INLA+: OpenMP and MPI
@@ -12,12 +12,17 @@
 // right-hand side b, so C Q^{-1} C^T, C Q^{-1} b and L^{-1} b fall out of the
 // factorisation's own MFMA updates.
 //
-// Steps per inner block j (width NBI = 64) of an outer panel [p0, p0 + nb):
-//   potf2_inv  : L_jj = chol(A_jj) and X = L_jj^{-1} in FP64 in LDS (one workgroup per theta)
-//   TRSM       : A[j+64:, j:j+64] <- A[j+64:, j:j+64] X^T     (MFMA, in place)
-//   PANEL      : A[j+64:, j+64:pend] -= A[j+64:, j:j+64] A[j+64:pend, j:j+64]^T
-// and per outer panel
+// Per outer panel [p0, pend = p0 + nb), left-looking inside the panel and
+// right-looking across panels:
+//   potf2_inv  : L_pp = chol(A_pp) and X = L_pp^{-1} in FP64 in LDS for the first
+//                diagonal block (one workgroup per theta)
+//   panel step : per 64-wide block column j, per 64-row tile I below it
+//                L[I,j] = (A[I,j] - L[I,p0:j] L[j,p0:j]^T) X_j^T, the SYRK of the
+//                in-panel diagonal block A[I,I], and chol / inverse of the next
+//                diagonal block by the tile just below (MFMA, one launch per j)
 //   TRAIL      : A[pend:, pend:ncols] -= A[pend:, p0:pend] A[pend:ncols, p0:pend]^T
+// Blocked right-looking Cholesky is the textbook form; the left-looking panel
+// and the fused diagonal factorisation are this implementation's choice.
 //
 // Storage and MFMA precision are template parameters: FP64 storage with
 // v_mfma_f64_16x16x4f64, or FP32 storage with v_mfma_f32_16x16x4f32 (FP32
@@ -33,7 +38,7 @@ namespace inla {
 // TRAIL updates everything right of the panel; with lookahead it is split into
 // TRAIL_A (the next panel's columns) and TRAIL_B (the columns after it), so
 // that the next panel can be factored while TRAIL_B runs.
-enum { KIND_TRSM = 0, KIND_PANEL = 1, KIND_TRAIL = 2, KIND_TRAIL_A = 3, KIND_TRAIL_B = 4 };
+enum { KIND_TRAIL = 0, KIND_TRAIL_A = 1, KIND_TRAIL_B = 2 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
@@ -43,53 +48,58 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // so the same sub-panel steps that produce L_jj turn the border into
 // I L_jj^{-T} = L_jj^{-T}, whose transpose is the inverse used by the MFMA TRSM.
 // Sub-panels of width 16: an unblocked 16 x 16 Cholesky held in registers of
-// wave 0 (lane r owns row r), a forward-substitution TRSM of the rows below
-// (one thread per row), and the rank-16 update of the rest (row in registers,
-// column values broadcast from LDS).  12 barriers in all.
+// wave 0 (lane r owns row r, pivots and columns broadcast with readlane), a
+// forward-substitution TRSM of the rows below (one thread per row, reciprocal
+// pivots), and the rank-16 update of the rest (row in registers, column values
+// broadcast from LDS).  12 barriers in all.
 // --------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__restrict__ descs, int j) {
-  const FactorDesc d = descs[blockIdx.x];
-  if (j >= d.nf) return;
+struct Potf2Lds {
+  double M[2 * NBI][NBI + 1];
+  double rd[NBI];   // reciprocal pivots 1 / L_cc
+  int fail;
+};
+
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __hiloint2double(hi, lo);
+}
+
+// S.M rows [0, 64) hold the block's lower triangle (zero above), rows [64, 128)
+// the identity, S.fail = 0; all of it visible to the block.  On return S.M
+// holds L_jj below and L_jj^{-T} in the border, S.fail the first failing pivot
+// (1-based) or 0.
+__device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
   constexpr int W = 16, M2 = 2 * NBI;
-  __shared__ double M[M2][NBI + 1];
-  __shared__ int fail;
-  const int tid = threadIdx.x;
-  __attribute__((address_space(1))) T *Ad = gptr((T *)d.A) + (size_t)j * d.ld + j;
-  for (int e = tid; e < NBI * NBI; e += 256) {
-    const int r = e & (NBI - 1), c = e >> 6;
-    M[r][c] = (r >= c) ? (double)Ad[(size_t)c * d.ld + r] : 0.0;
-    M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
-  }
-  if (tid == 0) fail = 0;
-  __syncthreads();
   for (int jb = 0; jb < NBI; jb += W) {
     // 1. 16 x 16 diagonal Cholesky in wave 0
     if (tid < 64) {
       const int r = tid & (W - 1);
       double a[W];
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) a[cc] = M[jb + r][jb + cc];
+      for (int cc = 0; cc < W; ++cc) a[cc] = S.M[jb + r][jb + cc];
       int bad = 0;
 #pragma unroll
       for (int c = 0; c < W; ++c) {
-        double dcc = __shfl(a[c], c, 64);
+        double dcc = lane_bcast(a[c], c);
         if (!(dcc > 0.0)) {
           if (bad == 0) bad = jb + c + 1;
           dcc = __builtin_nan("");
         }
-        const double sd = sqrt(dcc);
-        const double l = (r == c) ? sd : a[c] / sd;
+        const double sd = sqrt(dcc), rs = 1.0 / sd;
+        const double l = (r == c) ? sd : a[c] * rs;
         a[c] = l;
+        if (tid == 0) S.rd[jb + c] = rs;
 #pragma unroll
-        for (int cc = c + 1; cc < W; ++cc) a[cc] -= l * __shfl(l, cc, 64);
+        for (int cc = c + 1; cc < W; ++cc) a[cc] -= l * lane_bcast(l, cc);
       }
       if (tid < W) {
 #pragma unroll
         for (int cc = 0; cc < W; ++cc)
-          if (cc <= r) M[jb + r][jb + cc] = a[cc];
+          if (cc <= r) S.M[jb + r][jb + cc] = a[cc];
       }
-      if (tid == 0 && bad != 0 && fail == 0) fail = bad;
+      if (tid == 0 && bad != 0 && S.fail == 0) S.fail = bad;
     }
     __syncthreads();
     // 2. TRSM of every row below the sub-panel (block rows and border rows)
@@ -98,16 +108,16 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
       const int r = jb + W + tid;
       double x[W];
 #pragma unroll
-      for (int c = 0; c < W; ++c) x[c] = M[r][jb + c];
+      for (int c = 0; c < W; ++c) x[c] = S.M[r][jb + c];
 #pragma unroll
       for (int c = 0; c < W; ++c) {
         double s = x[c];
 #pragma unroll
-        for (int m = 0; m < c; ++m) s -= x[m] * M[jb + c][jb + m];
-        x[c] = s / M[jb + c][jb + c];
+        for (int m = 0; m < c; ++m) s -= x[m] * S.M[jb + c][jb + m];
+        x[c] = s * S.rd[jb + c];
       }
 #pragma unroll
-      for (int c = 0; c < W; ++c) M[r][jb + c] = x[c];
+      for (int c = 0; c < W; ++c) S.M[r][jb + c] = x[c];
     }
     __syncthreads();
     // 3. rank-16 update of columns [jb + 16, 64) for the rows below
@@ -119,39 +129,64 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
         const int r = jb + W + rr;
         double p[W];
 #pragma unroll
-        for (int m = 0; m < W; ++m) p[m] = M[r][jb + m];
+        for (int m = 0; m < W; ++m) p[m] = S.M[r][jb + m];
         const int per = (Cn + nsplit - 1) / nsplit;
         const int cb = jb + W + part * per;
         const int ce = min(cb + per, NBI);
         for (int c = cb; c < ce; ++c) {
           if (r < NBI && c > r) break;
-          double s = M[r][c];
+          double s = S.M[r][c];
 #pragma unroll
-          for (int m = 0; m < W; ++m) s -= p[m] * M[c][jb + m];
-          M[r][c] = s;
+          for (int m = 0; m < W; ++m) s -= p[m] * S.M[c][jb + m];
+          S.M[r][c] = s;
         }
       }
     }
     __syncthreads();
   }
-  // every diagonal block keeps its inverse (the triangular solves reuse them)
-  __attribute__((address_space(1))) T *Li = gptr((T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
-  for (int e = tid; e < NBI * NBI; e += 256) {
-    const int r = e & (NBI - 1), c = e >> 6;
-    if (r >= c) Ad[(size_t)c * d.ld + r] = (T)M[r][c];
-    Li[c * NBI + r] = (T)M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
-  }
-  if (tid == 0 && fail != 0 && *d.info == 0) *d.info = j + fail;
 }
 
-// Tile bx of one update launch: rows/columns of the C tile and the K range
-// [ks, ke).  TRSM launches enumerate row tiles of the block column; the other
-// kinds enumerate the lower-triangular tiles of the updated block in the
-// grouped order of trap_grouped.  Returns false when the
-// workgroup has no tile, its tile reads identity border rows (or columns)
-// that are still zero over [ks, ke), or the row selection excludes it
-// (sel: 0 every tile, 1 tiles of the factored rows (row < nf), 2 tiles of the
-// border rows (row >= nf)).
+// Writes L_jj over the block's lower triangle at Ad (column-major, ld) and its
+// inverse into slot j / 64 of d.linv; records a failing pivot in d.info.
+template <typename T>
+__device__ __forceinline__ void potf2_store(const Potf2Lds &S, const FactorDesc &d, int j,
+                                            __attribute__((address_space(1))) T *Ad, int tid) {
+  __attribute__((address_space(1))) T *Li = gptr((T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
+#pragma unroll 4
+  for (int i = 0; i < NBI * NBI / 256; ++i) {
+    const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
+    if (r >= c) Ad[(size_t)c * d.ld + r] = (T)S.M[r][c];
+    Li[c * NBI + r] = (T)S.M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
+  }
+  if (tid == 0 && S.fail != 0 && *d.info == 0) *d.info = j + S.fail;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__restrict__ descs, int j) {
+  const FactorDesc d = descs[blockIdx.x];
+  if (j >= d.nf) return;
+  __shared__ Potf2Lds S;
+  const int tid = threadIdx.x;
+  __attribute__((address_space(1))) T *Ad = gptr((T *)d.A) + (size_t)j * d.ld + j;
+  // all 16 loads in flight before the first LDS store
+  T v[NBI * NBI / 256];
+#pragma unroll
+  for (int i = 0; i < NBI * NBI / 256; ++i) {
+    const int e = tid + 256 * i;
+    v[i] = Ad[(size_t)(e >> 6) * d.ld + (e & (NBI - 1))];
+  }
+#pragma unroll
+  for (int i = 0; i < NBI * NBI / 256; ++i) {
+    const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
+    S.M[r][c] = (r >= c) ? (double)v[i] : 0.0;
+    S.M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  if (tid == 0) S.fail = 0;
+  __syncthreads();
+  potf2_factor(S, tid);
+  potf2_store<T>(S, d, j, Ad, tid);
+}
+
 // XCD-aware workgroup order.  The hardware hands the workgroup with linear id
 // L to XCD L % 8, and each XCD has its own L2; remapped, XCD k walks the
 // contiguous range [k N/8, (k+1) N/8) of (theta, tile) pairs, so workgroups
@@ -200,36 +235,35 @@ __device__ __forceinline__ bool trap_grouped(int t, int nr, int nc, int &I, int 
   return true;
 }
 
-__device__ __forceinline__ bool update_tile(const FactorDesc &d, int kind, int p0, int nb, int j, int TM, int TN,
-                                            int sel, int bx, int &row0, int &col0, int &ks, int &ke) {
-  if (j >= d.nf) return false;
+// Tile bx of one trailing-update launch: rows/columns of the C tile and the K
+// range [ks, ke) = [p0, pend), the lower-triangular tiles of the updated block
+// in the grouped order of trap_grouped.  Returns false when the workgroup has
+// no tile, its tile reads identity border rows (or columns) that are still
+// zero over [ks, ke), or the row selection excludes it (sel: 0 every tile,
+// 1 tiles of the factored rows (row < nf), 2 tiles of the border rows
+// (row >= nf)).
+__device__ __forceinline__ bool update_tile(const FactorDesc &d, int kind, int p0, int nb, int TM, int TN, int sel,
+                                            int bx, int &row0, int &col0, int &ks, int &ke) {
+  if (p0 >= d.nf) return false;
   const int pend = min(p0 + nb, d.nf);
   int r0, c0, cend;
-  if (kind == KIND_TRSM) {
-    r0 = j + NBI; c0 = j; cend = j + NBI; ks = j; ke = j + NBI;
-  } else if (kind == KIND_PANEL) {
-    r0 = j + NBI; c0 = j + NBI; cend = pend; ks = j; ke = j + NBI;
-  } else if (kind == KIND_TRAIL) {
-    r0 = pend; c0 = pend; cend = d.ncols; ks = p0; ke = pend;
+  ks = p0; ke = pend;
+  if (kind == KIND_TRAIL) {
+    r0 = pend; c0 = pend; cend = d.ncols;
   } else if (kind == KIND_TRAIL_A) {
-    r0 = pend; c0 = pend; cend = min(pend + nb, d.nf); ks = p0; ke = pend;
+    r0 = pend; c0 = pend; cend = min(pend + nb, d.nf);
   } else {
-    c0 = min(pend + nb, d.nf); r0 = c0; cend = d.ncols; ks = p0; ke = pend;
+    c0 = min(pend + nb, d.nf); r0 = c0; cend = d.ncols;
   }
   if (r0 >= d.nrows || c0 >= cend) return false;
   const int nr = (d.nrows - r0) / TM;
   int I, J;
-  if (kind == KIND_TRSM) {
-    if (bx >= nr) return false;
-    I = bx; J = 0;
-  } else if (!trap_grouped(bx, nr, (cend - c0) / TN, I, J)) {
-    return false;
-  }
+  if (!trap_grouped(bx, nr, (cend - c0) / TN, I, J)) return false;
   row0 = r0 + I * TM;
   col0 = c0 + J * TN;
   if ((sel == 1 && row0 >= d.nf) || (sel == 2 && row0 < d.nf)) return false;
   if (row0 >= d.id_row0 && row0 - d.id_row0 >= ke) return false;
-  if (kind != KIND_TRSM && col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return false;
+  if (col0 >= d.id_row0 && col0 - d.id_row0 >= ke) return false;
   return true;
 }
 
@@ -286,8 +320,7 @@ __device__ __forceinline__ void subtract_tile(__attribute__((address_space(1))) 
 // trailing update of every row is trail_update_kernel (below), so that each
 // launch class has its own kernel symbol.
 template <typename T, int TM, int TN, int SEL>
-__device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ descs, int kind, int p0, int nb,
-                                                 int j) {
+__device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ descs, int kind, int p0, int nb) {
   constexpr bool F64 = sizeof(T) == 8;
   // K chunk staged per LDS buffer: 16 deep in both precisions, which keeps a
   // 128 x 128 FP32 tile's buffers at 34 KB (up to four workgroups per CU)
@@ -310,14 +343,11 @@ __device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ 
   xcd_order(bx, by);
   const FactorDesc d = descs[by];
   int row0, col0, ks, ke;
-  if (!update_tile(d, kind, p0, nb, j, TM, TN, SEL, bx, row0, col0, ks, ke)) return;
+  if (!update_tile(d, kind, p0, nb, TM, TN, SEL, bx, row0, col0, ks, ke)) return;
 
-  const int ld = d.ld;
+  const int ld = d.ld, ldb = ld;
   gcT *Ag = gptr((const T *)d.A) + (size_t)ks * ld + row0;
-  gcT *Bg;
-  int ldb;
-  if (kind == KIND_TRSM) { Bg = gptr((const T *)d.linv) + (size_t)(j / NBI) * NBI * NBI; ldb = NBI; }
-  else { Bg = gptr((const T *)d.A) + (size_t)ks * ld + col0; ldb = ld; }
+  gcT *Bg = gptr((const T *)d.A) + (size_t)ks * ld + col0;
   gT *Cg = gptr((T *)d.A) + (size_t)col0 * ld + row0;
   const int K = ke - ks;
 
@@ -388,32 +418,247 @@ __device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ 
   // Epilogue: tile element (rl(a, v), cl(b, v)) for accumulator component v.
   auto rl = [&](int a, int v) { return wm * WTM + a * 16 + (F64 ? li : 4 * g + v); };
   auto cl = [&](int b, int v) { return wn * WTN + b * 16 + (F64 ? g + 4 * v : li); };
-  const bool diag_tile = (kind != KIND_TRSM) && (row0 < col0 + TN);
-  if (kind == KIND_TRSM) {
-#pragma unroll
-    for (int a = 0; a < BM; ++a)
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = acc[a][b][v];
-  } else {
-    subtract_tile<T, BM, BN>(Cg, ld, acc, rl, cl, diag_tile, row0, col0);
-  }
+  subtract_tile<T, BM, BN>(Cg, ld, acc, rl, cl, row0 < col0 + TN, row0, col0);
 }
 
-// Panel TRSM and in-panel updates (SEL 0), border rows beside a BF16 trailing
-// update (SEL 2).
+// The border rows' trailing update beside a BF16 trailing update (SEL 2).
 template <typename T, int TM, int TN, int SEL>
 __global__ __launch_bounds__(256, 2) void gemm_update_kernel(const FactorDesc *__restrict__ descs, int kind,
-                                                             int p0, int nb, int j) {
-  gemm_update_body<T, TM, TN, SEL>(descs, kind, p0, nb, j);
+                                                             int p0, int nb) {
+  gemm_update_body<T, TM, TN, SEL>(descs, kind, p0, nb);
 }
 
 // The trailing update of the blocked Cholesky (kinds TRAIL, TRAIL_A, TRAIL_B).
 template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256, 2) void trail_update_kernel(const FactorDesc *__restrict__ descs, int kind, int p0,
                                                               int nb) {
-  gemm_update_body<T, TM, TN, 0>(descs, kind, p0, nb, p0);
+  gemm_update_body<T, TM, TN, 0>(descs, kind, p0, nb);
+}
+
+// --------------------------------------------------------------------------
+// One step of the left-looking panel: block column j of the panel [p0, pend),
+// one 64-row tile I (rows r0 = j + 64 (t + 1) .. r0 + 63) per workgroup:
+//   C      = A[I, j] - A[I, p0:j] A[j, p0:j]^T     (the panel's earlier columns,
+//                                                  MFMA from global via LDS)
+//   L[I,j] = C L_jj^{-T}                           (MFMA, both operands in LDS)
+//   A[I,I] -= L[I,j] L[I,j]^T                      (tiles with r0 < pend: the
+//                                                  diagonal block's update)
+// The tile just below the diagonal block (t = 0) then holds the next diagonal
+// block fully updated and factors it (potf2_factor) in the same launch, so a
+// panel takes one potf2_inv launch and one launch per block column.  Each tile
+// reads its own rows of the panel's earlier columns and writes one 64 x 64
+// block, in place of the right-looking rank-64 updates that read and wrote
+// the panel's whole trailing part once per block column.
+//
+// Identity border rows (rows id_row0 + s hold e_s) are zero left of column s,
+// so a tile of them starts its K range at r0 - id_row0 and is skipped when
+// that is past the block column.
+//
+// Grid: act + 8 Q workgroups.  The first act (one per theta) take tile 0, so
+// the diagonal factorisations start first; the rest take tiles 1 .. gx - 1 of
+// every theta in the XCD-aware order of xcd_order (Q = ceil(act (gx - 1) / 8)).
+// --------------------------------------------------------------------------
+template <typename T>
+struct PanelLds {
+  static constexpr int LDC = NBI + 4;   // LDS row length (elements): conflict-free MFMA operand reads
+  union {
+    struct { T As[2][KC][LDC]; T Bs[2][KC][LDC]; } g;   // K chunks of the left-looking product
+    struct { T Cs[NBI][LDC]; T Xs[NBI][LDC]; } s;       // TRSM / SYRK operands, [k][row]
+    Potf2Lds f;                                         // the next diagonal block's factorisation
+  };
+};
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__restrict__ descs, int p0, int nb,
+                                                            int j, int act, int gx, int Q) {
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr int VEC = 16 / sizeof(T);
+  constexpr int WTM = 32, WTN = 32, BM = 2, BN = 2;   // 2 x 2 waves, 32 x 32 wave tiles
+  constexpr int LA = KC * NBI / VEC / 256;            // 16-byte loads per thread per operand chunk
+  typedef T vec_t __attribute__((ext_vector_type(VEC)));
+  typedef __attribute__((address_space(1))) T gT;
+  typedef __attribute__((address_space(1))) const vec_t gcvec;
+  typedef typename std::conditional<F64, d4, f4>::type acc_t;
+  __shared__ __attribute__((aligned(16))) PanelLds<T> S;
+
+  int th, t;
+  {
+    const int L = blockIdx.x;
+    if (L < act) {
+      th = L; t = 0;
+    } else {
+      const int L2 = L - act, G = (L2 & 7) * Q + (L2 >> 3);
+      if (gx <= 1 || G >= act * (gx - 1)) return;
+      th = G / (gx - 1);
+      t = 1 + G % (gx - 1);
+    }
+  }
+  const FactorDesc d = descs[th];
+  if (j >= d.nf) return;
+  const int r0 = j + NBI * (t + 1);
+  if (r0 >= d.nrows) return;
+  const int pend = min(p0 + nb, d.nf);
+  int ks = p0;
+  if (r0 >= d.id_row0) {
+    if (r0 - d.id_row0 >= j + NBI) return;   // zero in block column j: nothing to do
+    ks = max(ks, r0 - d.id_row0);
+  }
+  const int ld = d.ld, K = j - ks;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w >> 1, wn = w & 1;
+  const int g = lane >> 4, li = lane & 15;
+  // tile element (rl(a, v), cl(b, v)) of accumulator component v
+  auto rl = [&](int a, int v) { return wm * WTM + a * 16 + (F64 ? li : 4 * g + v); };
+  auto cl = [&](int b, int v) { return wn * WTN + b * 16 + (F64 ? g + 4 * v : li); };
+  acc_t acc[BM][BN];
+  auto zero = [&] {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  };
+  // acc += X(64 x 16) Y(64 x 16)^T for one 16-deep chunk held [k][row] in LDS
+  auto mfma_chunk = [&](const T (*X)[PanelLds<T>::LDC], const T (*Y)[PanelLds<T>::LDC], int k0) {
+#pragma unroll
+    for (int s = 0; s < KC / 4; ++s) {
+      const int kk = k0 + 4 * g + s;
+      T ya[BM], xb[BN];
+#pragma unroll
+      for (int a = 0; a < BM; ++a) ya[a] = X[kk][wm * WTM + a * 16 + li];
+#pragma unroll
+      for (int b = 0; b < BN; ++b) xb[b] = Y[kk][wn * WTN + b * 16 + li];
+#pragma unroll
+      for (int a = 0; a < BM; ++a)
+#pragma unroll
+        for (int b = 0; b < BN; ++b) {
+          if constexpr (F64) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
+          else acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[a], xb[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  };
+
+  // 1. acc = A[I, ks:j] A[j, ks:j]^T, double-buffered 16-deep chunks
+  zero();
+  if (K > 0) {
+    const __attribute__((address_space(1))) T *Ag = gptr((const T *)d.A) + (size_t)ks * ld + r0;
+    const __attribute__((address_space(1))) T *Bg = gptr((const T *)d.A) + (size_t)ks * ld + j;
+    vec_t ra[LA], rb[LA];
+    auto gload = [&](int kc) {
+#pragma unroll
+      for (int it = 0; it < LA; ++it) {
+        const int lin = it * 256 + tid, kk = lin / (NBI / VEC), rp = lin % (NBI / VEC);
+        ra[it] = *reinterpret_cast<gcvec *>(Ag + (size_t)(kc + kk) * ld + VEC * rp);
+        rb[it] = *reinterpret_cast<gcvec *>(Bg + (size_t)(kc + kk) * ld + VEC * rp);
+      }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+      for (int it = 0; it < LA; ++it) {
+        const int lin = it * 256 + tid, kk = lin / (NBI / VEC), rp = lin % (NBI / VEC);
+        *reinterpret_cast<vec_t *>(&S.g.As[buf][kk][VEC * rp]) = ra[it];
+        *reinterpret_cast<vec_t *>(&S.g.Bs[buf][kk][VEC * rp]) = rb[it];
+      }
+    };
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int kc = 0; kc < K; kc += KC) {
+      const bool more = kc + KC < K;
+      if (more) gload(kc + KC);
+      mfma_chunk(S.g.As[buf], S.g.Bs[buf], 0);
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+
+  // 2. C = A[I, j] - acc into LDS as the TRSM's left operand (k = column of
+  //    block j), and L_jj^{-1} (column-major: X[n][k] at k * 64 + n) as its right
+  gT *Cg = gptr((T *)d.A) + (size_t)j * ld + r0;
+  {
+    const __attribute__((address_space(1))) T *Li = gptr((const T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
+    vec_t xv[NBI * NBI / VEC / 256];
+#pragma unroll
+    for (int it = 0; it < NBI * NBI / VEC / 256; ++it) {
+      const int lin = it * 256 + tid;
+      xv[it] = *reinterpret_cast<gcvec *>(Li + (size_t)VEC * lin);
+    }
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rl(a, v), c = cl(b, v);
+          S.s.Cs[c][r] = Cg[(size_t)c * ld + r] - acc[a][b][v];
+        }
+#pragma unroll
+    for (int it = 0; it < NBI * NBI / VEC / 256; ++it) {
+      const int lin = it * 256 + tid, kk = lin / (NBI / VEC), rp = lin % (NBI / VEC);
+      *reinterpret_cast<vec_t *>(&S.s.Xs[kk][VEC * rp]) = xv[it];
+    }
+  }
+  __syncthreads();
+  // 3. L[I, j] = C L_jj^{-T}
+  zero();
+#pragma unroll
+  for (int k0 = 0; k0 < NBI; k0 += KC) mfma_chunk(S.s.Cs, S.s.Xs, k0);
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = acc[a][b][v];
+  if (r0 >= pend) return;
+
+  // 4. diagonal block of the tile's rows: A[I, I] -= L[I, j] L[I, j]^T
+  __syncthreads();   // every wave is done reading Cs
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) S.s.Cs[cl(b, v)][rl(a, v)] = acc[a][b][v];
+  __syncthreads();
+  zero();
+#pragma unroll
+  for (int k0 = 0; k0 < NBI; k0 += KC) mfma_chunk(S.s.Cs, S.s.Cs, k0);
+  gT *Dg = gptr((T *)d.A) + (size_t)r0 * ld + r0;
+  if (t != 0) {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = rl(a, v), c = cl(b, v);
+          if (r >= c) Dg[(size_t)c * ld + r] = Dg[(size_t)c * ld + r] - acc[a][b][v];
+        }
+    return;
+  }
+
+  // 5. tile 0: the block at r0 = j + 64 has had every update of the panel's
+  //    earlier columns; factor it in LDS and store L and its inverse
+  __syncthreads();   // every wave is done reading Cs before Potf2Lds reuses it
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rl(a, v), c = cl(b, v);
+        S.f.M[r][c] = (r >= c) ? (double)(T)(Dg[(size_t)c * ld + r] - acc[a][b][v]) : 0.0;
+      }
+#pragma unroll
+  for (int i = 0; i < NBI * NBI / 256; ++i) {
+    const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
+    S.f.M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  if (tid == 0) S.f.fail = 0;
+  __syncthreads();
+  potf2_factor(S.f, tid);
+  potf2_store<T>(S.f, d, r0, Dg, tid);
 }
 
 // --------------------------------------------------------------------------
@@ -465,7 +710,7 @@ __global__ __launch_bounds__(256, 2) void trail_bf16_kernel(const FactorDesc *__
   xcd_order(bx, by);
   const FactorDesc d = descs[by];
   int row0, col0, ks, ke;
-  if (!update_tile(d, kind, p0, nb, p0, TM, TN, 1, bx, row0, col0, ks, ke)) return;
+  if (!update_tile(d, kind, p0, nb, TM, TN, 1, bx, row0, col0, ks, ke)) return;
   const int ld = d.ld;
   // the packed panel: entry (group g, row r) at P[g * nf + r]; k = ks + 8 g
   gcbf8 *P = gptr((const bf8 *)d.pbf + (size_t)((p0 / nb) & 1) * d.pbf_slot);
@@ -578,18 +823,15 @@ static double lower_real(const HostFactor &h, int c0, int c1, bool only_factored
   return s;
 }
 
-static int tiles_for(const FactorDesc &d, int kind, int p0, int nb, int j, int TM) {
-  if (j >= d.nf) return 0;
+static int tiles_for(const FactorDesc &d, int kind, int p0, int nb, int TM) {
+  if (p0 >= d.nf) return 0;
   const int pend = std::min(p0 + nb, d.nf);
   int r0, c0, cend;
-  if (kind == KIND_TRSM) { r0 = j + NBI; c0 = j; cend = j + NBI; }
-  else if (kind == KIND_PANEL) { r0 = j + NBI; c0 = j + NBI; cend = pend; }
-  else if (kind == KIND_TRAIL) { r0 = pend; c0 = pend; cend = d.ncols; }
+  if (kind == KIND_TRAIL) { r0 = pend; c0 = pend; cend = d.ncols; }
   else if (kind == KIND_TRAIL_A) { r0 = pend; c0 = pend; cend = std::min(pend + nb, d.nf); }
   else { c0 = std::min(pend + nb, d.nf); r0 = c0; cend = d.ncols; }
   if (r0 >= d.nrows || c0 >= cend) return 0;
   const int nr = (d.nrows - r0) / TM;
-  if (kind == KIND_TRSM) return nr;
   const int nc = (cend - c0) / TM;
   return nc * (nc + 1) / 2 + (nr - nc) * nc;
 }
@@ -651,49 +893,51 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
     const HostFactor &h = fs[order[i]];
     key0.insert(key0.end(), {h.d.nf, h.d.nrows, h.d.ncols, h.d.id_row0, h.n_real, h.kb_real, h.ks_real});
   }
-  // the panel [p0, p0 + nb): potf2_inv, TRSM and in-panel update of every
-  // 64-wide block (one graph replay), enqueued on ctx.stream
+  // the panel [p0, p0 + nb): potf2_inv of its first diagonal block, then one
+  // left-looking panel step per 64-wide block column (one graph replay),
+  // enqueued on ctx.stream
   auto panel_seq = [&](int p0, const std::vector<int64_t> &key) -> int {
     return ctx.sequence(INLA_K_PANEL, key, hd.data(), sizeof(FactorDesc) * B, [&](const void *dv) {
       const FactorDesc *pd = (const FactorDesc *)dv;
       for (int j = p0; j < p0 + nb && j < nf_max; j += NBI) {
         const int act = active(j);
-        {
+        if (j == p0) {
           double fl = 0;
           for (int i = 0; i < act; ++i) {
-            const HostFactor &h = fs[order[i]];
-            const double kr = std::max(0, std::min(NBI, h.n_real - j));
+            const double kr = std::max(0, std::min(NBI, fs[order[i]].n_real - j));
             fl += 2.0 * kr * kr * kr / 3.0;
           }
           ctx.launch(INLA_K_POTF2, fl, 0.0, [&] {
             hipLaunchKernelGGL(potf2_inv_kernel<T>, dim3(act), dim3(256), 0, ctx.stream, pd, j);
           });
         }
-        for (int kind : {KIND_TRSM, KIND_PANEL}) {
-          int gx = 0;
-          double fl = 0, by = 0;
-          for (int i = 0; i < act; ++i) {
-            const HostFactor &h = fs[order[i]];
-            gx = std::max(gx, tiles_for(h.d, kind, p0, nb, j, 64));
-            const int pend = std::min(p0 + nb, h.d.nf);
-            const double kr = std::max(0, std::min(NBI, h.n_real - j));
-            if (kind == KIND_TRSM) {
-              const double m = count_rows_real(h, j + NBI);
-              fl += m * kr * kr;
-              by += 2.0 * esz * m * kr;
-            } else if (j + NBI < pend) {
-              const double nc = count_cols_real(h, j + NBI, pend), nr = count_rows_real(h, j + NBI);
-              fl += 2.0 * trap_elems(nr, nc) * kr;
-              by += 2.0 * esz * trap_elems(nr, nc) + esz * (nr + nc) * kr;
-            }
+        // algorithmic work per theta (real rows and columns): the left-looking
+        // product over [p0, j), the TRSM, the SYRK of each in-panel diagonal
+        // block below and the next diagonal block's factorisation
+        int gx = 0;
+        double fl = 0, by = 0;
+        for (int i = 0; i < act; ++i) {
+          const HostFactor &h = fs[order[i]];
+          gx = std::max(gx, (h.d.nrows - j - NBI) / NBI);
+          const int pend = std::min(p0 + nb, h.d.nf);
+          const double kr = std::max(0, std::min(NBI, h.n_real - j));
+          const double kl = std::max(0, std::min(j, h.n_real) - p0);
+          const double m = count_rows_real(h, j + NBI);
+          fl += 2.0 * m * kr * kl + m * kr * kr;
+          by += esz * m * (kl + 2.0 * kr);
+          for (int r = j + NBI; r < pend; r += NBI) {
+            const double kd = std::max(0, std::min(NBI, h.n_real - r));
+            fl += kd * (kd + 1.0) * kr;
+            by += 2.0 * esz * kd * (kd + 1.0) * 0.5;
+            if (r == j + NBI) fl += 2.0 * kd * kd * kd / 3.0;
           }
-          if (gx == 0) continue;
-          gx = round_up(gx, 8);   // xcd_order needs a grid of a multiple of 8 workgroups
-          ctx.launch(INLA_K_PANEL, fl, by, [&] {
-            hipLaunchKernelGGL((gemm_update_kernel<T, 64, 64, 0>), dim3(gx, act), dim3(256), 0, ctx.stream, pd,
-                               kind, p0, nb, j);
-          });
         }
+        if (gx == 0) continue;
+        const int Q = (act * (gx - 1) + 7) / 8;
+        ctx.launch(INLA_K_PANEL, fl, by, [&] {
+          hipLaunchKernelGGL(panel_step_kernel<T>, dim3(act + 8 * Q), dim3(256), 0, ctx.stream, pd, p0, nb, j, act,
+                             gx, Q);
+        });
       }
     });
   };
@@ -732,7 +976,7 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
     bool rows_q = false;                          // some theta has factored rows in the region
     for (int i = 0; i < act; ++i) {
       const HostFactor &h = fs[order[i]];
-      gx = std::max(gx, tiles_for(h.d, kind, p0, nb, p0, TT));
+      gx = std::max(gx, tiles_for(h.d, kind, p0, nb, TT));
       const int pend = std::min(p0 + nb, h.d.nf), pnext = std::min(pend + nb, h.d.nf);
       int c0 = pend, c1 = h.d.ncols;
       if (kind == KIND_TRAIL_A) c1 = pnext;
@@ -761,7 +1005,7 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
         });
       ctx.launch(INLA_K_BORDER, fl - fl_q, by - by_q, [&] {
         hipLaunchKernelGGL((gemm_update_kernel<T, 128, 128, 2>), dim3(gx, act), dim3(256), 0, ctx.stream, dd, kind,
-                           p0, nb, p0);
+                           p0, nb);
       });
     } else if (TT == 64) {
       ctx.launch(INLA_K_TRAIL, fl, by, [&] {
