@@ -198,6 +198,31 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
     }
 
 
+def time_unprofiled(lib, dms, thetas, xs, variant, steps, warmup, warm=None):
+    """Whole steps of a variant with profiling off (no per-launch events), so
+    that the whole-pass graphs, which profiling turns off, can run."""
+    import torch
+    prec = variant.split("+")[0]
+
+    def step():
+        if warm is None:
+            return lib.laplace_eval(dms, thetas, x=xs, prec=prec)
+        mlp, centre, scale, max_iter = warm
+        mlp.predict_modes(thetas, centre, scale, x=xs)
+        return lib.laplace_eval(dms, thetas, x=xs, start=1, max_iter=max_iter, prec=prec)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, _ = step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert all(r["info"] == 0 for r in res)
+    return {"value": steps * len(dms) / dt, "ms_per_step": dt / steps * 1e3, "steps": steps}
+
+
 def amortised_warm_start(results, train_info, counts=(512, 4096)):
     """What the learned warm start buys an INLA run once its one-time cost is
     charged to the evaluations it speeds up.  For each mixed precision p with a
@@ -723,6 +748,21 @@ def main():
                     "newton_iters": r["newton_iters"], "kernel_time_ms": r["kernel_time_ms"],
                     "roofline": {k: r["roofline"][k] for k in ("achieved", "peak", "unit", "frac", "launches",
                                                                "avg_launch_ms")}}
+    unprofiled = None
+    if not args.no_graphs:
+        # the headline variant without per-launch events, with and without the
+        # whole-pass graphs (each Newton pass and refinement step one hipGraph)
+        w = max(3, args.steps // 4)
+        st0 = lib.pass_graph_stats()
+        with_pg = time_unprofiled(lib, dms, thetas, xs, head, w, 2, warm)
+        st1 = lib.pass_graph_stats()
+        lib.set_pass_graphs(False)
+        direct = time_unprofiled(lib, dms, thetas, xs, head, w, 1, warm)
+        lib.set_pass_graphs(True)
+        unprofiled = {"pass_graphs": dict(with_pg, captured=st1["captured"] - st0["captured"],
+                                          replays=st1["replays"] - st0["replays"]),
+                      "chain_graphs_only": direct}
+        log(f"unprofiled headline: {unprofiled}")
     for v in variants:
         roof = results[v]["roofline"]
         pv = roof["precision"]
@@ -755,6 +795,7 @@ def main():
         },
         "roofline": hv["roofline"],
         "headline_prior_pass_in_order": in_order,
+        "headline_unprofiled": unprofiled,
         "variants": results,
         "autotune": tuning or None,
         "graphs": not args.no_graphs,

@@ -404,7 +404,12 @@ int inla_ccd_weights(int32_t n_points, const double *delta, const double *log_po
  *            (both triangles written), column-major, leading dimension ldp[b]
  *   rtol     relative rank threshold; <= 0: 1e-9
  *   rank     host [B] output: number of eigenvalues kept
- *   sweeps   host [B] output: Jacobi sweeps taken
+ *   sweeps   host [B] output: outer sweeps taken.  An outer sweep is one
+ *            round-robin sweep of the largest active matrix of the batch
+ *            (nbk - 1 rounds, nbk = its order in 32-index blocks); a smaller
+ *            matrix takes its own rounds in order meanwhile, so it completes
+ *            more than one of its own sweeps per outer sweep and is checked
+ *            for convergence at the outer sweep boundaries
  *   info     host [B] output: 0, INLA_INFO_EIG_MAXIT or INLA_INFO_NONFINITE
  * Uses the handle's workspace (2 ne^2 + O(ne) doubles per matrix, ne = n
  * rounded up to 64) and synchronises the handle's stream once per sweep.
@@ -568,6 +573,26 @@ int inla_set_lookahead(inla_handle *h, int32_t enable);
 int inla_set_overlap(inla_handle *h, int32_t enable);
 /* Graphs captured and replayed so far by this handle (host outputs; either may be NULL). */
 int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
+/* Whole-pass graphs (on by default; used while graphs are on and profiling is
+ * off).  Each pass of inla_laplace_eval / inla_constrained_mode over a set of
+ * theta (the bordered assembly at the current iterate, the factorisation of
+ * Q* with the constraint and right-hand-side border rows, the kriging system's
+ * build, factorisation and solve, and the Newton step: back-substitution and
+ * acceptance, or the correction-form restart, or the final log-dets) and each
+ * mixed-precision refinement step (FP64 KKT residual, the two triangular
+ * solves, the kriging correction and the update) is one hipGraph, keyed by the
+ * pass, the precision, the tuning table's state and every theta's sizes, and
+ * launched with one copy of its argument block; the host reads back only the
+ * per-theta results that decide the next pass.  A key's first pass runs
+ * directly, its second is captured, later ones replay (after re-deriving the
+ * arguments and checking the launch sequence against the captured one).  BF16
+ * passes and the factorisation's lookahead stay outside these graphs.
+ * Results are identical with and without them.  The handle keeps at most 64
+ * pass keys (4 MB of device arguments per captured pass) and releases them as
+ * inla_set_graphs(h, 0) does.  Returns -1 for a null handle. */
+int inla_set_pass_graphs(inla_handle *h, int32_t enable);
+/* Pass graphs captured and replayed so far by this handle (host outputs; either may be NULL). */
+int inla_pass_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
 /* Autotuner of the blocked Cholesky.  A configuration is int32_t[3] =
  * {nb, tm, lookahead}: panel width nb in {128, 256, 512, 1024}, trailing tile
  * tm in {64, 128} (128 only for INLA_PREC_BF16) and lookahead 0 or 1 (see

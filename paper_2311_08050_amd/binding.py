@@ -36,7 +36,8 @@ EXPORTS = [
     "inla_laplace_eval", "inla_marginal_var", "inla_profile", "inla_profile_get", "inla_version",
     "inla_mlp_create", "inla_mlp_destroy", "inla_mlp_num_params", "inla_mlp_get_params", "inla_mlp_set_params",
     "inla_mlp_forward", "inla_mlp_grad", "inla_mlp_train_step", "inla_mlp_predict_modes",
-    "inla_set_graphs", "inla_set_lookahead", "inla_set_overlap", "inla_graph_stats",
+    "inla_set_graphs", "inla_set_lookahead", "inla_set_overlap", "inla_graph_stats", "inla_set_pass_graphs",
+    "inla_pass_graph_stats",
     "inla_vb_mean", "inla_theta_mode", "inla_theta_hessian", "inla_ccd_design", "inla_ccd_points", "inla_ccd_weights", "inla_autotune", "inla_tune_set", "inla_tune_get",
     "inla_pinv", "inla_woodbury_eval", "inla_woodbury_var",
     "inla_pinv_prior_assemble", "inla_theta_mode_pinv", "inla_theta_hessian_pinv",
@@ -149,6 +150,8 @@ def load_library(path: str = LIBPATH):
     lib.inla_set_lookahead.argtypes = [P, i32]
     lib.inla_set_overlap.argtypes = [P, i32]
     lib.inla_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    lib.inla_set_pass_graphs.argtypes = [P, i32]
+    lib.inla_pass_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     lib.inla_autotune.argtypes = [P, i32, pi32, pi32, i32, i32, pi32, pd, pi32]
     lib.inla_tune_set.argtypes = [P, i32, i32, i32, pi32]
     lib.inla_tune_get.argtypes = [P, i32, i32, i32, pi32]
@@ -518,6 +521,15 @@ class Library:
     def graph_stats(self):
         cap, rep = C.c_int64(), C.c_int64()
         self._check(self.lib.inla_graph_stats(self.h, C.byref(cap), C.byref(rep)), "inla_graph_stats")
+        return {"captured": cap.value, "replays": rep.value}
+
+    def set_pass_graphs(self, on: bool):
+        """One hipGraph per Newton pass and per refinement step (default on)."""
+        self._check(self.lib.inla_set_pass_graphs(self.h, 1 if on else 0), "inla_set_pass_graphs")
+
+    def pass_graph_stats(self):
+        cap, rep = C.c_int64(), C.c_int64()
+        self._check(self.lib.inla_pass_graph_stats(self.h, C.byref(cap), C.byref(rep)), "inla_pass_graph_stats")
         return {"captured": cap.value, "replays": rep.value}
 
     def autotune(self, ns, kbs, prec="fp64", reps=2):

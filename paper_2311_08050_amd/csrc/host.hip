@@ -66,13 +66,25 @@ static bool ring_wrap(Ctx &c) {
 }
 
 void *Ctx::upload(const void *src, size_t bytes) {
-  bytes = align256(bytes);
-  if (bytes > ring_size) return nullptr;
-  if (ring_off + bytes > ring_size && !ring_wrap(*this)) return nullptr;
+  const size_t padded = align256(bytes);
+  if (pg_mode != PG_OFF) {
+    // a pass graph's argument block: the next slot, filled before the replay
+    const size_t off = pg.host.size();
+    if (off + padded > pg.cap) {
+      pg.overflow = true;
+      return nullptr;
+    }
+    pg.host.resize(off + padded, 0);
+    std::memcpy(pg.host.data() + off, src, bytes);
+    pg.sig.push_back(-(int64_t)bytes);
+    return pg.dbase + off;
+  }
+  if (padded > ring_size) return nullptr;
+  if (ring_off + padded > ring_size && !ring_wrap(*this)) return nullptr;
   std::memcpy(ring_host + ring_off, src, bytes);
   void *dst = ring + ring_off;
   if (hipMemcpyAsync(dst, ring_host + ring_off, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) return nullptr;
-  ring_off += bytes;
+  ring_off += padded;
   return dst;
 }
 
@@ -97,6 +109,15 @@ int Ctx::sequence(int cls, const std::vector<int64_t> &key, const void *args, si
 
 int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key0, const void *args, size_t nbytes,
                        const std::function<void(const void *)> &body) {
+  if (pg_mode != PG_OFF) {
+    // inside a pass graph: the arguments take a slot of its block and the
+    // launches become part of the pass
+    const void *d = upload(args, nbytes);
+    if (!d) return INLA_ERR_NOMEM;
+    pg.sig.insert(pg.sig.end(), key0.begin(), key0.end());
+    body(d);
+    return check();
+  }
   if (capturing) return INLA_ERR_UNSUPPORTED;   // sequences do not nest
   if (!graphs) {
     const void *d = upload(args, nbytes);
@@ -168,13 +189,127 @@ int Ctx::sequence_impl(int cls, const std::vector<int64_t> &key0, const void *ar
 }
 
 void Ctx::drop_graphs() {
-  if (graph_cache.empty()) return;
+  if (graph_cache.empty() && pass_cache.empty()) return;
   (void)sync_all();
   for (auto &kv : graph_cache) {
     (void)hipGraphExecDestroy(kv.second.exec);
     (void)hipFree(kv.second.dargs);
   }
   graph_cache.clear();
+  for (auto &kv : pass_cache) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.dargs) (void)hipFree(kv.second.dargs);
+  }
+  pass_cache.clear();
+}
+
+// Argument block of one pass graph, and the number of passes the handle keeps
+// (graphs and keys seen once, least recently used dropped first).
+static constexpr size_t PASS_ARGS_CAP = 4u << 20;
+static constexpr size_t PASS_CACHE_MAX = 64;
+
+int Ctx::pass_graph(int cls, const std::vector<int64_t> &key0, const std::function<int()> &body) {
+  if (!graphs || !pass_graphs || prof || capturing || pg_mode != PG_OFF) return body();
+  std::vector<int64_t> key = key0;
+  key.push_back(lane);
+  const int sticky0 = sticky;
+  auto drop = [&](std::map<std::vector<int64_t>, PassGraph>::iterator q) {
+    if (q->second.exec) {
+      (void)sync_all();
+      (void)hipGraphExecDestroy(q->second.exec);
+    }
+    if (q->second.dargs) (void)hipFree(q->second.dargs);
+    pass_cache.erase(q);
+  };
+  auto replay = [&](PassGraph &g, std::vector<char> &args) -> int {
+    g.used = ++graph_clock;
+    if (args != g.last) {
+      const int rc = upload_to(g.dargs, args.data(), args.size());
+      if (rc) return rc;
+      g.last.swap(args);
+    }
+    ++pass_replayed;
+    hipError_t le = hipSuccess;
+    launch(cls, g.flops, g.bytes, [&] { le = hipGraphLaunch(g.exec, stream); });
+    if (le != hipSuccess) {
+      last = le;
+      return INLA_ERR_HIP;
+    }
+    return check();
+  };
+  auto it = pass_cache.find(key);
+  if (it != pass_cache.end() && it->second.exec) {
+    // the host side of the pass, enqueueing nothing: its arguments in upload
+    // order, and its launch signature
+    PassGraph &g = it->second;
+    pg = PassRec{};
+    pg.dbase = g.dargs;
+    pg.cap = g.cap;
+    pg_mode = PG_COLLECT;
+    const int rc = body();
+    pg_mode = PG_OFF;
+    if (rc == INLA_OK && !pg.overflow && pg.sig == g.sig) return replay(g, pg.host);
+    sticky = sticky0;
+    if (rc == INLA_OK && !pg.overflow) drop(it);   // the key does not fix this pass: capture it anew next time
+    return body();
+  }
+  if (it == pass_cache.end()) {
+    // first sighting: remember the key, run directly
+    if (pass_cache.size() >= PASS_CACHE_MAX) {
+      auto lru = pass_cache.begin();
+      for (auto q = pass_cache.begin(); q != pass_cache.end(); ++q)
+        if (q->second.used < lru->second.used) lru = q;
+      drop(lru);
+    }
+    PassGraph g;
+    g.used = ++graph_clock;
+    pass_cache.emplace(key, std::move(g));
+    return body();
+  }
+  // second sighting: capture on the handle's private stream
+  PassGraph &g = it->second;
+  if (!cap_stream && hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    cap_stream = nullptr;
+    return body();
+  }
+  if (!g.dargs) {
+    if (hipMalloc(&g.dargs, PASS_ARGS_CAP) != hipSuccess) {
+      (void)hipGetLastError();
+      g.dargs = nullptr;
+      return body();
+    }
+    g.cap = PASS_ARGS_CAP;
+  }
+  pg = PassRec{};
+  pg.dbase = g.dargs;
+  pg.cap = g.cap;
+  hipStream_t user = stream;
+  stream = cap_stream;
+  pg_mode = PG_CAPTURE;
+  hipError_t e = hipStreamBeginCapture(cap_stream, hipStreamCaptureModeRelaxed);
+  const int rc = e == hipSuccess ? body() : INLA_ERR_HIP;
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = e == hipSuccess ? hipStreamEndCapture(cap_stream, &graph) : e;
+  stream = user;
+  pg_mode = PG_OFF;
+  hipGraphExec_t exec = nullptr;
+  bool ok = rc == INLA_OK && !pg.overflow && e == hipSuccess && e2 == hipSuccess && graph;
+  if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+  if (graph) (void)hipGraphDestroy(graph);
+  if (!ok) {
+    // nothing of the pass has run: run it directly
+    (void)hipGetLastError();
+    sticky = sticky0;
+    drop(it);
+    return body();
+  }
+  g.exec = exec;
+  g.sig.swap(pg.sig);
+  g.flops = pg.flops;
+  g.bytes = pg.bytes;
+  ++pass_captured;
+  return replay(g, pg.host);
 }
 
 char *Ctx::pbf_reserve(size_t bytes) {
@@ -212,6 +347,13 @@ bool Ctx::reserve(size_t bytes) {
 }
 
 void Ctx::launch(int cls, double flops, double bytes, const std::function<void()> &f) {
+  if (pg_mode != PG_OFF) {
+    pg.sig.insert(pg.sig.end(), {cls, (int64_t)std::llround(flops), (int64_t)std::llround(bytes)});
+    pg.flops += flops;
+    pg.bytes += bytes;
+    if (pg_mode == PG_CAPTURE) f();
+    return;
+  }
   if (capturing) {
     cap_flops += flops;
     cap_bytes += bytes;
@@ -277,6 +419,10 @@ Ctx::~Ctx() {
   for (auto &kv : graph_cache) {
     (void)hipGraphExecDestroy(kv.second.exec);
     (void)hipFree(kv.second.dargs);
+  }
+  for (auto &kv : pass_cache) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.dargs) (void)hipFree(kv.second.dargs);
   }
   if (cap_stream) (void)hipStreamDestroy(cap_stream);
   for (hipStream_t *s : {&side, &aux})
@@ -526,9 +672,33 @@ static int prior_build(Batch &b, const std::vector<int> &ids) {
 // PASS_STEP: a Newton step in correction form (factor and kriging system only;
 // the correction itself is one refinement step from the current iterate).
 enum Pass { PASS_PRIOR = 0, PASS_NEWTON = 1, PASS_FINAL = 2, PASS_STEP = 3 };
+
+// Key of a pass graph: the pass, its precision, the tuning table's state and
+// the sizes of every theta, in order (they fix every grid and scalar argument;
+// the pass graph also checks the launch signature).
+static std::vector<int64_t> pass_key(const Batch &b, const std::vector<int> &ids, int64_t tag, int prec) {
+  std::vector<int64_t> k = {0x50415353, tag, prec, (int64_t)b.ctx.tune_epoch, (int64_t)ids.size()};
+  for (int i : ids) {
+    const ThetaDesc &t = b.plans[i].t;
+    k.insert(k.end(), {t.n, t.k, t.n_pad, t.Nw, t.Ncw, t.k_pad, t.Ns, t.m, t.lik, t.prior});
+  }
+  return k;
+}
+
+static int run_pass_body(Batch &b, const std::vector<int> &ids, Pass pass, int prec);
+
+// A pass of every theta in `ids`, enqueued as one hipGraph per pass shape where
+// graphs allow (FP64 and FP32 passes; the BF16 trailing update's packed panel
+// copies grow their buffer between launches).
 static int run_pass(Batch &b, const std::vector<int> &ids, Pass pass, int prec) {
   PrecScope tag(b.ctx, prec);
   if (ids.empty()) return 0;
+  if (prec == INLA_PREC_BF16) return run_pass_body(b, ids, pass, prec);
+  return b.ctx.pass_graph(INLA_K_TRAIL, pass_key(b, ids, pass, prec),
+                          [&]() -> int { return run_pass_body(b, ids, pass, prec); });
+}
+
+static int run_pass_body(Batch &b, const std::vector<int> &ids, Pass pass, int prec) {
   ThetaDesc *d = upload_td(b, ids);
   if (!d) return INLA_ERR_NOMEM;
   const int B = (int)ids.size();
@@ -575,25 +745,29 @@ static int refine(Batch &b, const std::vector<int> &ids, int prec, int max_ir, d
   std::vector<double> d1(b.plans.size(), 0.0);
   const double esz = prec != INLA_PREC_FP64 ? 4.0 : 8.0;
   for (int s = 1; s <= max_ir && !act.empty(); ++s) {
-    ThetaDesc *d = upload_td(b, act);
-    if (!d) return INLA_ERR_NOMEM;
-    const int B = (int)act.size();
-    double rb = 0, tb = 0;
-    for (int i : act) {
-      const ThetaDesc &t = b.plans[i].t;
-      rb += 8.0 * 0.5 * (double)t.n * (t.n + 1.0);   // the lower triangle of Q_prior
-      tb += esz * (double)t.n * t.n;
-    }
-    const int npm = max_over(b, act, &ThetaDesc::n_pad), kpm = max_over(b, act, &ThetaDesc::k_pad);
-    launch_kkt_residual(b.ctx, d, B, npm, kpm, rb);
-    launch_trsv_fwd(b.ctx, b.last_td, npm, V_Z, V_U, 0.5 * tb, prec);
-    launch_ir_correct(b.ctx, d, B, kpm, prec);
-    launch_rhs(b.ctx, d, B, npm, 1, prec);
-    launch_trsv_bwd(b.ctx, b.last_td, npm, V_R, V_U, 0.5 * tb, prec);
-    launch_ir_update(b.ctx, d, B);
+    // one refinement step of every theta in `act` (one hipGraph per shape)
+    int rc = b.ctx.pass_graph(INLA_K_SOLVE, pass_key(b, act, 0x4952, prec), [&]() -> int {
+      ThetaDesc *d = upload_td(b, act);
+      if (!d) return INLA_ERR_NOMEM;
+      const int B = (int)act.size();
+      double rb = 0, tb = 0;
+      for (int i : act) {
+        const ThetaDesc &t = b.plans[i].t;
+        rb += 8.0 * 0.5 * (double)t.n * (t.n + 1.0);   // the lower triangle of Q_prior
+        tb += esz * (double)t.n * t.n;
+      }
+      const int npm = max_over(b, act, &ThetaDesc::n_pad), kpm = max_over(b, act, &ThetaDesc::k_pad);
+      launch_kkt_residual(b.ctx, d, B, npm, kpm, rb);
+      launch_trsv_fwd(b.ctx, b.last_td, npm, V_Z, V_U, 0.5 * tb, prec);
+      launch_ir_correct(b.ctx, d, B, kpm, prec);
+      launch_rhs(b.ctx, d, B, npm, 1, prec);
+      launch_trsv_bwd(b.ctx, b.last_td, npm, V_R, V_U, 0.5 * tb, prec);
+      launch_ir_update(b.ctx, d, B);
+      return b.ctx.check();
+    });
+    if (rc) return rc;
     for (int i : act) steps[i] += 1;
     {
-      int rc;
       if ((rc = readback(b))) return rc;
       std::vector<int> next;
       for (int i : act) {
@@ -1441,6 +1615,20 @@ int inla_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays) {
   return INLA_OK;
 }
 
+int inla_set_pass_graphs(inla_handle *h, int32_t enable) {
+  if (!h) return -1;
+  h->ctx.pass_graphs = enable != 0;
+  if (!enable) h->ctx.drop_graphs();
+  return INLA_OK;
+}
+
+int inla_pass_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays) {
+  if (!h) return -1;
+  if (captured) *captured = h->ctx.pass_captured;
+  if (replays) *replays = h->ctx.pass_replayed;
+  return INLA_OK;
+}
+
 int inla_autotune(inla_handle *h, int32_t B, const int32_t *n, const int32_t *kb, int32_t prec, int32_t reps,
                   int32_t *config, double *ms, int32_t *n_cand) {
   if (!h) return -1;
@@ -1468,11 +1656,13 @@ int inla_tune_set(inla_handle *h, int32_t prec, int32_t n_max, int32_t B, const 
   const std::vector<int64_t> key = tune_key(prec, round_up(n_max, PADN), B);
   if (!config) {
     h->ctx.tune.erase(key);
+    ++h->ctx.tune_epoch;
     return INLA_OK;
   }
   const TuneCfg c{config[0], config[1], config[2]};
   if (!tune_valid(prec, c)) return -5;
   h->ctx.tune[key] = c;
+  ++h->ctx.tune_epoch;
   return INLA_OK;
 }
 

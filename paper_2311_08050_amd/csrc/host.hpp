@@ -61,6 +61,40 @@ struct Ctx {
   uint64_t graph_clock = 0;
   int64_t graphs_captured = 0, graphs_replayed = 0;
   int sticky = 0;   // first failure of a sequence() whose caller has no return path; reported by check()
+  // Whole-pass graphs (see pass_graph()).  While a pass is collected or
+  // captured, upload() hands out consecutive slots of the pass graph's device
+  // argument block and appends the bytes to `pg.host`; sequence() does the
+  // same with its argument block and runs its body in place; launch() records
+  // the launch in `pg.sig` and, when collecting, enqueues nothing.
+  bool pass_graphs = true;
+  enum { PG_OFF = 0, PG_COLLECT = 1, PG_CAPTURE = 2 };
+  int pg_mode = PG_OFF;
+  struct PassRec {
+    char *dbase = nullptr;        // the pass graph's device argument block
+    size_t cap = 0;               // its capacity
+    bool overflow = false;        // an upload did not fit
+    std::vector<char> host;       // argument bytes in upload order
+    std::vector<int64_t> sig;     // launch classes and work, upload sizes, sequence keys
+    double flops = 0, bytes = 0;
+  } pg;
+  struct PassGraph {
+    hipGraphExec_t exec = nullptr;
+    char *dargs = nullptr;
+    size_t cap = 0;
+    std::vector<char> last;       // argument bytes last copied into dargs
+    std::vector<int64_t> sig;
+    double flops = 0, bytes = 0;
+    uint64_t used = 0;
+  };
+  std::map<std::vector<int64_t>, PassGraph> pass_cache;
+  int64_t pass_captured = 0, pass_replayed = 0;
+  // Enqueue `body` (which enqueues one pass's launches and uploads, and
+  // reads nothing back) as one hipGraph per distinct `key` (plus the stream
+  // lane).  Graphs on, profiling off and no capture in progress; otherwise, or
+  // when the pass's launch signature differs from the captured one, or its
+  // arguments outgrow the block, `body` runs directly.  Profiling times a
+  // replay as one launch of class `cls`.
+  int pass_graph(int cls, const std::vector<int64_t> &key, const std::function<int()> &body);
   // lookahead in the blocked Cholesky: a second stream of the handle (default
   // priority) runs the bulk of each trailing update while the caller's stream
   // factors the next panel (used where the tuned configuration asks for it and
@@ -90,6 +124,7 @@ struct Ctx {
   char *pbf_reserve(size_t bytes);
   // autotuned (panel width, trailing tile) per (precision, padded order, batch bucket)
   std::map<std::vector<int64_t>, TuneCfg> tune;
+  uint64_t tune_epoch = 0;   // counts changes of `tune` (pass graph keys carry it)
 
   // Copy a small host array to device memory through the ring; returns the device
   // pointer (valid for work enqueued after this call on `stream`).
@@ -109,7 +144,7 @@ struct Ctx {
                const std::function<void(const void *dargs)> &body);
   int sequence_impl(int cls, const std::vector<int64_t> &key, const void *args, size_t nbytes,
                     const std::function<void(const void *dargs)> &body);
-  void drop_graphs();
+  void drop_graphs();   // also drops the pass graphs
   // Grow the workspace to at least `bytes`.  Returns false on allocation failure.
   bool reserve(size_t bytes);
   // Launch through a wrapper that records events when profiling.

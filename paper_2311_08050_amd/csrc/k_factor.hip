@@ -1025,7 +1025,9 @@ static int factor_batch_t(Ctx &ctx, const std::vector<HostFactor> &fs, int nb, i
   // of the following panel waits for TRAIL_B, which updated its columns too.
   // (lookahead runs on the caller's lane only: the side stream and its events
   // serve one factorisation at a time)
-  const bool look = look_cfg && ctx.lookahead && ctx.lane == 0 && nf_max > nb && ctx.side_ready() == INLA_OK;
+  // (and not inside a pass graph, which is captured on one stream)
+  const bool look = look_cfg && ctx.lookahead && ctx.lane == 0 && ctx.pg_mode == Ctx::PG_OFF && nf_max > nb &&
+                    ctx.side_ready() == INLA_OK;
   int rc = 0;
   hipStream_t main_stream = ctx.stream;
   for (int p0 = 0; p0 < nf_max && !rc; p0 += nb) {
@@ -1189,6 +1191,7 @@ int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, T
   (void)hipEventDestroy(b);
   if (rc) return rc;
   ctx.tune[tune_key(prec, nf_max, B)] = cand[best];
+  ++ctx.tune_epoch;
   if (best_out) *best_out = cand[best];
   if (n_cand) *n_cand = (int)cand.size();
   return ctx.check();

@@ -106,8 +106,8 @@ __global__ __launch_bounds__(256) void jacobi_init_kernel(const JacDesc *__restr
 // Inner eigenproblem of one block pair: the JP x JP principal submatrix S of A
 // on the pair's indices is reduced in LDS by cyclic Jacobi (round-robin over
 // its JP indices, rotations accumulated from the identity, so R stays close to
-// I, which the outer iteration's convergence needs): at most JAC_INNER_SWEEPS
-// sweeps, fewer once its off-diagonal part is at the rounding level.  Writes R
+// I, which the outer iteration's convergence needs): JAC_INNER_SWEEPS sweeps,
+// none once its off-diagonal part is at the rounding level.  Writes R
 // (column-major).  Grid (nbk / 2 pairs, B).
 __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__restrict__ jd, int r) {
   const JacDesc J = jd[blockIdx.y];
@@ -129,7 +129,6 @@ __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__r
   }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
-  double prev = -1.0;
   for (int sw = 0; sw < JAC_INNER_SWEEPS; ++sw) {
     double off = 0.0, fro = 0.0;
     for (int e = tid; e < JP * JP; e += 256) {
@@ -140,11 +139,8 @@ __global__ __launch_bounds__(256) void jacobi_pair_eig_kernel(const JacDesc *__r
     }
     off = block_sum256(off, sh);
     fro = block_sum256(fro, sh);
-    // converged, or settled on its rounding floor (a sweep that no longer
-    // shrinks the off-diagonal sum of squares fourfold once it is below 1e-28
-    // of the total)
-    if (off <= 16.0 * eps * eps * fro || (prev >= 0.0 && off <= 1e-28 * fro && off > 0.25 * prev)) break;
-    prev = off;
+    // already diagonal to the rounding level: no rotation
+    if (off <= 16.0 * eps * eps * fro) break;
     for (int ri = 0; ri < JP - 1; ++ri) {
       if (tid < JP / 2) {
         const int p = rr_pos(tid, ri, JP), q = rr_pos(JP - 1 - tid, ri, JP);
@@ -466,7 +462,12 @@ static int pinv_batch(Ctx &ctx, int B, const int *n, const double *const *Q, con
   for (int b = 0; b < B; ++b) { act[b] = b; sweeps[b] = 0; info[b] = INLA_INFO_OK; }
   std::vector<double> prev(B, std::numeric_limits<double>::infinity());
   std::vector<double> hn(4 * (size_t)B);
-  int r = 0;   // global round counter: every matrix takes its rounds in order (r mod (nbk - 1))
+  // Global round counter: every matrix takes its own rounds in order (r mod
+  // (nbk - 1)).  An outer sweep is nbk - 1 rounds of the largest active matrix;
+  // a smaller one completes (nbk_max - 1) / (nbk - 1) of its own sweeps in it,
+  // and its convergence is checked, and its sweeps counted, at the outer sweep
+  // boundaries.
+  int r = 0;
   for (int sw = 0; sw < JAC_MAX_SWEEPS && !act.empty(); ++sw) {
     std::vector<JacDesc> ha;
     int ne_act = 0;

@@ -282,3 +282,52 @@ def test_concurrent_prior_pass_matches_in_order(prec):
     r0, _ = inorder.constrained_mode(dms, thetas, prec=prec)
     assert [r["info"] for r in r1] == [r["info"] for r in r0]
     assert [r["iters"] for r in r1] == [r["iters"] for r in r0]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("overlap", [False, True])
+def test_pass_graphs_match_direct_launches(prec, overlap):
+    """Whole-pass graphs (each Newton pass and each refinement step one
+    hipGraph): four evaluations in a row, with torch's own device work and
+    synchronisations between them, give the bits of a handle that launches
+    every kernel directly; the passes are captured and then replayed (on both
+    stream lanes with the concurrent prior pass), also for a batch of other
+    theta with the same sizes, whose arguments differ."""
+    import torch
+
+    from paper_2311_08050_amd import binding
+    models, thetas = uneven_case()
+    dms = dev_models(models)
+    eager = binding.Library()
+    eager.set_graphs(False)
+    eager.set_overlap(overlap)
+    g = binding.Library()
+    g.set_overlap(overlap)
+    other = thetas + np.array([0.05, -0.05, 0.1, 0.0])
+    ref, xref = eager.laplace_eval(dms, thetas, prec=prec)
+    ref2, xref2 = eager.laplace_eval(dms, other, prec=prec)
+    scratch = torch.randn(512, 512, device="cuda", dtype=torch.float64)
+    for rep in range(4):
+        say(f"pass graphs {prec} overlap={overlap}: evaluation {rep}")
+        th, r0, x0 = (thetas, ref, xref) if rep != 2 else (other, ref2, xref2)
+        res, xs = g.laplace_eval(dms, th, prec=prec)
+        scratch = scratch @ scratch.T / 512.0   # the program's own work between replays
+        torch.cuda.synchronize()
+        for b in range(len(models)):
+            for key in KEYS:
+                assert res[b][key] == r0[b][key], (prec, rep, b, key, res[b][key], r0[b][key])
+            assert torch.equal(xs[b], x0[b]), (prec, rep, b)
+    st = g.pass_graph_stats()
+    say(f"pass graphs {prec} overlap={overlap}: {st}")
+    assert st["captured"] > 0 and st["replays"] > st["captured"], st
+    assert eager.pass_graph_stats() == {"captured": 0, "replays": 0}
+    # constrained_mode runs the same passes
+    m1, _ = g.constrained_mode(dms, thetas, prec=prec)
+    m0, _ = eager.constrained_mode(dms, thetas, prec=prec)
+    assert [r["iters"] for r in m1] == [r["iters"] for r in m0]
+    assert [r["info"] for r in m1] == [r["info"] for r in m0]
+    # turning them off releases them; results unchanged
+    g.set_pass_graphs(False)
+    res, xs = g.laplace_eval(dms, thetas, prec=prec)
+    for b in range(len(models)):
+        assert res[b]["objective"] == ref[b]["objective"] and torch.equal(xs[b], xref[b]), b
