@@ -44,18 +44,20 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 // --------------------------------------------------------------------------
 // Diagonal block: Cholesky of the 64 x 64 block A_jj and its inverse in one
-// LDS-resident FP64 pass.  The block is bordered below by the 64 x 64 identity,
-// so the same sub-panel steps that produce L_jj turn the border into
-// I L_jj^{-T} = L_jj^{-T}, whose transpose is the inverse used by the MFMA TRSM.
-// Sub-panels of width 16: an unblocked 16 x 16 Cholesky held in registers of
-// wave 0 (lane r owns row r, pivots and columns broadcast with readlane), a
-// forward-substitution TRSM of the rows below (one thread per row, reciprocal
-// pivots), and the rank-16 update of the rest (row in registers, column values
-// broadcast from LDS).  12 barriers in all.
+// LDS-resident FP64 pass of 34 KB: L_jj overwrites the lower triangle and
+// X = L_jj^{-1} (lower triangular) is built in the strict upper triangle,
+// transposed, with its diagonal 1 / L_cc kept apart.
+// Cholesky by sub-panels of width 16: an unblocked 16 x 16 Cholesky held in
+// registers of wave 0 (lane r owns row r, pivots and columns broadcast with
+// readlane), a forward-substitution TRSM of the rows below (one thread per
+// row, reciprocal pivots), and the rank-16 update of the rest (row in
+// registers, column values broadcast from LDS).  Inverse by 16 x 16 blocks:
+// X_ii = L_ii^{-1} (one wave per block, one lane per column), then
+// X_ij = -X_ii (L_ij X_jj + ... + L_i,i-1 X_i-1,j) by distance i - j.
 // --------------------------------------------------------------------------
 struct Potf2Lds {
-  double M[2 * NBI][NBI + 1];
-  double rd[NBI];   // reciprocal pivots 1 / L_cc
+  double M[NBI][NBI + 1];   // lower: the block, then L; strict upper: X[a][b] at M[b][a] (a > b)
+  double rd[NBI];           // reciprocal pivots 1 / L_cc = X[c][c]
   int fail;
 };
 
@@ -66,19 +68,23 @@ __device__ __forceinline__ double lane_bcast(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-// S.M rows [0, 64) hold the block's lower triangle (zero above), rows [64, 128)
-// the identity, S.fail = 0; all of it visible to the block.  On return S.M
-// holds L_jj below and L_jj^{-T} in the border, S.fail the first failing pivot
-// (1-based) or 0.
+// X = L^{-1} element (a, b), a >= b, from its packed place.
+__device__ __forceinline__ double xinv(const Potf2Lds &S, int a, int b) {
+  return a == b ? S.rd[a] : S.M[b][a];
+}
+
+// S.M's lower triangle holds the block (upper triangle ignored), S.fail = 0;
+// all of it visible to the block.  On return the lower triangle holds L_jj,
+// S.rd its reciprocal pivots, S.fail the first failing pivot (1-based) or 0.
 __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
-  constexpr int W = 16, M2 = 2 * NBI;
+  constexpr int W = 16;
   for (int jb = 0; jb < NBI; jb += W) {
     // 1. 16 x 16 diagonal Cholesky in wave 0
     if (tid < 64) {
       const int r = tid & (W - 1);
       double a[W];
 #pragma unroll
-      for (int cc = 0; cc < W; ++cc) a[cc] = S.M[jb + r][jb + cc];
+      for (int cc = 0; cc < W; ++cc) a[cc] = cc <= r ? S.M[jb + r][jb + cc] : 0.0;
       int bad = 0;
 #pragma unroll
       for (int c = 0; c < W; ++c) {
@@ -102,8 +108,8 @@ __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
       if (tid == 0 && bad != 0 && S.fail == 0) S.fail = bad;
     }
     __syncthreads();
-    // 2. TRSM of every row below the sub-panel (block rows and border rows)
-    const int R = M2 - (jb + W);
+    // 2. TRSM of the block rows below the sub-panel
+    const int R = NBI - (jb + W);
     if (tid < R) {
       const int r = jb + W + tid;
       double x[W];
@@ -120,9 +126,8 @@ __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
       for (int c = 0; c < W; ++c) S.M[r][jb + c] = x[c];
     }
     __syncthreads();
-    // 3. rank-16 update of columns [jb + 16, 64) for the rows below
-    const int Cn = NBI - (jb + W);
-    if (Cn > 0) {
+    // 3. rank-16 update of the lower triangle of columns [jb + 16, 64)
+    if (R > 0) {
       const int nsplit = 256 / R;
       const int rr = tid % R, part = tid / R;
       if (part < nsplit) {
@@ -130,11 +135,10 @@ __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
         double p[W];
 #pragma unroll
         for (int m = 0; m < W; ++m) p[m] = S.M[r][jb + m];
-        const int per = (Cn + nsplit - 1) / nsplit;
+        const int per = (R + nsplit - 1) / nsplit;
         const int cb = jb + W + part * per;
-        const int ce = min(cb + per, NBI);
+        const int ce = min(cb + per, r + 1);
         for (int c = cb; c < ce; ++c) {
-          if (r < NBI && c > r) break;
           double s = S.M[r][c];
 #pragma unroll
           for (int m = 0; m < W; ++m) s -= p[m] * S.M[c][jb + m];
@@ -142,6 +146,60 @@ __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
         }
       }
     }
+    __syncthreads();
+  }
+}
+
+// X = L^{-1} into the strict upper triangle (transposed) after potf2_factor.
+__device__ __forceinline__ void potf2_invert(Potf2Lds &S, int tid) {
+  constexpr int W = 16;
+  // X_ii: wave i, lane c < 16 solves L_ii x = e_c by forward substitution
+  {
+    const int o = W * (tid >> 6), c = tid & 63;
+    if (c < W) {
+      double x[W];
+#pragma unroll
+      for (int r = 0; r < W; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int m = 0; m < r; ++m) s += S.M[o + r][o + m] * x[m];
+        x[r] = r < c ? 0.0 : (r == c ? S.rd[o + r] : -S.rd[o + r] * s);
+      }
+#pragma unroll
+      for (int r = 1; r < W; ++r)
+        if (r > c) S.M[o + c][o + r] = x[r];
+    }
+  }
+  __syncthreads();
+  // X_ij (i > j) by distance: T = sum_{k=j}^{i-1} L_ik X_kj, then X_ij = -X_ii T;
+  // thread (r, c) = (tid / 16, tid % 16) of each block at that distance
+  const int r = tid >> 4, c = tid & 15;
+#pragma unroll
+  for (int dist = 1; dist < NBI / W; ++dist) {
+    const int nblk = NBI / W - dist;
+    double t[NBI / W - 1];
+#pragma unroll
+    for (int q = 0; q < nblk; ++q) {
+      const int i = q + dist, j = q, ar = W * i + r, bc = W * j + c;
+      double s = 0.0;
+      for (int k = j; k < i; ++k)
+        for (int m = (k == j ? c : 0); m < W; ++m) s += S.M[ar][W * k + m] * xinv(S, W * k + m, bc);
+      t[q] = s;
+    }
+    // T goes to X_ij's place, so that every thread can read all of it
+#pragma unroll
+    for (int q = 0; q < nblk; ++q) S.M[W * q + c][W * (q + dist) + r] = t[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < nblk; ++q) {
+      const int i = q + dist, j = q;
+      double s = 0.0;
+      for (int m = 0; m <= r; ++m) s += xinv(S, W * i + r, W * i + m) * S.M[W * j + c][W * i + m];
+      t[q] = -s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < nblk; ++q) S.M[W * q + c][W * (q + dist) + r] = t[q];
     __syncthreads();
   }
 }
@@ -156,7 +214,7 @@ __device__ __forceinline__ void potf2_store(const Potf2Lds &S, const FactorDesc 
   for (int i = 0; i < NBI * NBI / 256; ++i) {
     const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
     if (r >= c) Ad[(size_t)c * d.ld + r] = (T)S.M[r][c];
-    Li[c * NBI + r] = (T)S.M[NBI + c][r];   // (L^{-1})[r][c] = (L^{-T})[c][r]
+    Li[c * NBI + r] = (T)(r >= c ? xinv(S, r, c) : 0.0);   // column-major (L^{-1})[r][c]
   }
   if (tid == 0 && S.fail != 0 && *d.info == 0) *d.info = j + S.fail;
 }
@@ -179,11 +237,11 @@ __global__ __launch_bounds__(256) void potf2_inv_kernel(const FactorDesc *__rest
   for (int i = 0; i < NBI * NBI / 256; ++i) {
     const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
     S.M[r][c] = (r >= c) ? (double)v[i] : 0.0;
-    S.M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
   }
   if (tid == 0) S.fail = 0;
   __syncthreads();
   potf2_factor(S, tid);
+  potf2_invert(S, tid);
   potf2_store<T>(S, d, j, Ad, tid);
 }
 
@@ -440,15 +498,17 @@ __global__ __launch_bounds__(256, 2) void trail_update_kernel(const FactorDesc *
 // one 64-row tile I (rows r0 = j + 64 (t + 1) .. r0 + 63) per workgroup:
 //   C      = A[I, j] - A[I, p0:j] A[j, p0:j]^T     (the panel's earlier columns,
 //                                                  MFMA from global via LDS)
-//   L[I,j] = C L_jj^{-T}                           (MFMA, both operands in LDS)
+//   L[I,j] = C L_jj^{-T}                           (MFMA, C from registers and
+//                                                  L_jj^{-1} staged in 16-deep chunks)
 //   A[I,I] -= L[I,j] L[I,j]^T                      (tiles with r0 < pend: the
 //                                                  diagonal block's update)
 // The tile just below the diagonal block (t = 0) then holds the next diagonal
-// block fully updated and factors it (potf2_factor) in the same launch, so a
-// panel takes one potf2_inv launch and one launch per block column.  Each tile
-// reads its own rows of the panel's earlier columns and writes one 64 x 64
-// block, in place of the right-looking rank-64 updates that read and wrote
-// the panel's whole trailing part once per block column.
+// block fully updated and factors and inverts it (potf2_factor, potf2_invert)
+// in the same launch, so a panel takes one potf2_inv launch and one launch per
+// block column.  Each tile reads its own rows of the panel's earlier columns
+// and writes one 64 x 64 block, in place of the right-looking rank-64 updates
+// that read and wrote the panel's whole trailing part once per block column.
+// Every phase fits in about 34 KB of LDS, so four workgroups share a CU.
 //
 // Identity border rows (rows id_row0 + s hold e_s) are zero left of column s,
 // so a tile of them starts its K range at r0 - id_row0 and is skipped when
@@ -460,21 +520,24 @@ __global__ __launch_bounds__(256, 2) void trail_update_kernel(const FactorDesc *
 // --------------------------------------------------------------------------
 template <typename T>
 struct PanelLds {
-  static constexpr int LDC = NBI + 4;   // LDS row length (elements): conflict-free MFMA operand reads
+  static constexpr int LDC = NBI + 4;          // LDS row length (elements): conflict-free MFMA operand reads
+  static constexpr int PKC = sizeof(T) == 4 ? 32 : 16;   // K chunk of the left-looking product
   union {
-    struct { T As[2][KC][LDC]; T Bs[2][KC][LDC]; } g;   // K chunks of the left-looking product
-    struct { T Cs[NBI][LDC]; T Xs[NBI][LDC]; } s;       // TRSM / SYRK operands, [k][row]
-    Potf2Lds f;                                         // the next diagonal block's factorisation
+    struct { T As[2][PKC][LDC]; T Bs[2][PKC][LDC]; } g;   // K chunks ([k][row]); chunk 0 also stages
+                                                           // the TRSM and SYRK operands
+    Potf2Lds f;                                            // the next diagonal block's factorisation
   };
 };
 
 template <typename T>
-__global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__restrict__ descs, int p0, int nb,
+__global__ __launch_bounds__(256, 4) void panel_step_kernel(const FactorDesc *__restrict__ descs, int p0, int nb,
                                                             int j, int act, int gx, int Q) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int VEC = 16 / sizeof(T);
+  constexpr int LDC = PanelLds<T>::LDC, PKC = PanelLds<T>::PKC;
   constexpr int WTM = 32, WTN = 32, BM = 2, BN = 2;   // 2 x 2 waves, 32 x 32 wave tiles
-  constexpr int LA = KC * NBI / VEC / 256;            // 16-byte loads per thread per operand chunk
+  constexpr int LA = PKC * NBI / VEC / 256;           // 16-byte loads per thread per operand chunk
+  constexpr int LX = KC * NBI / VEC / 256;            // ... per 16-deep chunk of L_jj^{-1}
   typedef T vec_t __attribute__((ext_vector_type(VEC)));
   typedef __attribute__((address_space(1))) T gT;
   typedef __attribute__((address_space(1))) const vec_t gcvec;
@@ -510,15 +573,14 @@ __global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__
   // tile element (rl(a, v), cl(b, v)) of accumulator component v
   auto rl = [&](int a, int v) { return wm * WTM + a * 16 + (F64 ? li : 4 * g + v); };
   auto cl = [&](int b, int v) { return wn * WTN + b * 16 + (F64 ? g + 4 * v : li); };
-  acc_t acc[BM][BN];
-  auto zero = [&] {
+  auto zero = [&](acc_t (&c)[BM][BN]) {
 #pragma unroll
     for (int a = 0; a < BM; ++a)
 #pragma unroll
-      for (int b = 0; b < BN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+      for (int b = 0; b < BN; ++b) c[a][b] = acc_t{0, 0, 0, 0};
   };
-  // acc += X(64 x 16) Y(64 x 16)^T for one 16-deep chunk held [k][row] in LDS
-  auto mfma_chunk = [&](const T (*X)[PanelLds<T>::LDC], const T (*Y)[PanelLds<T>::LDC], int k0) {
+  // c += X(64 x 16) Y(64 x 16)^T for one 16-deep chunk held [k][row] in LDS
+  auto mfma_chunk = [&](acc_t (&c)[BM][BN], const T (*X)[LDC], const T (*Y)[LDC], int k0) {
 #pragma unroll
     for (int s = 0; s < KC / 4; ++s) {
       const int kk = k0 + 4 * g + s;
@@ -531,14 +593,27 @@ __global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__
       for (int a = 0; a < BM; ++a)
 #pragma unroll
         for (int b = 0; b < BN; ++b) {
-          if constexpr (F64) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], acc[a][b], 0, 0, 0);
-          else acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[a], xb[b], acc[a][b], 0, 0, 0);
+          if constexpr (F64) c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(xb[b], ya[a], c[a][b], 0, 0, 0);
+          else c[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[a], xb[b], c[a][b], 0, 0, 0);
         }
     }
   };
+  // columns [k0, k0 + 16) of the tile held in accumulator layout, into LDS as [k][row]
+  auto stage_cols = [&](const acc_t (&c)[BM][BN], T (*dst)[LDC], int k0) {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = cl(b, v) - k0;
+          if (col >= 0 && col < KC) dst[col][rl(a, v)] = c[a][b][v];
+        }
+  };
 
-  // 1. acc = A[I, ks:j] A[j, ks:j]^T, double-buffered 16-deep chunks
-  zero();
+  // 1. acc = A[I, ks:j] A[j, ks:j]^T, double-buffered PKC-deep chunks
+  acc_t acc[BM][BN];
+  zero(acc);
   if (K > 0) {
     const __attribute__((address_space(1))) T *Ag = gptr((const T *)d.A) + (size_t)ks * ld + r0;
     const __attribute__((address_space(1))) T *Bg = gptr((const T *)d.A) + (size_t)ks * ld + j;
@@ -563,67 +638,63 @@ __global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__
     lstore(0);
     __syncthreads();
     int buf = 0;
-    for (int kc = 0; kc < K; kc += KC) {
-      const bool more = kc + KC < K;
-      if (more) gload(kc + KC);
-      mfma_chunk(S.g.As[buf], S.g.Bs[buf], 0);
+    for (int kc = 0; kc < K; kc += PKC) {   // K is a multiple of 64
+      const bool more = kc + PKC < K;
+      if (more) gload(kc + PKC);
+#pragma unroll
+      for (int k0 = 0; k0 < PKC; k0 += KC) mfma_chunk(acc, S.g.As[buf], S.g.Bs[buf], k0);
       if (more) lstore(buf ^ 1);
       __syncthreads();
       buf ^= 1;
     }
   }
 
-  // 2. C = A[I, j] - acc into LDS as the TRSM's left operand (k = column of
-  //    block j), and L_jj^{-1} (column-major: X[n][k] at k * 64 + n) as its right
+  // 2. C = A[I, j] - acc (in acc), then L[I, j] = C L_jj^{-T} into lacc over
+  //    16-deep chunks of k (columns of block j): C's columns and rows of
+  //    L_jj^{-1} (column-major: X[n][k] at k * 64 + n) staged in LDS chunk 0
   gT *Cg = gptr((T *)d.A) + (size_t)j * ld + r0;
-  {
-    const __attribute__((address_space(1))) T *Li = gptr((const T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
-    vec_t xv[NBI * NBI / VEC / 256];
-#pragma unroll
-    for (int it = 0; it < NBI * NBI / VEC / 256; ++it) {
-      const int lin = it * 256 + tid;
-      xv[it] = *reinterpret_cast<gcvec *>(Li + (size_t)VEC * lin);
-    }
-#pragma unroll
-    for (int a = 0; a < BM; ++a)
-#pragma unroll
-      for (int b = 0; b < BN; ++b)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int r = rl(a, v), c = cl(b, v);
-          S.s.Cs[c][r] = Cg[(size_t)c * ld + r] - acc[a][b][v];
-        }
-#pragma unroll
-    for (int it = 0; it < NBI * NBI / VEC / 256; ++it) {
-      const int lin = it * 256 + tid, kk = lin / (NBI / VEC), rp = lin % (NBI / VEC);
-      *reinterpret_cast<vec_t *>(&S.s.Xs[kk][VEC * rp]) = xv[it];
-    }
-  }
-  __syncthreads();
-  // 3. L[I, j] = C L_jj^{-T}
-  zero();
-#pragma unroll
-  for (int k0 = 0; k0 < NBI; k0 += KC) mfma_chunk(S.s.Cs, S.s.Xs, k0);
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
     for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) Cg[(size_t)cl(b, v) * ld + rl(a, v)] = acc[a][b][v];
+      for (int v = 0; v < 4; ++v) acc[a][b][v] = Cg[cl(b, v) * ld + rl(a, v)] - acc[a][b][v];
+  const __attribute__((address_space(1))) T *Li = gptr((const T *)d.linv) + (size_t)(j / NBI) * NBI * NBI;
+  acc_t lacc[BM][BN];
+  zero(lacc);
+#pragma unroll
+  for (int k0 = 0; k0 < NBI; k0 += KC) {
+    vec_t xv[LX];
+#pragma unroll
+    for (int it = 0; it < LX; ++it)
+      xv[it] = *reinterpret_cast<gcvec *>(Li + (size_t)k0 * NBI + (size_t)VEC * (it * 256 + tid));
+    stage_cols(acc, S.g.As[0], k0);
+#pragma unroll
+    for (int it = 0; it < LX; ++it) {
+      const int lin = it * 256 + tid, kk = lin / (NBI / VEC), rp = lin % (NBI / VEC);
+      *reinterpret_cast<vec_t *>(&S.g.Bs[0][kk][VEC * rp]) = xv[it];
+    }
+    __syncthreads();
+    mfma_chunk(lacc, S.g.As[0], S.g.Bs[0], 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cg[cl(b, v) * ld + rl(a, v)] = lacc[a][b][v];
   if (r0 >= pend) return;
 
-  // 4. diagonal block of the tile's rows: A[I, I] -= L[I, j] L[I, j]^T
-  __syncthreads();   // every wave is done reading Cs
+  // 3. diagonal block of the tile's rows: D = L[I, j] L[I, j]^T (into acc)
+  zero(acc);
 #pragma unroll
-  for (int a = 0; a < BM; ++a)
-#pragma unroll
-    for (int b = 0; b < BN; ++b)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) S.s.Cs[cl(b, v)][rl(a, v)] = acc[a][b][v];
-  __syncthreads();
-  zero();
-#pragma unroll
-  for (int k0 = 0; k0 < NBI; k0 += KC) mfma_chunk(S.s.Cs, S.s.Cs, k0);
+  for (int k0 = 0; k0 < NBI; k0 += KC) {
+    stage_cols(lacc, S.g.As[0], k0);
+    __syncthreads();
+    mfma_chunk(acc, S.g.As[0], S.g.As[0], 0);
+    __syncthreads();
+  }
   gT *Dg = gptr((T *)d.A) + (size_t)r0 * ld + r0;
   if (t != 0) {
 #pragma unroll
@@ -633,14 +704,13 @@ __global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = rl(a, v), c = cl(b, v);
-          if (r >= c) Dg[(size_t)c * ld + r] = Dg[(size_t)c * ld + r] - acc[a][b][v];
+          if (r >= c) Dg[c * ld + r] = Dg[c * ld + r] - acc[a][b][v];
         }
     return;
   }
 
-  // 5. tile 0: the block at r0 = j + 64 has had every update of the panel's
-  //    earlier columns; factor it in LDS and store L and its inverse
-  __syncthreads();   // every wave is done reading Cs before Potf2Lds reuses it
+  // 4. tile 0: the block at r0 = j + 64 has had every update of the panel's
+  //    earlier columns; factor and invert it in LDS, store L and its inverse
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
@@ -648,16 +718,12 @@ __global__ __launch_bounds__(256, 2) void panel_step_kernel(const FactorDesc *__
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int r = rl(a, v), c = cl(b, v);
-        S.f.M[r][c] = (r >= c) ? (double)(T)(Dg[(size_t)c * ld + r] - acc[a][b][v]) : 0.0;
+        S.f.M[r][c] = (r >= c) ? (double)(T)(Dg[c * ld + r] - acc[a][b][v]) : 0.0;
       }
-#pragma unroll
-  for (int i = 0; i < NBI * NBI / 256; ++i) {
-    const int e = tid + 256 * i, r = e & (NBI - 1), c = e >> 6;
-    S.f.M[NBI + r][c] = (r == c) ? 1.0 : 0.0;
-  }
   if (tid == 0) S.f.fail = 0;
   __syncthreads();
   potf2_factor(S.f, tid);
+  potf2_invert(S.f, tid);
   potf2_store<T>(S.f, d, r0, Dg, tid);
 }
 
