@@ -73,6 +73,23 @@ __device__ __forceinline__ double xinv(const Potf2Lds &S, int a, int b) {
   return a == b ? S.rd[a] : S.M[b][a];
 }
 
+// sqrt(x) and 1 / sqrt(x) for x > 0 by Goldschmidt's coupled iteration
+// (g -> sqrt(x), h -> 1 / (2 sqrt(x)), each step squaring the relative error
+// r = 1/2 - g h) from the hardware reciprocal square root estimate; two steps
+// take the estimate's error below the FP64 rounding level.
+__device__ __forceinline__ void sqrt_rsqrt(double x, double &sq, double &rs) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+  }
+  sq = g;
+  rs = 2.0 * h;
+}
+
 // S.M's lower triangle holds the block (upper triangle ignored), S.fail = 0;
 // all of it visible to the block.  On return the lower triangle holds L_jj,
 // S.rd its reciprocal pivots, S.fail the first failing pivot (1-based) or 0.
@@ -93,7 +110,8 @@ __device__ __forceinline__ void potf2_factor(Potf2Lds &S, int tid) {
           if (bad == 0) bad = jb + c + 1;
           dcc = __builtin_nan("");
         }
-        const double sd = sqrt(dcc), rs = 1.0 / sd;
+        double sd, rs;
+        sqrt_rsqrt(dcc, sd, rs);
         const double l = (r == c) ? sd : a[c] * rs;
         a[c] = l;
         if (tid == 0) S.rd[jb + c] = rs;
