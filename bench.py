@@ -651,6 +651,9 @@ def main():
                          "(inla_set_overlap; on by default here: +3.5%% at the headline)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the separately timed marginal-variance, VB-correction and Stage-1 figures")
+    ap.add_argument("--timed-only", action="store_true",
+                    help="skip the headline's second timings (prior pass in order, unprofiled), so that the "
+                         "variants' timed regions are the last dispatches of a profiled run")
     ap.add_argument("--rocprof-window", metavar="CSV",
                     help="only summarise a rocprofv3 per-dispatch CSV over the timed region of --bench-json")
     ap.add_argument("--bench-json", metavar="FILE", help="the JSON line printed by the profiled bench run")
@@ -737,7 +740,7 @@ def main():
     head = variants[-1]
     hv = results[head]
     in_order = None
-    if not args.no_overlap:
+    if not args.no_overlap and not args.timed_only:
         # the headline variant once more with the prior pass in order: the
         # trailing kernel's own rate, which the concurrent prior pass stretches
         lib.set_overlap(False)
@@ -749,7 +752,7 @@ def main():
                     "roofline": {k: r["roofline"][k] for k in ("achieved", "peak", "unit", "frac", "launches",
                                                                "avg_launch_ms")}}
     unprofiled = None
-    if not args.no_graphs:
+    if not args.no_graphs and not args.timed_only:
         # the headline variant without per-launch events, with and without the
         # whole-pass graphs (each Newton pass and refinement step one hipGraph)
         w = max(3, args.steps // 4)
