@@ -526,7 +526,7 @@ __global__ __launch_bounds__(256, 2) void trail_update_kernel(const FactorDesc *
 // block column.  Each tile reads its own rows of the panel's earlier columns
 // and writes one 64 x 64 block, in place of the right-looking rank-64 updates
 // that read and wrote the panel's whole trailing part once per block column.
-// Every phase fits in about 34 KB of LDS, so four workgroups share a CU.
+// Every phase fits in about 34 KB of LDS, so four workgroups can share a CU.
 //
 // Identity border rows (rows id_row0 + s hold e_s) are zero left of column s,
 // so a tile of them starts its K range at r0 - id_row0 and is skipped when
@@ -547,8 +547,10 @@ struct PanelLds {
   };
 };
 
+// Four workgroups per CU in FP32; three in FP64, whose registers would
+// otherwise spill at the 128-register budget of four.
 template <typename T>
-__global__ __launch_bounds__(256, 4) void panel_step_kernel(const FactorDesc *__restrict__ descs, int p0, int nb,
+__global__ __launch_bounds__(256, sizeof(T) == 4 ? 4 : 3) void panel_step_kernel(const FactorDesc *__restrict__ descs, int p0, int nb,
                                                             int j, int act, int gx, int Q) {
   constexpr bool F64 = sizeof(T) == 8;
   constexpr int VEC = 16 / sizeof(T);
