@@ -90,17 +90,22 @@ __device__ __forceinline__ double *vsel(const ThetaDesc &t, int v) {
 
 // y = M v (trans = 0) or y = M^T v (trans = 1) for a 64 x 64 block M stored
 // column-major at Mg (element (m, c) at Mg[c * 64 + m]); v and y live in LDS.
-// The block is staged through LDS with one coalesced load per thread and
-// element, then each wave sums a quarter of the columns.  All 256 threads take
-// part; returns after a barrier.
+// block64_load reads the block with one coalesced load per thread and element
+// (so that the caller can issue it ahead of other work), block64_apply stages
+// it through LDS and each wave sums a quarter of the columns.  All 256 threads
+// take part; block64_apply returns after a barrier.
 template <typename T>
-__device__ __forceinline__ void block64_apply(const T *__restrict__ Mg, const double *v, int trans, double *y,
+__device__ __forceinline__ void block64_load(const T *__restrict__ Mg, T (&e)[16]) {
+  const auto *g = gptr(Mg);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) e[q] = g[q * 256 + threadIdx.x];
+}
+// y = M v (trans 0) or M^T v (trans 1) for the 64 x 64 column-major block whose
+// elements block64_load read into e.
+template <typename T>
+__device__ __forceinline__ void block64_apply(const T (&e)[16], const double *v, int trans, double *y,
                                               T (*sM)[65], double (*part)[64]) {
   const int tid = threadIdx.x, m = tid & 63, w = tid >> 6;
-  const auto *g = gptr(Mg);
-  T e[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) e[q] = g[q * 256 + tid];
 #pragma unroll
   for (int q = 0; q < 16; ++q) sM[(q * 256 + tid) >> 6][tid & 63] = e[q];
   __syncthreads();
@@ -137,28 +142,36 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__r
   T(*sM)[65] = reinterpret_cast<T(*)[65]>(smem);
   __shared__ double part[4][64];
   __shared__ double zb[64], rb[64], zn[64];
+  const bool next = blockIdx.x == 0 && i0 + 64 < np;   // this workgroup forms z_{b+1}
+  T e[16];
   if (i0 == 0) {
+    block64_load(linv, e);
     if (tid < 64) rb[tid] = r[tid];
     __syncthreads();
-    block64_apply(linv, rb, 0, zb, sM, part);
+    block64_apply(e, rb, 0, zb, sM, part);
     if (blockIdx.x == 0 && tid < 64) z[tid] = zb[tid];
   } else {
     if (tid < 64) zb[tid] = z[i0 + tid];
     __syncthreads();
   }
+  // the next diagonal block's inverse is read while the rows are updated
+  if (next) block64_load(linv + (size_t)(i0 / 64 + 1) * 4096, e);
   const int j = i0 + 64 + blockIdx.x * 256 + tid;
   double nv = 0.0;
   if (j < np) {
+    T lv[64];   // all 64 loads in flight before the first product
+#pragma unroll
+    for (int c = 0; c < 64; ++c) lv[c] = L[(size_t)(i0 + c) * t.ldw + j];
     double s = 0.0;
-#pragma unroll 16
-    for (int c = 0; c < 64; ++c) s += (double)L[(size_t)(i0 + c) * t.ldw + j] * zb[c];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) s += (double)lv[c] * zb[c];
     nv = r[j] - s;
     r[j] = nv;
   }
-  if (blockIdx.x == 0 && i0 + 64 < np) {
+  if (next) {
     if (tid < 64) rb[tid] = nv;
     __syncthreads();
-    block64_apply(linv + (size_t)(i0 / 64 + 1) * 4096, rb, 0, zn, sM, part);
+    block64_apply(e, rb, 0, zn, sM, part);
     if (tid < 64) z[i0 + 64 + tid] = zn[tid];
   }
 }
@@ -186,10 +199,12 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
   double(*prod)[65] = reinterpret_cast<double(*)[65]>(smem);
   __shared__ double part[4][64];
   __shared__ double xb[64], rb[64], xn[64];
+  T e[16];
   if (i0 + 64 == np) {
+    block64_load(linv + (size_t)(i0 / 64) * 4096, e);
     if (tid < 64) rb[tid] = r[i0 + tid];
     __syncthreads();
-    block64_apply(linv + (size_t)(i0 / 64) * 4096, rb, 1, xb, sM, part);
+    block64_apply(e, rb, 1, xb, sM, part);
     if (blockIdx.x == 0 && tid < 64) x[i0 + tid] = xb[tid];
   } else {
     if (tid < 64) xb[tid] = x[i0 + tid];
@@ -197,6 +212,10 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
   }
   const int g = blockIdx.x;
   if (64 * g >= i0) return;
+  // the workgroup holding the columns just above the block forms x_{b-1}:
+  // its diagonal block's inverse is read while the columns are updated
+  const bool prev = 64 * g + 64 == i0;
+  if (prev) block64_load(linv + (size_t)(i0 / 64 - 1) * 4096, e);
   const double xm = xb[lane];
   const int j0 = 64 * g + 16 * w;
   T v[16];
@@ -217,10 +236,10 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
     nv = r[jc] - s;
     r[jc] = nv;
   }
-  if (64 * g + 64 == i0) {
+  if (prev) {
     if (p == 0) rb[cc] = nv;
     __syncthreads();
-    block64_apply(linv + (size_t)(i0 / 64 - 1) * 4096, rb, 1, xn, sM, part);
+    block64_apply(e, rb, 1, xn, sM, part);
     if (tid < 64) x[i0 - 64 + tid] = xn[tid];
   }
 }
