@@ -284,13 +284,18 @@ __global__ __launch_bounds__(256) void symv_lower_part_kernel(const ThetaDesc *_
   if (tid < 64) vc[tid] = c0 + tid < n ? v[c0 + tid] : 0.0;
   const double *Qc = t.Qp + (size_t)c0 * t.ldqp;
   double dot = 0.0;
+  // the next tile's 16 loads per thread are in flight while this tile is reduced
+  double buf[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) buf[q] = Qc[(size_t)(part + 4 * q) * t.ldqp + c0 + lo];
   for (int r0 = c0; r0 < np; r0 += 64) {
     __syncthreads();   // the previous tile and its row sums are consumed
-    double buf[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) buf[q] = Qc[(size_t)(part + 4 * q) * t.ldqp + r0 + lo];
 #pragma unroll
     for (int q = 0; q < 16; ++q) T[lo][part + 4 * q] = buf[q];
+    if (r0 + 64 < np) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) buf[q] = Qc[(size_t)(part + 4 * q) * t.ldqp + r0 + 64 + lo];
+    }
     if (tid < 64) vr[tid] = r0 + tid < n ? v[r0 + tid] : 0.0;
     __syncthreads();
     const bool diag = r0 == c0;
