@@ -88,36 +88,74 @@ __device__ __forceinline__ double *vsel(const ThetaDesc &t, int v) {
   return v == V_X ? t.x : v == V_R ? t.r : v == V_XN ? t.xn : v == V_Z ? t.z : t.u;
 }
 
-// y = M v (trans = 0) or y = M^T v (trans = 1) for a 64 x 64 block M stored
-// column-major at Mg (element (m, c) at Mg[c * 64 + m]); v and y live in LDS.
-// block64_load reads the block with one coalesced load per thread and element
-// (so that the caller can issue it ahead of other work), block64_apply stages
-// it through LDS and each wave sums a quarter of the columns.  All 256 threads
-// take part; block64_apply returns after a barrier.
+// y = M v or y = M^T v for a 64 x 64 block M stored column-major at Mg
+// (element (m, c) at Mg[c * 64 + m]).  block64_load reads the block into
+// registers, lane m of wave w holding row m of columns 16w .. 16w + 15 (each
+// load 64 contiguous elements of one column), so that the caller can issue it
+// ahead of other work; neither product stages the block in LDS, which keeps
+// the solve steps' LDS at a few KB.
 template <typename T>
 __device__ __forceinline__ void block64_load(const T *__restrict__ Mg, T (&e)[16]) {
   const auto *g = gptr(Mg);
+  const int m = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) e[q] = g[q * 256 + threadIdx.x];
+  for (int q = 0; q < 16; ++q) e[q] = g[(16 * w + q) * 64 + m];
 }
-// y = M v (trans 0) or M^T v (trans 1) for the 64 x 64 column-major block whose
-// elements block64_load read into e.
-template <typename T>
-__device__ __forceinline__ void block64_apply(const T (&e)[16], const double *v, int trans, double *y,
-                                              T (*sM)[65], double (*part)[64]) {
-  const int tid = threadIdx.x, m = tid & 63, w = tid >> 6;
+
+// Sums a[0..15] over the 64 lanes of a wave: lane l returns the total of
+// a[l >> 2].  A butterfly that halves the values it carries at each of the
+// first four exchanges (lane bits 5, 4, 3, 2 pick the half kept), then adds
+// across lane bits 1 and 0: 17 exchanges in place of 16 full reductions.
+// a is overwritten.
+template <int HALF>
+__device__ __forceinline__ void fold_half(double (&a)[16], int l) {
+  const bool up = (l & (4 * HALF)) != 0;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) sM[(q * 256 + tid) >> 6][tid & 63] = e[q];
-  __syncthreads();
+  for (int h = 0; h < HALF; ++h) {
+    const double keep = up ? a[h + HALF] : a[h], send = up ? a[h] : a[h + HALF];
+    a[h] = keep + __shfl_xor(send, 4 * HALF, 64);
+  }
+}
+__device__ __forceinline__ double wave_sum16(double (&a)[16]) {
+  const int l = threadIdx.x & 63;
+  fold_half<8>(a, l);
+  fold_half<4>(a, l);
+  fold_half<2>(a, l);
+  fold_half<1>(a, l);
+  double s = a[0];
+  s += __shfl_xor(s, 2, 64);
+  s += __shfl_xor(s, 1, 64);
+  return s;
+}
+
+// y = M v for the block whose elements block64_load read into e: each wave
+// sums its 16 columns, the four partial sums meet in `part` (4 x 64 doubles of
+// LDS).  v and y live in LDS.  All 256 threads take part; returns after a
+// barrier.
+template <typename T>
+__device__ __forceinline__ void block64_mv(const T (&e)[16], const double *v, double *y, double (*part)[64]) {
+  const int tid = threadIdx.x, m = tid & 63, w = tid >> 6;
   double s = 0.0;
 #pragma unroll
-  for (int cc = 0; cc < 16; ++cc) {
-    const int c = 16 * w + cc;
-    s += (double)(trans ? sM[m][c] : sM[c][m]) * v[c];
-  }
+  for (int q = 0; q < 16; ++q) s += (double)e[q] * v[16 * w + q];
   part[w][m] = s;
   __syncthreads();
   if (tid < 64) y[tid] = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+  __syncthreads();
+}
+
+// y = M^T v for the block in e: y[16w + q] = sum over the rows m (the lanes)
+// of M[m][16w + q] v[m], formed whole by wave w.  v and y live in LDS; returns
+// after a barrier.
+template <typename T>
+__device__ __forceinline__ void block64_mtv(const T (&e)[16], const double *v, double *y) {
+  const int m = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double vm = v[m];
+  double a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (double)e[q] * vm;
+  const double s = wave_sum16(a);
+  if ((m & 3) == 0) y[16 * w + (m >> 2)] = s;
   __syncthreads();
 }
 
@@ -138,8 +176,6 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__r
   const T *linv = (const T *)t.linv;
   auto *r = gptr(vsel(t, src));
   auto *z = gptr(vsel(t, dst));
-  __shared__ double smem[64 * 65];
-  T(*sM)[65] = reinterpret_cast<T(*)[65]>(smem);
   __shared__ double part[4][64];
   __shared__ double zb[64], rb[64], zn[64];
   const bool next = blockIdx.x == 0 && i0 + 64 < np;   // this workgroup forms z_{b+1}
@@ -148,7 +184,7 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__r
     block64_load(linv, e);
     if (tid < 64) rb[tid] = r[tid];
     __syncthreads();
-    block64_apply(e, rb, 0, zb, sM, part);
+    block64_mv(e, rb, zb, part);
     if (blockIdx.x == 0 && tid < 64) z[tid] = zb[tid];
   } else {
     if (tid < 64) zb[tid] = z[i0 + tid];
@@ -171,7 +207,7 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__r
   if (next) {
     if (tid < 64) rb[tid] = nv;
     __syncthreads();
-    block64_apply(e, rb, 0, zn, sM, part);
+    block64_mv(e, rb, zn, part);
     if (tid < 64) z[i0 + 64 + tid] = zn[tid];
   }
 }
@@ -180,9 +216,10 @@ __global__ __launch_bounds__(256) void trsv_fwd_step_kernel(const ThetaDesc *__r
 // On entry x_b = L_bb^{-T} r_b is already in x (the bottom block of a theta
 // forms it from the stored inverse).  The columns above are updated,
 // r_j -= sum_m L[i0 + m][j] x_b[m]: a workgroup takes 64 columns, a wave 16 of
-// them with its lanes on the 64 contiguous rows of each; the 16 x 64 products
-// are summed per column through LDS.  The workgroup holding the columns just
-// above the block finalises them and forms x_{b-1} for the next launch.
+// them with its lanes on the 64 contiguous rows of each, and the wave's 16 x 64
+// products are summed per column across its lanes (wave_sum16).  The workgroup
+// holding the columns just above the block finalises them and forms x_{b-1}
+// for the next launch.
 template <typename T>
 __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__restrict__ td, int i0, int src, int dst) {
   const ThetaDesc t = td[blockIdx.y];
@@ -193,18 +230,13 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
   const T *linv = (const T *)t.linv;
   auto *r = gptr(vsel(t, src));
   auto *x = gptr(vsel(t, dst));
-  // the staged diagonal block and the product tile are never live together
-  __shared__ double smem[64 * 65];
-  T(*sM)[65] = reinterpret_cast<T(*)[65]>(smem);
-  double(*prod)[65] = reinterpret_cast<double(*)[65]>(smem);
-  __shared__ double part[4][64];
   __shared__ double xb[64], rb[64], xn[64];
   T e[16];
   if (i0 + 64 == np) {
     block64_load(linv + (size_t)(i0 / 64) * 4096, e);
     if (tid < 64) rb[tid] = r[i0 + tid];
     __syncthreads();
-    block64_apply(e, rb, 1, xb, sM, part);
+    block64_mtv(e, rb, xb);
     if (blockIdx.x == 0 && tid < 64) x[i0 + tid] = xb[tid];
   } else {
     if (tid < 64) xb[tid] = x[i0 + tid];
@@ -221,25 +253,20 @@ __global__ __launch_bounds__(256) void trsv_bwd_step_kernel(const ThetaDesc *__r
   T v[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) v[q] = L[(size_t)(j0 + q) * t.ldw + i0 + lane];
+  double a[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) prod[16 * w + q][lane] = (double)v[q] * xm;
-  __syncthreads();
-  const int cc = tid >> 2, p = tid & 3;
-  double s = 0.0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) s += prod[cc][16 * p + i];
-  s += __shfl_xor(s, 1, 64);
-  s += __shfl_xor(s, 2, 64);
-  const int jc = 64 * g + cc;
+  for (int q = 0; q < 16; ++q) a[q] = (double)v[q] * xm;
+  const double s = wave_sum16(a);
+  const int jc = j0 + (lane >> 2);
   double nv = 0.0;
-  if (p == 0) {
+  if ((lane & 3) == 0) {
     nv = r[jc] - s;
     r[jc] = nv;
   }
   if (prev) {
-    if (p == 0) rb[cc] = nv;
+    if ((lane & 3) == 0) rb[16 * w + (lane >> 2)] = nv;
     __syncthreads();
-    block64_apply(e, rb, 1, xn, sM, part);
+    block64_mtv(e, rb, xn);
     if (tid < 64) x[i0 - 64 + tid] = xn[tid];
   }
 }
