@@ -412,8 +412,11 @@ __device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ 
   typedef __attribute__((address_space(1))) const T gcT;
   typedef __attribute__((address_space(1))) const vec_t gcvec;
   typedef typename std::conditional<F64, d4, f4>::type acc_t;
-  __shared__ __attribute__((aligned(16))) T As[2][KCH][TM + PAD];
-  __shared__ __attribute__((aligned(16))) T Bs[2][KCH][TN + PAD];
+  // FP64 64 x 64 tiles: one LDS buffer (17 KB), so that the workgroups of
+  // another stream still find LDS on a CU that holds four of them
+  constexpr int NBUF = (F64 && TM == 64) ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) T As[NBUF][KCH][TM + PAD];
+  __shared__ __attribute__((aligned(16))) T Bs[NBUF][KCH][TN + PAD];
 
   int bx, by;
   xcd_order(bx, by);
@@ -486,9 +489,17 @@ __device__ __forceinline__ void gemm_update_body(const FactorDesc *__restrict__ 
           else acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya[a], xb[b], acc[a][b], 0, 0, 0);
         }
     }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
+    if constexpr (NBUF == 2) {
+      if (more) lstore(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    } else {
+      __syncthreads();   // every wave is done reading the buffer
+      if (more) {
+        lstore(0);
+        __syncthreads();
+      }
+    }
   }
 
   // Epilogue: tile element (rl(a, v), cl(b, v)) for accumulator component v.
