@@ -41,11 +41,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}   # dense MFMA peaks
 TYPE_NAME = {"fp64": "double", "fp32": "float"}
 
 
-def trail_kernel_name(precision, tile):
-    """Symbol of the trailing-update kernel of a precision at the tuned tile."""
+def trail_kernel_name(precision, tile, aux=False):
+    """Symbol of the trailing-update kernel of a precision at the tuned tile
+    (`aux`: the kernel of a factorisation on the handle's aux stream, i.e. the
+    concurrent prior pass)."""
     if precision == "bf16":
         return "trail_bf16_kernel<128,128>"
-    return f"trail_update_kernel<{TYPE_NAME[precision]},{tile},{tile}>"
+    name = "trail_update_aux_kernel" if aux else "trail_update_kernel"
+    return f"{name}<{TYPE_NAME[precision]},{tile},{tile}>"
 MLP_TRAIN = {"n_train": 2048, "epochs": 6400, "batch": 256, "hidden": 256, "lr": 4e-3, "lr_final": 0.01, "seed": 91}
 
 
@@ -127,7 +130,10 @@ def run_variant(lib, binding, dms, thetas, xs, variant, steps, warmup, warm=None
     prec = variant.split("+")[0]
 
     def tname(p):   # the trailing kernel at the tile the handle uses for this batch
-        return trail_kernel_name(p, lib.tune_get(p, dms[0].n, len(dms))[1])
+        # (a mixed variant's FP64 updates are its prior pass, on the aux stream
+        # with overlap on; the fp64 variant's are mostly its Newton passes)
+        aux = p == "fp64" and prec != "fp64" and lib.overlap
+        return trail_kernel_name(p, lib.tune_get(p, dms[0].n, len(dms))[1], aux)
 
     def step():
         if warm is None:
@@ -777,6 +783,11 @@ def main():
             roof["traffic_basis"] = (f"HBM bytes per launch = this run's algorithmic bytes per launch x the ratio of "
                                      f"FETCH_SIZE + WRITE_SIZE (copy-calibrated) to algorithmic bytes in "
                                      f"profiles/{os.path.basename(summary)}")
+    if in_order is not None:
+        # the same kernel's rate in the in-order repeat of the headline (the
+        # figure above is measured beside the concurrent prior pass, with which
+        # it shares the MFMA units)
+        hv["roofline"]["frac_prior_pass_in_order"] = in_order["roofline"]["frac"]
     out = {
         "metric": METRIC,
         "value": hv["value"],

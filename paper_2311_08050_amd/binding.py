@@ -243,6 +243,7 @@ class Library:
         self.torch = torch
         self.lib = load_library(path)
         self.h = C.c_void_p()
+        self.overlap = False   # concurrent prior pass (set_overlap)
         rc = self.lib.inla_create(C.byref(self.h), C.c_void_p(torch.cuda.current_stream().cuda_stream))
         self._check(rc, "inla_create")
 
@@ -517,6 +518,7 @@ class Library:
         """Run each evaluation's FP64 prior pass beside its Newton iteration on a
         stream of the handle (default off; results identical either way)."""
         self._check(self.lib.inla_set_overlap(self.h, 1 if on else 0), "inla_set_overlap")
+        self.overlap = bool(on)
 
     def graph_stats(self):
         cap, rep = C.c_int64(), C.c_int64()
