@@ -128,3 +128,24 @@ def test_rocprof_window_reads_counter_values(tmp_path):
     out = bench.rocprof_window(str(csv), str(js))
     assert out["quantity"] == "FETCH_SIZE" and out["window"] == 2
     assert out["window_mean"] == pytest.approx(30.0)
+
+
+def test_prior_pass_kernel_is_named_and_windowed_apart(tmp_path):
+    """The concurrent prior pass's trailing update is a kernel of its own
+    (`trail_update_aux_kernel`): the bench names it for that pass, and a window
+    over one of the two symbols never counts the other's dispatches."""
+    aux = bench.trail_kernel_name("fp64", 64, aux=True)
+    assert aux == "trail_update_aux_kernel<double,64,64>"
+    assert bench.trail_kernel_name("fp64", 64) == KERNEL
+    assert bench.trail_kernel_name("fp32", 128, aux=True) == "trail_update_aux_kernel<float,128,128>"
+    csv = tmp_path / "trace.csv"
+    rows = ["Kernel_Name,Dispatch_Id,Start_Timestamp,End_Timestamp"]
+    for d in range(1, 9):
+        sym = aux if d % 2 else KERNEL
+        rows.append(f'"void inla::{sym}(inla::FactorDesc const*, int, int, int)",{d},0,{1_000_000 * d}')
+    csv.write_text("\n".join(rows) + "\n")
+    for sym, want in ((KERNEL, (6 + 8) / 2), (aux, (5 + 7) / 2)):
+        js = tmp_path / "bench.json"
+        _bench_json(js, sym, 2, 1.0)
+        out = bench.rocprof_window(str(csv), str(js))
+        assert out["dispatches_in_csv"] == 4 and out["window_mean"] == pytest.approx(want), (sym, out)
