@@ -13,11 +13,16 @@ what the tests compare against:
 Each file holds every scalar term of the Laplace objective (Eq. (41) with the
 constraint terms), the Newton iteration count, the mode and the kriging-
 corrected marginal variances at sampled indices (every STRIDE-th index plus the
-last one), and their maxima.  It calls only ``oracle/`` and the input generator
-``synth`` (which holds none of the method's arithmetic); nothing here reads the
-GPU library.
+last one), and their maxima.
 
-    python tests/golden/make_full_size.py [8192|16384 ...]
+With ``ns8192`` or ``ns16384``, it writes instead the same case's objective,
+mode and marginal variances by the constraint-surface route of
+``oracle/nullspace_route.py`` (``*_nullspace.json``), which pins the stored
+kriging-oracle values at full size.  It calls only ``oracle/`` and the input
+generator ``synth`` (which holds none of the method's arithmetic); nothing here
+reads the GPU library.
+
+    python tests/golden/make_full_size.py [8192|16384|ns8192|ns16384 ...]
 """
 from __future__ import annotations
 
@@ -33,6 +38,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 from oracle import inla_oracle as O  # noqa: E402
+from oracle import nullspace_route as NS  # noqa: E402
 from paper_2311_08050_amd import synth  # noqa: E402
 
 STRIDE = 8
@@ -86,6 +92,39 @@ def write(n):
           f"({t1 - t0:.0f} s + {t2 - t1:.0f} s)", flush=True)
 
 
+def write_nullspace(n):
+    fname, model, theta, what = case(n)
+    t0 = time.perf_counter()
+    Q = NS.kron_prior(model, theta)
+    y = np.asarray(model["y"], dtype=np.float64)
+    E = np.asarray(model["E"], dtype=np.float64)
+    x, obj, gmax, var = NS.nullspace_laplace(Q, None, y, E, float(theta[3]), model["C"], model["e"])
+    t1 = time.perf_counter()
+    idx = sample_index(model["n"])
+    out = {
+        "what": f"constraint-surface route (oracle/nullspace_route.py) on {what}",
+        "n": int(model["n"]), "k": int(model["C"].shape[0]),
+        "theta": [float(v) for v in theta],
+        "objective": float(obj),
+        "gradient_absmax": gmax,
+        "constraint_residual": float(np.max(np.abs(model["C"] @ x - model["e"]))),
+        "index": idx,
+        "x": [float(x[i]) for i in idx],
+        "x_absmax": float(np.max(np.abs(x))),
+        "var": [float(var[i]) for i in idx],
+        "var_max": float(np.max(var)),
+        "seconds": t1 - t0,
+    }
+    name = fname.replace(".json", "_nullspace.json")
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(f"{name}: objective={obj!r} ({t1 - t0:.0f} s)", flush=True)
+
+
 if __name__ == "__main__":
     for arg in sys.argv[1:] or ["8192", "16384"]:
-        write(int(arg))
+        if arg.startswith("ns"):
+            write_nullspace(int(arg[2:]))
+        else:
+            write(int(arg))

@@ -1,101 +1,21 @@
 """Pin of the oracle's Laplace objective for Poisson likelihoods at sizes the
-exact-rational twin cannot reach (n up to 240), through a route that shares
-none of the oracle's algorithm.
-
-The oracle conditions on C x = e by kriging (Eq. (41) with the constraint terms:
-log|Q_p|, log|C Q_p^{-1} C^T|, e^T (C Q_p^{-1} C^T)^{-1} e, log|Q*| and
-log|C Q*^{-1} C^T|).  Here the constrained field is instead written in
-coordinates of the constraint surface,
-
-    x = x_p + N z,   C x_p = e,   N an orthonormal basis of null(C),
-
-where the conditioned prior is an ordinary Gaussian in z with precision
-P = N^T Q_p N and centre z_c = -P^{-1} N^T Q_p x_p.  The textbook Laplace
-approximation of the marginal likelihood in z is
-
-    log p(y | z*) - 1/2 (z* - z_c)^T P (z* - z_c) + 1/2 log|P| - 1/2 log|P + N^T A^T W A N|,
-
-with z* the mode, found here by scipy's trust-region Newton optimiser.  By
-det(N^T Q N) = det(Q) det(C Q^{-1} C^T) / det(C C^T) and
-(x - mu_c)^T Q (x - mu_c) = x^T Q x - e^T (C Q^{-1} C^T)^{-1} e on {C x = e},
-this equals the kriging form term by term, so a dropped or mis-signed term of the
-oracle's objective (the e-term, either Schur log-determinant), a transposed
-design matrix or a wrong Poisson weight makes the two disagree.  The posterior
-covariance of the Gaussian approximation on the surface is N H^{-1} N^T (H the
-Hessian in z), which pins the oracle's kriging-corrected marginal variances.
-The prior precision, the likelihood and every determinant are written here from
-their definitions, not taken from the oracle.
-"""
-import math
+exact-rational twin cannot reach, through the constraint-surface route of
+``oracle/nullspace_route.py``, which shares none of the oracle's algorithm
+(the reasoning is in that module's docstring): n = 96 ... 240 here, the n = 3000
+configuration's shape as a slow test, and the stored n = 8192 values of the
+headline's theta 0 (``tests/golden/kron8192_theta0*.json``, written once by
+``tests/golden/make_full_size.py``)."""
+import json
+import os
 
 import numpy as np
 import pytest
-from scipy.linalg import null_space
-from scipy.optimize import minimize
 
 from oracle import inla_oracle as O
+from oracle.nullspace_route import kron_prior, nullspace_laplace
 from paper_2311_08050_amd import synth
 
-
-def kron_prior(model, theta):
-    """tau (R_t kron Sigma_s(rho)^{-1} + delta I): R_t the first-order random
-    walk structure, Sigma_s(rho)_ij = exp(-|p_i - p_j| / rho), index t n_s + s."""
-    n_s, n_t = model["n_s"], model["n_t"]
-    tau, rho, delta = math.exp(theta[0]), math.exp(theta[1]), math.exp(theta[2])
-    p = np.asarray(model["coords"], dtype=np.float64)
-    d = np.sqrt(((p[:, None, :] - p[None, :, :]) ** 2).sum(axis=2))
-    Sinv = np.linalg.inv(np.exp(-d / rho))
-    R = 2.0 * np.eye(n_t) - np.eye(n_t, k=1) - np.eye(n_t, k=-1)
-    R[0, 0] = R[-1, -1] = 1.0
-    return tau * (np.kron(R, Sinv) + delta * np.eye(n_s * n_t))
-
-
-def nullspace_laplace(Q, A, y, E, offset, C, e):
-    """Mode and Laplace objective in constraint-surface coordinates (Poisson)."""
-    n = Q.shape[0]
-    if C is None:
-        N, xp = np.eye(n), np.zeros(n)
-    else:
-        N = null_space(C)
-        xp = np.linalg.lstsq(C, e, rcond=None)[0]
-    P = N.T @ Q @ N
-    zc = -np.linalg.solve(P, N.T @ (Q @ xp))
-    AN = N if A is None else A @ N
-    eta0 = offset + (xp if A is None else A @ xp)
-    lgy = sum(math.lgamma(v + 1.0) for v in y)
-
-    def parts(z):
-        eta = eta0 + AN @ z
-        mu = E * np.exp(eta)
-        dz = z - zc
-        return float(np.sum(y * (np.log(E) + eta) - mu) - lgy), mu, dz
-
-    def f(z):
-        ll, _, dz = parts(z)
-        return -(ll - 0.5 * dz @ P @ dz)
-
-    def grad(z):
-        _, mu, dz = parts(z)
-        return -(AN.T @ (y - mu) - P @ dz)
-
-    def hess(z):
-        _, mu, _ = parts(z)
-        return P + AN.T @ (mu[:, None] * AN)
-
-    res = minimize(f, zc, jac=grad, hess=hess, method="trust-exact", options={"gtol": 1e-10, "maxiter": 200})
-    z = res.x
-    # one more Newton step from the optimiser's answer (quadratic convergence
-    # puts the iterate at the rounding level of the gradient)
-    z = z - np.linalg.solve(hess(z), grad(z))
-    ll, mu, dz = parts(z)
-    sp, ldP = np.linalg.slogdet(P)
-    sh, ldH = np.linalg.slogdet(hess(z))
-    assert sp > 0 and sh > 0
-    gmax = float(np.max(np.abs(grad(z))))
-    obj = ll - 0.5 * dz @ P @ dz + 0.5 * ldP - 0.5 * ldH
-    # posterior covariance of the Gaussian approximation on the surface: N H^{-1} N^T
-    var = np.einsum("ij,ji->i", N, np.linalg.solve(hess(z), N.T))
-    return xp + N @ z, obj, gmax, var
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _kron_case(n_s, n_t, seed, e_scale, constrained=True):
@@ -158,3 +78,24 @@ def test_laplace_objective_equals_nullspace_route_at_n3000():
     assert np.max(np.abs(m["C"] @ x_ns - m["e"])) <= 1e-10 * max(1.0, float(np.max(np.abs(x_ns))))
     v = O.marginal_var(m, th, r["x"])
     assert np.max(np.abs(v - var_ns)) <= 1e-9 * float(np.max(var_ns))
+
+
+def test_stored_oracle_values_equal_nullspace_route_at_n8192():
+    """The stored oracle values of the headline's theta 0 (n = 8192, k = 191:
+    objective, mode and marginal variances at every 8th index) against the same
+    case by the constraint-surface route (z of dimension 8001), both written by
+    ``tests/golden/make_full_size.py`` from ``oracle/`` only.  This pins the
+    full-size parity tests' expected values by a route that shares none of the
+    oracle's algorithm."""
+    with open(os.path.join(GOLDEN, "kron8192_theta0.json")) as f:
+        ref = json.load(f)
+    with open(os.path.join(GOLDEN, "kron8192_theta0_nullspace.json")) as f:
+        ns = json.load(f)
+    assert ref["n"] == ns["n"] == 8192 and ref["k"] == ns["k"] and ref["theta"] == ns["theta"]
+    assert ref["index"] == ns["index"]
+    assert ns["gradient_absmax"] <= 1e-8 and ns["constraint_residual"] <= 1e-10 * max(1.0, ns["x_absmax"])
+    assert abs(ref["objective"] - ns["objective"]) <= 1e-9 * abs(ns["objective"])
+    x_ref, x_ns = np.array(ref["x"]), np.array(ns["x"])
+    assert np.max(np.abs(x_ref - x_ns)) <= 1e-8 * max(1.0, ns["x_absmax"])
+    v_ref, v_ns = np.array(ref["var"]), np.array(ns["var"])
+    assert np.max(np.abs(v_ref - v_ns)) <= 1e-9 * ns["var_max"]
