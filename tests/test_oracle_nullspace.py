@@ -2,8 +2,8 @@
 exact-rational twin cannot reach, through the constraint-surface route of
 ``oracle/nullspace_route.py``, which shares none of the oracle's algorithm
 (the reasoning is in that module's docstring): n = 96 ... 240 here, the n = 3000
-configuration's shape as a slow test, and the stored n = 8192 values of the
-headline's theta 0 (``tests/golden/kron8192_theta0*.json``, written once by
+configuration's shape as a slow test, and the stored full-size values (n = 8192
+and 16384, ``tests/golden/kron*_theta0*.json``, written once by
 ``tests/golden/make_full_size.py``)."""
 import json
 import os
@@ -80,18 +80,20 @@ def test_laplace_objective_equals_nullspace_route_at_n3000():
     assert np.max(np.abs(v - var_ns)) <= 1e-9 * float(np.max(var_ns))
 
 
-def test_stored_oracle_values_equal_nullspace_route_at_n8192():
-    """The stored oracle values of the headline's theta 0 (n = 8192, k = 191:
-    objective, mode and marginal variances at every 8th index) against the same
-    case by the constraint-surface route (z of dimension 8001), both written by
-    ``tests/golden/make_full_size.py`` from ``oracle/`` only.  This pins the
-    full-size parity tests' expected values by a route that shares none of the
-    oracle's algorithm."""
-    with open(os.path.join(GOLDEN, "kron8192_theta0.json")) as f:
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_stored_oracle_values_equal_nullspace_route_at_full_size(n):
+    """The stored oracle values of the full-size cases (the headline's theta 0,
+    n = 8192, k = 191; the precision configuration at theta0, n = 16384,
+    k = 255: objective, mode and marginal variances at every 8th index) against
+    the same cases by the constraint-surface route (z of dimension 8001 and
+    16129), both written by ``tests/golden/make_full_size.py`` from ``oracle/``
+    only.  This pins the full-size parity tests' expected values by a route that
+    shares none of the oracle's algorithm."""
+    with open(os.path.join(GOLDEN, f"kron{n}_theta0.json")) as f:
         ref = json.load(f)
-    with open(os.path.join(GOLDEN, "kron8192_theta0_nullspace.json")) as f:
+    with open(os.path.join(GOLDEN, f"kron{n}_theta0_nullspace.json")) as f:
         ns = json.load(f)
-    assert ref["n"] == ns["n"] == 8192 and ref["k"] == ns["k"] and ref["theta"] == ns["theta"]
+    assert ref["n"] == ns["n"] == n and ref["k"] == ns["k"] and ref["theta"] == ns["theta"]
     assert ref["index"] == ns["index"]
     assert ns["gradient_absmax"] <= 1e-8 and ns["constraint_residual"] <= 1e-10 * max(1.0, ns["x_absmax"])
     assert abs(ref["objective"] - ns["objective"]) <= 1e-9 * abs(ns["objective"])
