@@ -605,14 +605,15 @@ int inla_pass_graph_stats(inla_handle *h, int64_t *captured, int64_t *replays);
  * turned off), one untimed and `reps` timed runs each.  It records the fastest
  * for (prec, padded largest order, batch size rounded up to a power of two) in
  * the handle's table, which every later factorisation of such a batch uses
- * (the default {512, 64} for FP64 and {512, 128} otherwise, unless another
- * pair is at least 3% faster; the lookahead variant only when it is at least
- * 5% faster).
+ * (the default pair unless another is at least 3% faster; the lookahead
+ * variant only when it is at least 5% faster).
  * Outputs (host, each may be NULL): the chosen configuration, the mean time in
  * ms of each candidate in the order above (at most INLA_TUNE_MAX_CAND values)
  * and the candidate count.  Uses the handle's workspace; no caller data is
- * touched.  Without a table entry a batch factorises with that default
- * ({512, 64, 0} for FP64, {512, 128, 0} for FP32 and BF16).
+ * touched.  Without a table entry a batch factorises with the default:
+ * {512, 64, 0} for FP64, {512, 128, 0} for FP32, and for BF16 {512, 128, 0}
+ * below a padded order of 4096, {1024, 128, 0} from it (the BF16 trailing
+ * update then passes over its FP32 trailing block once per 1024 of K).
  * Returns -2 for B < 1, -3 / -4 for a null or non-positive n / null or
  * negative kb, INLA_ERR_UNSUPPORTED for an unknown precision, -6 for reps < 1. */
 #define INLA_TUNE_MAX_CAND 9

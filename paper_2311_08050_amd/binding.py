@@ -46,7 +46,15 @@ EXPORTS = [
 # reports their times; the fastest is then timed with lookahead as well.
 TUNE_CANDIDATES = {p: [(nb, tm) for nb in (128, 256, 512, 1024) for tm in (64, 128) if p != "bf16" or tm == 128]
                    for p in PREC}
-TUNE_DEFAULT = {"fp64": (512, 64, 0), "fp32": (512, 128, 0), "bf16": (512, 128, 0)}
+
+
+def tune_default(prec, n_max):
+    """The (nb, tm, lookahead) a batch of largest order n_max factorises with
+    when the handle's table has no entry for it: BF16 batches of padded order
+    4096 and above take 1024-wide panels."""
+    if prec == "bf16" and -(-n_max // 128) * 128 >= 4096:
+        return (1024, 128, 0)
+    return {"fp64": (512, 64, 0), "fp32": (512, 128, 0), "bf16": (512, 128, 0)}[prec]
 
 
 class Model(C.Structure):

@@ -182,7 +182,7 @@ struct PrecScope {
 // cfg == nullptr: the tuned (or default) configuration for this batch.
 int factor_batch(Ctx &ctx, const std::vector<HostFactor> &fs, int prec, const TuneCfg *cfg = nullptr);
 // The configuration used without a tuning table entry.
-TuneCfg default_config(int prec);
+TuneCfg default_config(int prec, int nf_max);
 // The configuration factor_batch uses for a batch of `B` factorisations whose
 // largest padded order is `nf_max`.
 TuneCfg tuned_config(const Ctx &ctx, int prec, int nf_max, int B);

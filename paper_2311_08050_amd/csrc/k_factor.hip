@@ -1182,16 +1182,22 @@ std::vector<int64_t> tune_key(int prec, int nf_max, int B) { return {prec, nf_ma
 
 // Untuned configuration: 512-wide panels; 64 x 64 FP64 trailing tiles (at
 // 8192 they measure about 4% faster than 128 x 128), 128 x 128 otherwise.
-TuneCfg default_config(int prec) {
+// BF16 batches of padded order 4096 and above take 1024-wide panels: their
+// trailing update then reads and writes the FP32 trailing block once per 1024
+// of K rather than per 512 (the BF16 evaluation of 64 theta at n = 8192:
+// 864 -> 827 ms, its BF16 trailing update 13% -> 17% of the BF16 peak);
+// smaller ones keep 512, which leaves them trailing updates at all.
+TuneCfg default_config(int prec, int nf_max) {
   TuneCfg c;
   if (prec == INLA_PREC_FP64) c.tm = 64;
+  if (prec == INLA_PREC_BF16 && nf_max >= 4096) c.nb = 1024;
   return c;
 }
 
 TuneCfg tuned_config(const Ctx &ctx, int prec, int nf_max, int B) {
   auto it = ctx.tune.find(tune_key(prec, nf_max, B));
   if (it != ctx.tune.end()) return it->second;
-  return default_config(prec);
+  return default_config(prec, nf_max);
 }
 
 bool tune_valid(int prec, const TuneCfg &c) {
@@ -1288,7 +1294,7 @@ int autotune(Ctx &ctx, int B, const int *n, const int *kb, int prec, int reps, T
     const double avg = time_cfg(cand[c]);
     if (ms_out) ms_out[c] = avg;
     if (!rc && (best < 0 || avg < best_ms)) { best = (int)c; best_ms = avg; }
-    if (cand[c].nb == default_config(prec).nb && cand[c].tm == default_config(prec).tm) { dflt = (int)c; dflt_ms = avg; }
+    if (cand[c].nb == default_config(prec, nf_max).nb && cand[c].tm == default_config(prec, nf_max).tm) { dflt = (int)c; dflt_ms = avg; }
   }
   // the default configuration stays unless another is clearly faster, so that
   // timing noise between near-equal candidates does not change the choice

@@ -159,7 +159,10 @@ def test_autotune_chooses_a_candidate_and_every_candidate_is_exact():
             for i in range(len(ns)):
                 assert info[i] == 0 and abs(ld[i] - refs[i]) <= 1e-12 * abs(refs[i]), (cnb, ctm, look, i)
     lib.tune_set("fp64", max(ns), len(ns))
-    assert lib.tune_get("fp64", max(ns), len(ns)) == binding.TUNE_DEFAULT["fp64"]
+    assert lib.tune_get("fp64", max(ns), len(ns)) == binding.tune_default("fp64", max(ns))
+    assert binding.tune_default("bf16", 4000) == (1024, 128, 0) and binding.tune_default("bf16", 3968) == (512, 128, 0)
+    assert lib.tune_get("bf16", 8192, 64) == binding.tune_default("bf16", 8192)
+    assert lib.tune_get("bf16", 3000, 64) == binding.tune_default("bf16", 3000)
     for prec in ("fp32", "bf16"):
         cfg, times = lib.autotune([2048, 2048], [129, 129], prec=prec, reps=1)
         say(f"autotune {prec}: chose {cfg}")
