@@ -169,6 +169,35 @@ def test_autotune_chooses_a_candidate_and_every_candidate_is_exact():
         assert cfg in times and (cfg[0], cfg[1]) in binding.TUNE_CANDIDATES[prec]
 
 
+def test_bf16_default_panel_width_from_order_4096():
+    """BF16 batches of padded order 4096 and above factor with 1024-wide panels
+    by default (two 512-deep halves of K per pass of the BF16 trailing update
+    over its FP32 block); the log-determinants of a batch of order 4224 with
+    the default and with 512-wide panels both meet the BF16 bound against the
+    FP64 factorisation, and differ from each other (the default really changed
+    the panel width)."""
+    import torch
+
+    from paper_2311_08050_amd import binding
+    lib = binding.Library()
+    ns = [4224, 4100]
+    mats = [torch.tensor(synth.random_spd(n, seed=700 + n)).cuda() for n in ns]
+    assert lib.tune_get("bf16", max(ns), len(ns)) == (1024, 128, 0)
+    ld64, inf = lib.logdet([m.clone() for m in mats], prec="fp64")
+    assert list(inf) == [0, 0]
+    say("bf16 logdet, default panels")
+    ld_d, inf = lib.logdet([m.clone() for m in mats], prec="bf16")
+    assert list(inf) == [0, 0]
+    lib.tune_set("bf16", max(ns), len(ns), 512, 128, 0)
+    say("bf16 logdet, 512-wide panels")
+    ld_5, inf = lib.logdet([m.clone() for m in mats], prec="bf16")
+    assert list(inf) == [0, 0]
+    for i in range(len(ns)):
+        say(f"n={ns[i]}: FP64 {ld64[i]:.10f}, BF16 nb=1024 {ld_d[i]:.10f}, nb=512 {ld_5[i]:.10f}")
+        assert rel(ld_d[i], ld64[i]) <= 1e-4 and rel(ld_5[i], ld64[i]) <= 1e-4, i
+    assert any(a != b for a, b in zip(ld_d, ld_5))
+
+
 @pytest.mark.parametrize("nb,tm", [(128, 64), (256, 128), (1024, 64)])
 def test_laplace_under_other_configurations(nb, tm):
     from paper_2311_08050_amd import binding
@@ -249,7 +278,7 @@ def test_set_stream_rebinds_the_handle():
         assert sign > 0 and abs(v - want) <= 1e-12 * abs(want)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_concurrent_prior_pass_matches_in_order(prec):
     """The prior pass on the handle's aux stream, beside the Newton iteration,
     runs the same kernels on the same data as the pass in order: identical bits
