@@ -18,11 +18,14 @@ last one), and their maxima.
 With ``ns8192`` or ``ns16384``, it writes instead the same case's objective,
 mode and marginal variances by the constraint-surface route of
 ``oracle/nullspace_route.py`` (``*_nullspace.json``), which pins the stored
-kriging-oracle values at full size.  It calls only ``oracle/`` and the input
+kriging-oracle values at full size.  With ``vb8192`` it writes the
+variational-Bayes corrected mean of the headline case (``oracle/vb_oracle.py``
+from the oracle's mode and marginal variances) at the same sampled indices
+(``kron8192_theta0_vb.json``).  It calls only ``oracle/`` and the input
 generator ``synth`` (which holds none of the method's arithmetic); nothing here
 reads the GPU library.
 
-    python tests/golden/make_full_size.py [8192|16384|ns8192|ns16384 ...]
+    python tests/golden/make_full_size.py [8192|16384|ns8192|ns16384|vb8192 ...]
 """
 from __future__ import annotations
 
@@ -39,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 from oracle import inla_oracle as O  # noqa: E402
 from oracle import nullspace_route as NS  # noqa: E402
+from oracle import vb_oracle as V  # noqa: E402
 from paper_2311_08050_amd import synth  # noqa: E402
 
 STRIDE = 8
@@ -122,9 +126,42 @@ def write_nullspace(n):
     print(f"{name}: objective={obj!r} ({t1 - t0:.0f} s)", flush=True)
 
 
+def write_vb(n):
+    fname, model, theta, what = case(n)
+    t0 = time.perf_counter()
+    ref = O.laplace_eval(model, theta)
+    assert ref["info"] == O.INFO_OK, ref["info"]
+    var = O.marginal_var(model, theta, ref["x"])
+    t1 = time.perf_counter()
+    mu, iters, info = V.vb_mean(model, theta, ref["x"], var)
+    t2 = time.perf_counter()
+    assert info == O.INFO_OK, info
+    idx = sample_index(model["n"])
+    out = {
+        "what": f"variational-Bayes corrected mean (oracle/vb_oracle.py vb_mean from the oracle's mode and marginal "
+                f"variances) on {what}",
+        "n": int(model["n"]), "k": int(model["C"].shape[0]),
+        "theta": [float(v) for v in theta],
+        "iters": int(iters),
+        "index": idx,
+        "mu": [float(mu[i]) for i in idx],
+        "mu_absmax": float(np.max(np.abs(mu))),
+        "shift_from_mode_absmax": float(np.max(np.abs(mu - ref["x"]))),
+        "oracle_seconds": {"mode_and_variances": t1 - t0, "vb_mean": t2 - t1},
+    }
+    name = fname.replace(".json", "_vb.json")
+    with open(os.path.join(HERE, name), "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(f"{name}: {iters} iterations, shift from the mode {out['shift_from_mode_absmax']:.3e} "
+          f"({t2 - t0:.0f} s)", flush=True)
+
+
 if __name__ == "__main__":
     for arg in sys.argv[1:] or ["8192", "16384"]:
         if arg.startswith("ns"):
             write_nullspace(int(arg[2:]))
+        elif arg.startswith("vb"):
+            write_vb(int(arg[2:]))
         else:
             write(int(arg))

@@ -79,3 +79,32 @@ def test_vb_at_n3000_is_stationary(lib):
             f"{np.max(np.abs(r - C.T @ lam)) / np.max(np.abs(r)):.2e}")
         assert np.max(np.abs(r - C.T @ lam)) <= 1e-8 * np.max(np.abs(r))
         assert np.max(np.abs(C @ mu - e)) <= 1e-10
+
+
+@pytest.mark.timeout(600)
+def test_vb_at_n8192_against_stored_oracle_values(lib):
+    """The headline model at theta 0 of its batch (n = 8192, k = 191): the
+    corrected mean from the library's FP64 mode and marginal variances against
+    the oracle's, from the oracle's mode and variances (stored by
+    tests/golden/make_full_size.py), at every 8th index, to 1e-9 relative."""
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "kron8192_theta0_vb.json")) as f:
+        g = json.load(f)
+    model, thetas = synth.headline(B=64)
+    th = thetas[:1]
+    assert np.array_equal(th[0], np.array(g["theta"]))
+    dms = dev_models([model])
+    say("n=8192: mode, marginal variances, correction")
+    _, xs = lib.constrained_mode(dms, th)
+    var, vinfo = lib.marginal_var(dms, th, xs)
+    assert vinfo[0] == 0
+    mus, its, info = lib.vb_mean(dms, th, var, xs)
+    assert info[0] == 0, info
+    idx = np.array(g["index"])
+    mu = mus[0].cpu().numpy()
+    err = np.max(np.abs(mu[idx] - np.array(g["mu"]))) / max(1.0, g["mu_absmax"])
+    say(f"n=8192: {its[0]} iterations (oracle {g['iters']}), error {err:.2e}, "
+        f"shift from the mode {g['shift_from_mode_absmax']:.3e}")
+    assert err <= 1e-9 and abs(int(its[0]) - g["iters"]) <= 1
